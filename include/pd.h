@@ -1,0 +1,224 @@
+/*
+ * pd.h -- C ABI of libpd, an MI355X (gfx950) solver for the wavelet-l1
+ * deblurring energy of Escande & Weiss, "Fast Wavelet Decomposition of Linear
+ * Operators through Product-Convolution Expansions" (arXiv:2005.09870):
+ *
+ *     argmin_f  E(f) = 1/2 ||H f - f0||_2^2 + ||Psi^* f||_{1,w}          (eq. 4.1)
+ *
+ * solved in coefficient form (Appendix A.1, eq. A.1) by FISTA with the exact
+ * spatial operator ("FISTA-Spa", Table 1):
+ *
+ *     z(0) = y(1) = init
+ *     z(i)   = Prox_{tau ||.||_{1,w}}( y(i) - tau Psi^* H^T (H Psi y(i) - f0) )
+ *     y(i+1) = z(i) + (i-1)/(i+2) (z(i) - z(i-1))
+ *
+ * Psi is a periodic orthogonal separable 2-D wavelet transform (Sections 2.1,
+ * 2.2); H is a row-separable spatially varying blur whose impulse response
+ * depends on the source row only (Operator 1 of Section 4.1 is one).
+ *
+ * Conventions for every entry point
+ *  - Images and coefficient planes are row-major, x1 (index i1) fastest:
+ *    element (c, i2, i1) of a C x n2 x n1 planar array is at c*n1*n2 + i2*n1 + i1.
+ *  - Wavelet coefficients use the Mallat layout in an n2 x n1 plane: after one
+ *    level the band low-pass in both axes is at [0,n2/2) x [0,n1/2), the band
+ *    high-pass along x1 at [0,n2/2) x [n1/2,n1), high-pass along x2 at
+ *    [n2/2,n2) x [0,n1/2), high-pass in both at [n2/2,n2) x [n1/2,n1); the next
+ *    level recurses on the first band.
+ *  - Band index k (weights): k = 0 is the coarsest approximation band, k = 1..L
+ *    the detail bands from the coarsest (decomposition level L) to the finest
+ *    (level 1).  For a full-depth transform k - 1 is the paper's scale |lambda|.
+ *  - "device" pointers are HIP device memory owned by the caller; libpd never
+ *    allocates or frees device memory: scratch space comes from a caller
+ *    workspace of the size the matching *_workspace_size call reports.
+ *    "host" pointers are read during the call only.
+ *  - Every GPU entry point enqueues its work on `stream` (a hipStream_t; NULL
+ *    is the default stream) and returns without synchronising unless stated.
+ *  - Every entry point returns PD_OK (0) or a negative pd_status; nothing is
+ *    thrown across the ABI.  On an argument error nothing is enqueued.
+ *  - Element type of every device array is the call's dtype (float or double).
+ *  - Concurrent calls that share a workspace race; distinct workspaces are
+ *    independent.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PD_OK = 0,
+    PD_ERR_ARG = -1,         /* null pointer, bad enum, negative count          */
+    PD_ERR_SHAPE = -2,       /* n1 or n2 not divisible by 2^levels, bad sizes   */
+    PD_ERR_WORKSPACE = -3,   /* workspace smaller than required                 */
+    PD_ERR_TAU = -4,         /* step size <= 0 or not finite                    */
+    PD_ERR_NONFINITE = -5,   /* a prox argument was NaN/Inf (check_finite only) */
+    PD_ERR_HIP = -6,         /* a HIP runtime call failed                       */
+    PD_ERR_UNSUPPORTED = -7  /* valid request outside what this build supports  */
+} pd_status;
+
+typedef enum { PD_F32 = 0, PD_F64 = 1 } pd_dtype;
+
+typedef enum {
+    PD_OP_IDENTITY = 0, /* H = Id: wavelet denoising, the closed-form special case      */
+    PD_OP_ROWBLUR = 1   /* H f(x) = sum_y k_{y2}(x1-y1) k_{y2}(x2-y2) f(y), periodic:     */
+                        /* the response of source row y2 is the outer product of one    */
+                        /* 1-D profile k_{y2}[-R..R] with itself (Section 1, eq. 1.1;   */
+                        /* Operator 1 of Section 4.1 when built by pd_op1_taps)         */
+} pd_op_kind;
+
+/* Problem size: n1 x n2 pixels (n1 fastest), `channels` planar channels,
+ * `levels` >= 1 decomposition levels; n1 and n2 must be divisible by
+ * 2^levels, levels <= 16, channels in [1, 4]. */
+typedef struct {
+    int32_t n1, n2, channels, levels;
+} pd_shape;
+
+/* Blur operator.  taps: device array [n2][2*radius+1] of the call's dtype,
+ * row i2 holding the profile k_{i2}[d], d = -radius..radius, of SOURCE row
+ * i2 (ignored for PD_OP_IDENTITY).  radius in [0, 9]. */
+typedef struct {
+    int32_t kind;
+    int32_t radius;
+    const void *taps;
+} pd_operator;
+
+/* Low-pass filter h[0..len-1] of the orthogonal wavelet (Section 2.1; the
+ * high-pass filter is derived as g[k] = (-1)^(1-k) h[1-k]).  host doubles;
+ * len even, 2 <= len <= 12 (12 = Symmlet of order 6, Section 4.2). */
+typedef struct {
+    int32_t len;
+    const double *h;
+} pd_wavelet;
+
+/* Weights w of the weighted l1 norm (eq. 4.1).  Exactly one of
+ *   level_w : host doubles [levels+1], one weight per band index k, or
+ *   coeff_w : device array [channels][n2][n1] (Mallat layout), one weight per
+ *             coefficient,
+ * is non-NULL.  joint != 0 selects group soft-thresholding of the channel
+ * vector of each coefficient (an extension for colour images, not in the
+ * paper; level_w only). */
+typedef struct {
+    const double *level_w;
+    const void *coeff_w;
+    int32_t joint;
+} pd_weights;
+
+/* Iteration parameters.  tau > 0 is the step (the paper asks tau <=
+ * ||H||^-2).  iters >= 0 iterations are run, numbered iter_offset+1 ..
+ * iter_offset+iters (the momentum uses the global number).  check_finite != 0
+ * makes the call synchronise the stream at the end and return
+ * PD_ERR_NONFINITE if any prox argument was not finite. */
+typedef struct {
+    double tau;
+    int32_t iters;
+    int32_t iter_offset;
+    int32_t check_finite;
+} pd_params;
+
+/* Bytes of device workspace pd_solve needs for this size and dtype. */
+size_t pd_workspace_size(const pd_shape *shape, int32_t dtype);
+
+/* Run FISTA on eq. 4.1 (Appendix A.1).
+ *   f0      device [C][n2][n1] observation.
+ *   z_cur, z_prev  device [C][n2][n1] Mallat coefficient state, in/out.  On
+ *           entry they hold z(k) and z(k-1) for k = iter_offset (for k = 0 both
+ *           hold z(0)); on exit z(k+iters) and z(k+iters-1).  If init_from_f0
+ *           != 0 both are first set to Psi^* f0 (the default initial guess).
+ *   f_out   device [C][n2][n1] or NULL: receives Psi z(k+iters).
+ *   stats   device double [iters][3] or NULL: for each iteration i, the two
+ *           terms of eq. 4.1 at y(i), 1/2||H Psi y(i) - f0||^2 and
+ *           ||y(i)||_{1,w}, and ||z(i) - y(i)||^2 (the squared gradient-mapping
+ *           norm times tau^2).  Accumulated in FP64; the caller zeroes it.
+ * Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_TAU, PD_ERR_WORKSPACE,
+ * PD_ERR_UNSUPPORTED, PD_ERR_HIP, PD_ERR_NONFINITE (check_finite only). */
+int pd_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+             const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+             const void *f0, void *z_cur, void *z_prev, int32_t init_from_f0,
+             void *f_out, double *stats, void *workspace, size_t ws_bytes,
+             void *stream);
+
+/* One image of a batch for pd_solve_batched.  Arrays of image b start at
+ * element `offset` of the packed buffers (each image planar C x n2 x n1).
+ * op.taps is the image's own device tap table; level_w its host band weights. */
+typedef struct {
+    pd_shape shape;
+    int64_t offset;
+    double tau;
+    pd_operator op;
+    const double *level_w;
+} pd_image_desc;
+
+/* Bytes of device workspace pd_solve_batched needs for these images. */
+size_t pd_batched_workspace_size(int32_t batch, const pd_image_desc *descs, int32_t dtype);
+
+/* Solve `batch` independent instances of eq. 4.1 of uneven sizes from the
+ * default initial guess, `iters` iterations each, in lock-step launches that
+ * cover every image (the same per-image arithmetic as pd_solve, so results
+ * match pd_solve bit for bit).  f0_packed / f_out_packed: device, packed as
+ * described by descs[b].offset.  stats: device double [batch][iters][3] or
+ * NULL.  descs is a host array. */
+int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32_t dtype,
+                     const pd_wavelet *wav, int32_t iters, const void *f0_packed,
+                     void *f_out_packed, double *stats, void *workspace,
+                     size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace pd_backward needs. */
+size_t pd_backward_workspace_size(const pd_shape *shape, int32_t dtype, int32_t iters,
+                                  int32_t checkpoint_every);
+
+/* Reverse mode of pd_solve from the default initial guess (init = Psi^* f0,
+ * iter_offset = 0, scalar prox), for f = Psi z(iters):
+ *   grad_f   device [C][n2][n1]: dLoss/df.
+ *   grad_f0  device [C][n2][n1] or NULL: receives dLoss/df0.
+ *   grad_w   device [C][n2][n1] or NULL: receives dLoss/dw (needs coeff_w).
+ * The forward recursion is recomputed internally in segments of
+ * `checkpoint_every` iterations from stored (z(i), z(i-1)) pairs, so memory
+ * is O(iters/checkpoint_every + checkpoint_every) planes.  The derivative of
+ * the soft threshold at the kink |v| = tau w is taken as 0.
+ * Errors as pd_solve. */
+int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                const void *f0, const void *grad_f, void *grad_f0, void *grad_w,
+                int32_t checkpoint_every, void *workspace, size_t ws_bytes,
+                void *stream);
+
+/* Building blocks, exposed for tests and for setting up a solve.            */
+
+/* Forward (inverse == 0: out = Psi^* in) or inverse (out = Psi in) periodic
+ * 2-D wavelet transform of C channels (Sections 2.1-2.2).  in and out are
+ * device [C][n2][n1] and must not overlap.  workspace: pd_workspace_size bytes. */
+int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wav,
+           int32_t inverse, const void *in, void *out, void *workspace,
+           size_t ws_bytes, void *stream);
+
+/* out = H in (transpose == 0) or H^T in (transpose != 0) for C channels;
+ * device [C][n2][n1], non-overlapping. */
+int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                int32_t transpose, const void *in, void *out, void *stream);
+
+/* Host: low-pass filter of the orthogonal wavelet with `moments` vanishing
+ * moments and minimal support 2*moments whose phase is closest to linear
+ * (the Symmlet family; Section 2.1 filter bank, Section 4.2 "Symmlet of order
+ * 6"), normalised to sum sqrt(2).  h_out: host double [2*moments].
+ * moments in [1, 10]. */
+int pd_symmlet(int32_t moments, double *h_out);
+
+/* Host: Operator 1 of Section 4.1.  Source row i2 emits an isotropic Gaussian
+ * of standard deviation sigma_max * i2/(n2-1) pixels, truncated to the square
+ * window that keeps the fraction `mass` of the Gaussian and renormalised to
+ * unit sum.  Writes the common half-width to *radius and, if taps_out is not
+ * NULL, the profiles as host doubles [n2][2*radius+1]. */
+int pd_op1_taps(int32_t n2, double sigma_max, double mass, int32_t *radius,
+                double *taps_out);
+
+/* Short description of a pd_status code. */
+const char *pd_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PD_H */

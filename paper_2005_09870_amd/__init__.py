@@ -1,0 +1,19 @@
+"""MI355X-native FISTA solver for the wavelet-l1 deblurring energy of
+Escande & Weiss (arXiv:2005.09870, eq. 4.1, Appendix A.1).
+
+The compute path is libpd.so (hand-written HIP for gfx950 behind the C ABI in
+include/pd.h); this package only marshals torch device tensors into it.
+"""
+from ._lib import PDError, load  # noqa: F401
+from .solver import (  # noqa: F401
+    Operator,
+    lipschitz,
+    pd_apply_op,
+    pd_fwt,
+    pd_op1_taps,
+    pd_solve,
+    pd_solve_batched,
+    pd_symmlet,
+    pd_workspace_size,
+    step_size,
+)

@@ -1,0 +1,118 @@
+"""ctypes declarations of libpd's C ABI (include/pd.h).  Loading fails loudly
+when the library has not been built: there is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpd.so")
+
+PD_OK = 0
+PD_ERR_ARG = -1
+PD_ERR_SHAPE = -2
+PD_ERR_WORKSPACE = -3
+PD_ERR_TAU = -4
+PD_ERR_NONFINITE = -5
+PD_ERR_HIP = -6
+PD_ERR_UNSUPPORTED = -7
+
+PD_F32 = 0
+PD_F64 = 1
+PD_OP_IDENTITY = 0
+PD_OP_ROWBLUR = 1
+
+
+class pd_shape(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("levels", ctypes.c_int32)]
+
+
+class pd_operator(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("radius", ctypes.c_int32), ("taps", ctypes.c_void_p)]
+
+
+class pd_wavelet(ctypes.Structure):
+    _fields_ = [("len", ctypes.c_int32), ("h", ctypes.POINTER(ctypes.c_double))]
+
+
+class pd_weights(ctypes.Structure):
+    _fields_ = [("level_w", ctypes.POINTER(ctypes.c_double)), ("coeff_w", ctypes.c_void_p),
+                ("joint", ctypes.c_int32)]
+
+
+class pd_params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("iter_offset", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
+
+
+class pd_image_desc(ctypes.Structure):
+    _fields_ = [("shape", pd_shape), ("offset", ctypes.c_int64), ("tau", ctypes.c_double),
+                ("op", pd_operator), ("level_w", ctypes.POINTER(ctypes.c_double))]
+
+
+# every symbol include/pd.h declares
+EXPORTS = [
+    "pd_workspace_size", "pd_solve", "pd_batched_workspace_size", "pd_solve_batched",
+    "pd_backward_workspace_size", "pd_backward", "pd_fwt", "pd_apply_op", "pd_symmlet",
+    "pd_op1_taps", "pd_strerror",
+]
+
+_lib = None
+
+
+class PDError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpd.so not built at {LIB_PATH}; run `python -m paper_2005_09870_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, sz, i32, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    dp = P(ctypes.c_double)
+    L.pd_workspace_size.argtypes = [P(pd_shape), i32]
+    L.pd_workspace_size.restype = sz
+    L.pd_solve.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights),
+                           P(pd_params), vp, vp, vp, i32, vp, vp, vp, sz, vp]
+    L.pd_solve.restype = ctypes.c_int
+    L.pd_batched_workspace_size.argtypes = [i32, P(pd_image_desc), i32]
+    L.pd_batched_workspace_size.restype = sz
+    L.pd_solve_batched.argtypes = [i32, P(pd_image_desc), i32, P(pd_wavelet), i32, vp, vp, vp,
+                                   vp, sz, vp]
+    L.pd_solve_batched.restype = ctypes.c_int
+    L.pd_backward_workspace_size.argtypes = [P(pd_shape), i32, i32, i32]
+    L.pd_backward_workspace_size.restype = sz
+    L.pd_backward.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights),
+                              P(pd_params), vp, vp, vp, vp, i32, vp, sz, vp]
+    L.pd_backward.restype = ctypes.c_int
+    L.pd_fwt.argtypes = [P(pd_shape), i32, P(pd_wavelet), i32, vp, vp, vp, sz, vp]
+    L.pd_fwt.restype = ctypes.c_int
+    L.pd_apply_op.argtypes = [P(pd_shape), i32, P(pd_operator), i32, vp, vp, vp]
+    L.pd_apply_op.restype = ctypes.c_int
+    L.pd_symmlet.argtypes = [i32, dp]
+    L.pd_symmlet.restype = ctypes.c_int
+    L.pd_op1_taps.argtypes = [i32, d, d, P(i32), dp]
+    L.pd_op1_taps.restype = ctypes.c_int
+    L.pd_strerror.argtypes = [i32]
+    L.pd_strerror.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return load().pd_strerror(int(code)).decode()
+    except ImportError:
+        return f"status {code}"
+
+
+def check(code: int, where: str) -> None:
+    if code != PD_OK:
+        raise PDError(code, where)

@@ -1,0 +1,233 @@
+"""Python binding of libpd: argument marshalling over torch device tensors.
+
+Every step of the solver runs in libpd's HIP kernels; torch only provides
+device memory and the current HIP stream.  Names follow the C ABI
+(include/pd.h).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+_DT = {torch.float32: C.PD_F32, torch.float64: C.PD_F64}
+
+
+def _dtype_code(dtype: torch.dtype) -> int:
+    if dtype not in _DT:
+        raise TypeError(f"unsupported dtype {dtype}; use float32 or float64")
+    return _DT[dtype]
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("libpd needs contiguous device tensors")
+
+
+# ------------------------------------------------------------------- set-up --
+def pd_symmlet(moments: int = 6) -> np.ndarray:
+    """Low-pass filter of the Symmlet with `moments` vanishing moments (host)."""
+    h = np.zeros(2 * moments)
+    C.check(C.load().pd_symmlet(moments, _dptr(h)), "pd_symmlet")
+    return h
+
+
+def pd_op1_taps(n2: int, sigma_max: float = 3.0, mass: float = 0.99):
+    """Operator-1 profile table (n2, 2R+1) of source rows and its half-width R."""
+    r = ctypes.c_int32()
+    L = C.load()
+    C.check(L.pd_op1_taps(n2, sigma_max, mass, ctypes.byref(r), None), "pd_op1_taps")
+    taps = np.zeros((n2, 2 * r.value + 1))
+    C.check(L.pd_op1_taps(n2, sigma_max, mass, ctypes.byref(r), _dptr(taps)), "pd_op1_taps")
+    return taps, r.value
+
+
+@dataclass
+class Operator:
+    """Blur operator on the device: PD_OP_IDENTITY or a row-profile table."""
+    kind: int
+    radius: int = 0
+    taps: torch.Tensor | None = None
+
+    @staticmethod
+    def identity() -> "Operator":
+        return Operator(C.PD_OP_IDENTITY)
+
+    @staticmethod
+    def op1(n2: int, dtype=torch.float32, device="cuda", sigma_max=3.0, mass=0.99) -> "Operator":
+        taps, R = pd_op1_taps(n2, sigma_max, mass)
+        return Operator(C.PD_OP_ROWBLUR, R, torch.as_tensor(taps, dtype=dtype, device=device).contiguous())
+
+    @staticmethod
+    def from_taps(taps, radius: int, dtype=torch.float32, device="cuda") -> "Operator":
+        t = torch.as_tensor(np.asarray(taps), dtype=dtype, device=device).contiguous()
+        return Operator(C.PD_OP_ROWBLUR, int(radius), t)
+
+    def c(self) -> C.pd_operator:
+        return C.pd_operator(self.kind, self.radius, None if self.taps is None else self.taps.data_ptr())
+
+
+def _shape(x: torch.Tensor, levels: int) -> C.pd_shape:
+    if x.dim() != 3:
+        raise ValueError("expected a (C, n2, n1) tensor")
+    c, n2, n1 = x.shape
+    return C.pd_shape(n1, n2, c, levels)
+
+
+def _wavelet(h) -> tuple[C.pd_wavelet, np.ndarray]:
+    h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+    return C.pd_wavelet(len(h), _dptr(h)), h
+
+
+def pd_workspace_size(shape: C.pd_shape, dtype: torch.dtype) -> int:
+    return int(C.load().pd_workspace_size(ctypes.byref(shape), _dtype_code(dtype)))
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------- solve ---
+def pd_solve(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
+             level_w=None, coeff_w: torch.Tensor | None = None, joint: bool = False,
+             z_cur: torch.Tensor | None = None, z_prev: torch.Tensor | None = None,
+             init: bool = True, iter_offset: int = 0, want_f: bool = True,
+             stats: bool = False, check_finite: bool = False,
+             ws: torch.Tensor | None = None):
+    """Run `iters` FISTA iterations on eq. 4.1.  Returns a dict with f (Psi z),
+    z_cur, z_prev and stats ((iters, 3) FP64: data term and regulariser at
+    y(i), ||z(i) - y(i)||^2)."""
+    _check_dev(f0, coeff_w, z_cur, z_prev)
+    dt = _dtype_code(f0.dtype)
+    shape = _shape(f0, levels)
+    wav, hh = _wavelet(h)
+    lw = None
+    if level_w is not None:
+        lw = np.ascontiguousarray(np.asarray(level_w, dtype=np.float64))
+        if lw.shape != (levels + 1,):
+            raise ValueError("level_w needs levels+1 entries")
+    w = C.pd_weights(_dptr(lw) if lw is not None else None,
+                     None if coeff_w is None else coeff_w.data_ptr(), 1 if joint else 0)
+    prm = C.pd_params(float(tau), int(iters), int(iter_offset), 1 if check_finite else 0)
+    if z_cur is None:
+        z_cur = torch.empty_like(f0)
+    if z_prev is None:
+        z_prev = torch.empty_like(f0)
+    f = torch.empty_like(f0) if want_f else None
+    st = torch.zeros((max(iters, 1), 3), dtype=torch.float64, device=f0.device) if stats else None
+    need = pd_workspace_size(shape, f0.dtype)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, f0.device)
+    opc = op.c()
+    rc = C.load().pd_solve(ctypes.byref(shape), dt, ctypes.byref(opc), ctypes.byref(wav),
+                           ctypes.byref(w), ctypes.byref(prm), _ptr(f0), _ptr(z_cur), _ptr(z_prev),
+                           1 if init else 0, _ptr(f), _ptr(st), _ptr(ws), ws.numel(),
+                           _stream(f0.device))
+    C.check(rc, "pd_solve")
+    return {"f": f, "z_cur": z_cur, "z_prev": z_prev,
+            "stats": None if st is None else st[:iters]}
+
+
+def pd_fwt(x: torch.Tensor, h, levels: int, inverse: bool = False,
+           ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Psi^* x (forward) or Psi x (inverse) for a (C, n2, n1) tensor."""
+    _check_dev(x)
+    shape = _shape(x, levels)
+    wav, hh = _wavelet(h)
+    out = torch.empty_like(x)
+    need = pd_workspace_size(shape, x.dtype)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, x.device)
+    rc = C.load().pd_fwt(ctypes.byref(shape), _dtype_code(x.dtype), ctypes.byref(wav),
+                         1 if inverse else 0, _ptr(x), _ptr(out), _ptr(ws), ws.numel(),
+                         _stream(x.device))
+    C.check(rc, "pd_fwt")
+    return out
+
+
+def pd_apply_op(x: torch.Tensor, op: Operator, transpose: bool = False) -> torch.Tensor:
+    """H x or H^T x for a (C, n2, n1) tensor."""
+    _check_dev(x)
+    shape = _shape(x, 1 if x.shape[1] % 2 == 0 and x.shape[2] % 2 == 0 else 0)
+    shape.levels = 1
+    out = torch.empty_like(x)
+    opc = op.c()
+    rc = C.load().pd_apply_op(ctypes.byref(shape), _dtype_code(x.dtype), ctypes.byref(opc),
+                              1 if transpose else 0, _ptr(x), _ptr(out), _stream(x.device))
+    C.check(rc, "pd_apply_op")
+    return out
+
+
+def lipschitz(op: Operator, n1: int, n2: int, iters: int = 200, seed: int = 0,
+              dtype=torch.float64, device="cuda") -> float:
+    """||H^T H||_2 by power iteration on the GPU (host-side normalisation)."""
+    if op.kind == C.PD_OP_IDENTITY:
+        return 1.0
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    x = torch.randn((1, n2, n1), generator=g, dtype=torch.float64).to(device=device, dtype=dtype)
+    x /= torch.linalg.vector_norm(x)
+    lam = 0.0
+    opd = op if op.taps is None or op.taps.dtype == dtype else Operator(op.kind, op.radius, op.taps.to(dtype))
+    for _ in range(iters):
+        y = pd_apply_op(pd_apply_op(x, opd), opd, transpose=True)
+        lam = float(torch.linalg.vector_norm(y))
+        x = y / lam
+    return lam
+
+
+def step_size(op: Operator, n1: int, n2: int, device="cuda") -> float:
+    return 1.0 / (lipschitz(op, n1, n2, device=device) * (1.0 + 1e-6))
+
+
+# ----------------------------------------------------------------- batched ---
+def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, taus, h,
+                     levels: list[int], iters: int, stats: bool = False):
+    """Solve a batch of uneven-size problems; returns the list of f = Psi z."""
+    dev = f0s[0].device
+    dtype = f0s[0].dtype
+    sizes = [t.numel() for t in f0s]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    f0p = torch.cat([t.reshape(-1) for t in f0s]).contiguous()
+    fo = torch.empty_like(f0p)
+    descs = (C.pd_image_desc * len(f0s))()
+    keep = []
+    for b, t in enumerate(f0s):
+        lw = np.ascontiguousarray(np.asarray(level_ws[b], dtype=np.float64))
+        keep.append(lw)
+        descs[b].shape = _shape(t, levels[b])
+        descs[b].offset = int(offs[b])
+        descs[b].tau = float(taus[b])
+        descs[b].op = ops[b].c()
+        descs[b].level_w = _dptr(lw)
+    wav, hh = _wavelet(h)
+    L = C.load()
+    dt = _dtype_code(dtype)
+    need = L.pd_batched_workspace_size(len(f0s), descs, dt)
+    if need == 0:
+        raise C.PDError(C.PD_ERR_SHAPE, "pd_batched_workspace_size")
+    ws = workspace(need, dev)
+    st = torch.zeros((len(f0s), max(iters, 1), 3), dtype=torch.float64, device=dev) if stats else None
+    rc = L.pd_solve_batched(len(f0s), descs, dt, ctypes.byref(wav), int(iters), _ptr(f0p), _ptr(fo),
+                            _ptr(st), _ptr(ws), ws.numel(), _stream(dev))
+    C.check(rc, "pd_solve_batched")
+    outs = [fo[o:o + n].view_as(t) for o, n, t in zip(offs, sizes, f0s)]
+    return outs, st

@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+its host-side set-up matches the oracle, and argument errors are reported
+before any GPU work is enqueued (no device calls happen in these tests)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2005_09870_amd import _lib as C
+from paper_2005_09870_amd import solver as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "pd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.load()
+    syms = declared_symbols()
+    assert len(syms) >= 11
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(C.EXPORTS) == syms
+
+
+def test_symmlet_matches_oracle():
+    for M in range(1, 9):
+        np.testing.assert_allclose(S.pd_symmlet(M), O.symmlet(M), atol=5e-15)
+
+
+def test_op1_taps_match_oracle():
+    for n2 in (2, 8, 64, 96, 512, 2048):
+        t, R = S.pd_op1_taps(n2)
+        kt, RR = O.op1_profiles(n2)
+        assert R == RR
+        np.testing.assert_allclose(t, kt, atol=1e-15)
+
+
+def _fake(n):
+    return ctypes.c_void_p(0x1000 * n)
+
+
+def _call_solve(shape, dtype=C.PD_F32, op=None, wav=None, w=None, prm=None, f0=1, zc=2, zp=3,
+                ws=4, ws_bytes=None):
+    L = C.load()
+    h = S.pd_symmlet(6)
+    wav = wav or C.pd_wavelet(12, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    lw = np.zeros(shape.levels + 1 if shape.levels > 0 else 1)
+    w = w or C.pd_weights(lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0)
+    op = op or C.pd_operator(C.PD_OP_IDENTITY, 0, None)
+    prm = prm or C.pd_params(0.5, 10, 0, 0)
+    if ws_bytes is None:
+        ws_bytes = 1 << 40
+    return L.pd_solve(ctypes.byref(shape), dtype, ctypes.byref(op), ctypes.byref(wav), ctypes.byref(w),
+                      ctypes.byref(prm), _fake(f0) if f0 else None, _fake(zc) if zc else None,
+                      _fake(zp) if zp else None, 1, None, None, _fake(ws) if ws else None,
+                      ws_bytes, None)
+
+
+def test_argument_errors_are_reported_without_gpu_work():
+    ok = C.pd_shape(64, 64, 1, 6)
+    assert _call_solve(C.pd_shape(100, 64, 1, 3)) == C.PD_ERR_SHAPE      # 100 % 8 != 0
+    assert _call_solve(C.pd_shape(64, 64, 1, 7)) == C.PD_ERR_SHAPE       # too deep
+    assert _call_solve(C.pd_shape(64, 64, 0, 3)) == C.PD_ERR_SHAPE       # no channel
+    assert _call_solve(C.pd_shape(64, 64, 5, 3)) == C.PD_ERR_SHAPE       # too many channels
+    assert _call_solve(ok, dtype=7) == C.PD_ERR_ARG
+    assert _call_solve(ok, f0=0) == C.PD_ERR_ARG
+    assert _call_solve(ok, zc=2, zp=2) == C.PD_ERR_ARG                   # aliased state
+    assert _call_solve(ok, prm=C.pd_params(0.0, 10, 0, 0)) == C.PD_ERR_TAU
+    assert _call_solve(ok, prm=C.pd_params(float("nan"), 10, 0, 0)) == C.PD_ERR_TAU
+    assert _call_solve(ok, prm=C.pd_params(0.5, -1, 0, 0)) == C.PD_ERR_ARG
+    assert _call_solve(ok, op=C.pd_operator(9, 0, None)) == C.PD_ERR_ARG
+    assert _call_solve(ok, op=C.pd_operator(C.PD_OP_ROWBLUR, 9, None)) == C.PD_ERR_ARG
+    assert _call_solve(ok, op=C.pd_operator(C.PD_OP_ROWBLUR, 12, _fake(9))) == C.PD_ERR_UNSUPPORTED
+    h3 = np.zeros(3)
+    assert _call_solve(ok, wav=C.pd_wavelet(3, h3.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))) \
+        == C.PD_ERR_UNSUPPORTED
+    both = C.pd_weights(None, None, 0)
+    assert _call_solve(ok, w=both) == C.PD_ERR_ARG
+    need = C.load().pd_workspace_size(ctypes.byref(ok), C.PD_F32)
+    assert need > 0
+    assert _call_solve(ok, ws_bytes=need - 1) == C.PD_ERR_WORKSPACE
+
+
+def test_workspace_size_rejects_bad_shapes():
+    L = C.load()
+    assert L.pd_workspace_size(ctypes.byref(C.pd_shape(100, 64, 1, 3)), C.PD_F32) == 0
+    a = L.pd_workspace_size(ctypes.byref(C.pd_shape(512, 512, 1, 9)), C.PD_F32)
+    b = L.pd_workspace_size(ctypes.byref(C.pd_shape(512, 512, 1, 9)), C.PD_F64)
+    assert 2 * 512 * 512 * 4 < a < b
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert C.strerror(code) != "unknown status"
