@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the FISTA-Spa hot path on one MI355X.
+
+Workload (the step): one solve of eq. 4.1 on a 512 x 512 FP32 image -- a
+seeded piecewise-constant scene (40 rectangles, 25 disks, ramp background)
+blurred by the paper's Operator 1 plus Gaussian noise (sigma 0.05), Symmlet-6,
+9 levels, weights linear in scale with 0.08 on the finest band -- for 2000
+FISTA iterations, FP64 energy reductions on.  Inputs are resident in HBM when
+the timed region starts.
+
+Prints ONE JSON line.  value = Mpixel-iterations/s of the forward solve.
+Extra fields: the dominant kernel's roofline (algorithmic bytes per launch /
+its average duration from HIP events the library records on the launch
+stream), the oracle timed on the host cores on a bounded sample, and the
+batched (uneven sizes) vs per-image comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_w: bool) -> float:
+    """Algorithmic (compulsory) HBM bytes of one launch of a kernel class.
+
+    blur      : read x, f0; write s                         -> 3 planes
+    synthesis : level l writes the (n >> (l-1)) approximation; reads the
+                3 detail bands twice (z(i-1), z(i-2)) and the coarser
+                approximation once                           -> 2.75 x output
+    analysis  : level l reads its input (n >> (l-1)), z(i-1) and z(i-2) on
+                its detail bands, writes z(i) there and the coarser
+                approximation                                -> 3.5 x input
+                (+0.75 x input with a per-coefficient weight map)
+    coarse    : all levels from l on, one workgroup          -> 5 x input
+    """
+    if kernel == "blur":
+        return 3.0 * es * n1 * n2 * C
+    if level < 1:
+        return 0.0
+    m = (n1 >> (level - 1)) * (n2 >> (level - 1)) * C
+    if kernel == "coarse":
+        # level = first level of the block: reads the level's input approximation
+        # and z(i-1), z(i-2) on the block, writes z(i) and the next approximation
+        return 5.0 * es * m
+    if kernel == "synthesis":
+        return 2.75 * es * m
+    if kernel == "analysis":
+        return (3.5 + (0.75 if coeff_w else 0.0)) * es * m
+    return 0.0
+
+
+def make_problem(torch, P, SI, n=512, seed=2):
+    case = SI.case_512(seed)
+    dev = "cuda"
+    op = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    clean = torch.as_tensor(case.clean, dtype=torch.float32, device=dev)
+    f0 = P.pd_apply_op(clean, op) + torch.as_tensor(case.noise, dtype=torch.float32, device=dev)
+    tau = P.step_size(op, n, n, device=dev)
+    return case, op, f0.contiguous(), tau
+
+
+def time_forward(torch, P, case, op, f0, tau, iters, steps, warmup, h):
+    shape = P.solver._shape(f0, case.levels)
+    ws = P.solver.workspace(P.pd_workspace_size(shape, f0.dtype), f0.device)
+    zc = torch.empty_like(f0)
+    zp = torch.empty_like(f0)
+    out = torch.empty_like(f0)
+
+    def step():
+        r = P.pd_solve(f0, op, h, case.levels, tau, iters, level_w=case.level_w, z_cur=zc,
+                       z_prev=zp, stats=True, ws=ws, want_f=True)
+        out.copy_(r["f"])
+        return r
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        r = step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    return wall, ev_ms, r, step
+
+
+def kernel_table(torch, P, step):
+    """One instrumented step: per-launch HIP events recorded by the library."""
+    P.solver.pd_timing_enable(True)
+    step()
+    torch.cuda.synchronize()
+    rows = P.solver.pd_timing_read()
+    P.solver.pd_timing_enable(False)
+    return rows
+
+
+def cpu_baseline(SI, seconds_target=15.0):
+    """The oracle (plain FP64 C, OpenMP over rows) on the same 512^2 workload,
+    for a bounded number of iterations."""
+    import numpy as np
+    from oracle import oracle as O
+    case = SI.case_512()
+    n = 512
+    pb = O.Problem(n, n, 1, case.levels, h=O.symmlet(6),
+                   w=O.expand_level_weights(case.level_w, n, n, case.levels))
+    f0 = O.apply_H(pb, case.clean) + case.noise
+    tau = 0.89
+    t = time.perf_counter()
+    O.fista(pb, f0, tau, 2)
+    per_it = (time.perf_counter() - t) / 2
+    iters = int(max(4, min(200, seconds_target / max(per_it, 1e-6))))
+    t = time.perf_counter()
+    O.fista(pb, f0, tau, iters)
+    dt = time.perf_counter() - t
+    return {"value": round(n * n * iters / dt / 1e6, 4), "unit": "Mpixel-iter/s",
+            "cores": O.threads(), "kind": "oracle",
+            "sample": f"512x512 FP64, {iters} FISTA iterations (of the 2000-iteration workload), "
+                      f"{dt:.1f} s"}
+
+
+def batched_vs_per_image(torch, P, SI, h, iters, count):
+    """Uneven sizes (sides uniform on {96..1024 step 32}, per-image lambda):
+    one pd_solve_batched call vs a loop of pd_solve calls on one stream."""
+    cases = SI.case_batch(count)
+    dev = "cuda"
+    f0s, ops, taus, lws, levels = [], [], [], [], []
+    for c in cases:
+        op = P.Operator.op1(c.n2, dtype=torch.float32, device=dev)
+        clean = torch.as_tensor(c.clean, dtype=torch.float32, device=dev)
+        f0 = (P.pd_apply_op(clean, op) + torch.as_tensor(c.noise, dtype=torch.float32, device=dev)).contiguous()
+        f0s.append(f0)
+        ops.append(op)
+        lws.append(c.level_w)
+        levels.append(c.levels)
+        taus.append(0.89)
+    px = sum(c.n1 * c.n2 for c in cases)
+
+    def per_image():
+        return [P.pd_solve(f0, op, h, L, t, iters, level_w=lw)["f"]
+                for f0, op, L, t, lw in zip(f0s, ops, levels, taus, lws)]
+
+    def batched():
+        return P.pd_solve_batched(f0s, ops, lws, taus, h, levels, iters)[0]
+
+    res = {}
+    for name, fn in (("per_image", per_image), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        outs = fn()
+        torch.cuda.synchronize()
+        res[name] = px * iters / (time.perf_counter() - t) / 1e6
+        res[name + "_out"] = outs
+    same = all(torch.equal(a, b) for a, b in zip(res["per_image_out"], res["batched_out"]))
+    return {"images": count, "iters": iters, "pixels": px,
+            "batched_mpx_it_s": round(res["batched"], 1),
+            "per_image_mpx_it_s": round(res["per_image"], 1),
+            "speedup": round(res["batched"] / res["per_image"], 3), "bitwise_equal": same}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-iters", type=int, default=100)
+    ap.add_argument("--batched-count", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; multi-GPU sharding is not "
+                                   "implemented (one image or batch per GPU)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2005_09870_amd as P
+    import syninputs as SI
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    h = P.pd_symmlet(6)
+    case, op, f0, tau = make_problem(torch, P, SI)
+    n = case.n1
+    log(f"[bench] 512x512 FP32, {args.iters} iterations, tau={tau:.6f}, steps={args.steps}, warmup={args.warmup}")
+    wall, ev_ms, r, step = time_forward(torch, P, case, op, f0, tau, args.iters, args.steps,
+                                        args.warmup, h)
+    ms_per_step = ev_ms / args.steps
+    value = n * n * args.iters / (ms_per_step / 1e3) / 1e6
+    log(f"[bench] {ms_per_step:.2f} ms/step (events), wall {1e3 * wall / args.steps:.2f} ms/step, "
+        f"{value:.1f} Mpx-it/s")
+
+    rows = kernel_table(torch, P, step)
+    for rw in rows:
+        rw["alg_bytes_per_launch"] = alg_bytes(rw["kernel"], rw["level"], n, n, 1, 4, False)
+    dom = max(rows, key=lambda rw: rw["total_ms"])
+    achieved = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{dom['kernel']}" + (f" level {dom['level']}" if dom["level"] else ""),
+                "avg_us": round(dom["avg_us"], 3), "launches_per_step": dom["launches"],
+                "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+    log("[bench] kernels: " + "; ".join(f"{rw['kernel']}/{rw['level']}: {rw['avg_us']:.2f} us x "
+                                        f"{rw['launches']}" for rw in rows))
+
+    line = {"metric": "Mpixel-iter/s (fwd) at 512^2 FP32", "value": round(value, 1),
+            "unit": "Mpixel-iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "512x512 FP32 deblurring (Operator 1, Symmlet-6, 9 levels), "
+                                   "2000 FISTA iterations per step, FP64 energy reductions",
+                       "iters": args.iters, "n1": n, "n2": n, "levels": case.levels},
+            "roofline": roofline}
+    if not args.no_batched:
+        log(f"[bench] batched vs per-image: {args.batched_count} images, {args.batched_iters} iterations")
+        line["batched"] = batched_vs_per_image(torch, P, SI, h, args.batched_iters, args.batched_count)
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(SI)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

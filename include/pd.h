@@ -215,6 +215,27 @@ int pd_symmlet(int32_t moments, double *h_out);
 int pd_op1_taps(int32_t n2, double sigma_max, double mass, int32_t *radius,
                 double *taps_out);
 
+/* Diagnostics: per-launch kernel timing.  While enabled, every kernel launch
+ * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt is bracketed by
+ * two HIP events recorded on its launch stream, keyed by kernel class and
+ * decomposition level.  Adds one event pair per launch; not thread-safe.   */
+typedef enum {
+    PD_K_BLUR = 1,      /* fused r = H x - f0, s = H^T r                       */
+    PD_K_SYNTH = 2,     /* one synthesis level (level = decomposition level)   */
+    PD_K_ANALYSIS = 3,  /* one analysis level with the fused prox              */
+    PD_K_COARSE = 4,    /* all coarse levels of an iteration in one workgroup  */
+    PD_K_OTHER = 5      /* copies and set-up                                   */
+} pd_kernel_class;
+
+/* Start (enable != 0) or stop recording.  Starting clears the record. */
+int pd_timing_enable(int32_t enable);
+
+/* Waits for the recorded events and writes up to max_rows rows (kernel
+ * class, level, launches, total milliseconds) to the host arrays; *rows gets
+ * the number of rows available. */
+int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *launches,
+                   double *total_ms, int32_t *rows);
+
 /* Short description of a pd_status code. */
 const char *pd_strerror(int32_t status);
 

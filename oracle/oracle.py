@@ -59,6 +59,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         i = ctypes.c_int
         d = ctypes.c_double
+        L.or_threads.argtypes = []
+        L.or_threads.restype = i
         L.or_fwt2.argtypes = [dp, i, i, i, dp, i]
         L.or_ifwt2.argtypes = [dp, i, i, i, dp, i]
         L.or_blur.argtypes = [dp, dp, i, i, dp, i, i]
@@ -69,6 +71,11 @@ def lib():
         L.or_fista_reverse.argtypes = [i, i, i, i, dp, i, dp, i, i, dp, d, i, dp, dp, dp, dp]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_threads())
 
 
 def _p(a):

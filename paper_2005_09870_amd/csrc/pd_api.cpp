@@ -3,8 +3,12 @@
 // (Escande & Weiss, arXiv:2005.09870, Appendix A.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "pd.h"
@@ -84,7 +88,7 @@ Filt<T> make_filt(const pd_wavelet *w)
 // Workspace: approximation pyramid (levels 1..L-1), x, s, flag.
 struct Layout {
     size_t apx[PD_MAXL + 1];
-    size_t x, s, flag, total;
+    size_t x, s, flag, slots, total;
 };
 
 Layout layout(const pd_shape *s, size_t es)
@@ -104,14 +108,53 @@ Layout layout(const pd_shape *s, size_t es)
     off = align_up(off + plane);
     l.flag = off;
     off = align_up(off + 256);
+    l.slots = off;
+    off = align_up(off + 3 * PD_NSLOT * sizeof(double));
     l.total = off;
     return l;
+}
+
+// ------------------------------------------------ per-launch event timing --
+struct TimedLaunch {
+    int kclass, level;
+    hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_launches;
+
+template <typename F>
+hipError_t timed(int kclass, int level, hipStream_t st, F &&launch)
+{
+    if (!g_timing) return launch();
+    TimedLaunch t{kclass, level, nullptr, nullptr};
+    hipError_t e;
+    if ((e = hipEventCreate(&t.a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&t.b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(t.a, st)) != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(t.b, st)) != hipSuccess) return e;
+    g_launches.push_back(t);
+    return hipSuccess;
+}
+
+void clear_timing()
+{
+    for (auto &t : g_launches) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_launches.clear();
 }
 
 #define PD_TRY_HIP(expr)                      \
     do {                                      \
         if ((expr) != hipSuccess) return PD_ERR_HIP; \
     } while (0)
+
+// Largest approximation (per side) the coarse kernel holds in LDS.
+constexpr int COARSE_MAX = 64;
+constexpr size_t COARSE_LDS_MAX = 64 * 1024;
 
 template <typename T>
 struct Ctx {
@@ -120,19 +163,91 @@ struct Ctx {
     char *ws;
     Layout lay;
     hipStream_t st;
+    int lc;  // first level handled by the coarse kernel (levels + 1: none)
     int64_t N() const { return (int64_t)sh->n1 * sh->n2; }
     T *apx(int j) const { return (T *)(ws + lay.apx[j]); }
     T *x() const { return (T *)(ws + lay.x); }
     T *s() const { return (T *)(ws + lay.s); }
     int *flag() const { return (int *)(ws + lay.flag); }
+    double *slots() const { return (double *)(ws + lay.slots); }
 };
 
-// x = Psi y, y = zc + beta (zc - zp)
+// First level lc such that the level lc-1 approximation fits the coarse
+// kernel (<= COARSE_MAX per side and its LDS budget); levels+1 if none.
 template <typename T>
-int synth_chain(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
+int coarse_level(const pd_shape *sh, int joint)
+{
+    const int chans = joint ? sh->channels : 1;
+    for (int lc = 1; lc <= sh->levels; ++lc) {
+        int m1 = sh->n1 >> (lc - 1), m2 = sh->n2 >> (lc - 1);
+        if (m1 <= COARSE_MAX && m2 <= COARSE_MAX &&
+            coarse_lds_bytes<T>(m1, m2, chans) <= COARSE_LDS_MAX)
+            return lc;
+    }
+    return sh->levels + 1;
+}
+
+template <typename T>
+ProxArgs<T> prox_args(const Ctx<T> &c, const T *zc, const T *zp, T *zn, T beta, T tau,
+                      const pd_weights *w, double *stats)
+{
+    ProxArgs<T> p;
+    p.zc = zc;
+    p.zp = zp;
+    p.zn = zn;
+    p.beta = beta;
+    p.tau = tau;
+    p.plane = c.N();
+    p.pitch = c.sh->n1;
+    p.wmap = nullptr;
+    for (int k = 0; k <= PD_MAXL; ++k) p.wlev[k] = T(0);
+    p.joint = 0;
+    if (w) {
+        p.wmap = (const T *)w->coeff_w;
+        if (w->level_w)
+            for (int k = 0; k <= c.sh->levels; ++k) p.wlev[k] = (T)w->level_w[k];
+        p.joint = w->joint ? 1 : 0;
+    }
+    p.C = c.sh->channels;
+    p.slots = stats ? c.slots() : nullptr;
+    p.stats = stats;
+    p.flag = c.flag();
+    return p;
+}
+
+// Coarse kernel: ops = COARSE_* bits.  Analysis input is the level lc-1
+// approximation (apx[lc-1], or `in` when lc == 1); synthesis output goes to
+// apx[lc-1] or `out` when lc == 1.
+template <typename T>
+int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T> &p, T beta_next)
+{
+    const int L = c.sh->levels, lc = c.lc;
+    CoarseArgs<T> a;
+    a.f = c.f;
+    a.ops = ops;
+    a.m1 = c.sh->n1 >> (lc - 1);
+    a.m2 = c.sh->n2 >> (lc - 1);
+    a.nlev = L - lc + 1;
+    a.band_top = L + 1 - lc;
+    a.apx_in = lc == 1 ? in : c.apx(lc - 1);
+    a.apx_in_plane = lc == 1 ? c.N() : (int64_t)a.m1 * a.m2;
+    a.apx_out = lc == 1 ? out : c.apx(lc - 1);
+    a.apx_out_plane = a.apx_in_plane;
+    a.beta_next = beta_next;
+    a.p = p;
+    const int groups = p.joint ? 1 : c.sh->channels;
+    a.finalize = groups == 1 ? 1 : 0;
+    PD_TRY_HIP(timed(PD_K_COARSE, lc, c.st, [&] { return launch_coarse<T>(a, groups, c.st); }));
+    return PD_OK;
+}
+
+// Fine synthesis levels lc-1 .. 1 (their approximation input comes from the
+// coarse kernel's output, or from the state when there is no coarse kernel).
+template <typename T>
+int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
 {
     const int L = c.sh->levels, n1 = c.sh->n1, n2 = c.sh->n2;
-    for (int lev = L; lev >= 1; --lev) {
+    for (int lev = c.lc - 1; lev >= 1; --lev) {
         SynthArgs<T> a;
         a.f = c.f;
         a.zc = zc;
@@ -147,19 +262,30 @@ int synth_chain(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
         a.out_plane = lev == 1 ? c.N() : (int64_t)(n1 >> (lev - 1)) * (n2 >> (lev - 1));
         a.M1c = n1 >> lev;
         a.M2c = n2 >> lev;
-        PD_TRY_HIP(launch_synth<T>(a, c.sh->channels, c.st));
+        PD_TRY_HIP(timed(PD_K_SYNTH, lev, c.st, [&] { return launch_synth<T>(a, c.sh->channels, c.st); }));
     }
     return PD_OK;
 }
 
-// Forward transform of `in`: plain coefficients (mode PLAIN) or the fused
-// gradient step + prox + momentum (mode PROX).
+// x = Psi y, y = zc + beta (zc - zp): coarse kernel (synthesis only) + fine levels
 template <typename T>
-int analysis_chain(const Ctx<T> &c, const T *in, int mode, const T *zc, const T *zp, T *zn,
-                   T beta, T tau, const pd_weights *w, double *stats)
+int synth_chain(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
+{
+    int rc;
+    if (c.lc <= c.sh->levels) {
+        ProxArgs<T> p = prox_args<T>(c, zc, zp, nullptr, beta, T(0), nullptr, nullptr);
+        if ((rc = coarse_step<T>(c, COARSE_SYN, nullptr, out, p, T(0))) != PD_OK) return rc;
+    }
+    return synth_fine<T>(c, zc, zp, beta, out);
+}
+
+// Fine analysis levels 1 .. lc-1: plain coefficients (MODE_PLAIN) or the fused
+// gradient step + prox + momentum (MODE_PROX).
+template <typename T>
+int analysis_fine(const Ctx<T> &c, const T *in, int mode, const ProxArgs<T> &p)
 {
     const int L = c.sh->levels, n1 = c.sh->n1, n2 = c.sh->n2;
-    for (int lev = 1; lev <= L; ++lev) {
+    for (int lev = 1; lev <= c.lc - 1; ++lev) {
         AnalysisArgs<T> a;
         a.f = c.f;
         a.in = lev == 1 ? in : c.apx(lev - 1);
@@ -171,28 +297,21 @@ int analysis_chain(const Ctx<T> &c, const T *in, int mode, const T *zc, const T 
         a.apx_out = lev < L ? c.apx(lev) : nullptr;
         a.apx_plane = (int64_t)(n1 >> lev) * (n2 >> lev);
         a.mode = mode;
-        a.zc = zc;
-        a.zp = zp;
-        a.zn = zn;
-        a.beta = beta;
-        a.tau = tau;
-        a.plane = c.N();
-        a.pitch = n1;
-        a.wmap = nullptr;
-        for (int k = 0; k <= PD_MAXL; ++k) a.wlev[k] = T(0);
-        a.joint = 0;
-        if (w) {
-            a.wmap = (const T *)w->coeff_w;
-            if (w->level_w)
-                for (int k = 0; k <= L; ++k) a.wlev[k] = (T)w->level_w[k];
-            a.joint = w->joint ? 1 : 0;
-        }
         a.band_detail = L + 1 - lev;
-        a.C = c.sh->channels;
-        a.stats = stats;
-        a.flag = c.flag();
-        PD_TRY_HIP(launch_analysis<T>(a, c.st));
+        a.p = p;
+        PD_TRY_HIP(timed(PD_K_ANALYSIS, lev, c.st, [&] { return launch_analysis<T>(a, c.st); }));
     }
+    return PD_OK;
+}
+
+// Plain forward transform out = Psi^* in.
+template <typename T>
+int analysis_plain(const Ctx<T> &c, const T *in, T *out)
+{
+    int rc;
+    ProxArgs<T> p = prox_args<T>(c, nullptr, nullptr, out, T(0), T(0), nullptr, nullptr);
+    if ((rc = analysis_fine<T>(c, in, MODE_PLAIN, p)) != PD_OK) return rc;
+    if (c.lc <= c.sh->levels) return coarse_step<T>(c, COARSE_ANA, in, nullptr, p, T(0));
     return PD_OK;
 }
 
@@ -209,15 +328,13 @@ int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T
     a.C = c.sh->channels;
     a.R = op->radius;
     a.plane = c.N();
-    a.stats = stats;
-    PD_TRY_HIP(launch_blur<T>(a, op->kind == PD_OP_IDENTITY, c.st));
+    a.slots = stats ? c.slots() : nullptr;
+    PD_TRY_HIP(timed(PD_K_BLUR, 0, c.st, [&] { return launch_blur<T>(a, op->kind == PD_OP_IDENTITY, c.st); }));
     return PD_OK;
 }
 
 template <typename T>
-int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
-               const pd_params *prm, const T *f0, T *z_cur, T *z_prev, int init, T *f_out,
-               double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
+Ctx<T> make_ctx(const pd_shape *sh, const pd_wavelet *wav, void *workspace, hipStream_t st, int joint)
 {
     Ctx<T> c;
     c.sh = sh;
@@ -225,37 +342,63 @@ int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav,
     c.ws = (char *)workspace;
     c.lay = layout(sh, sizeof(T));
     c.st = st;
+    c.lc = coarse_level<T>(sh, joint);
+    return c;
+}
+
+// Momentum of y(i) = z(i-1) + b (z(i-1) - z(i-2)):  b_{i-1} = (i-2)/(i+1), 0 for i = 1.
+inline double beta_y(int i) { return i >= 2 ? (double)(i - 2) / (double)(i + 1) : 0.0; }
+
+template <typename T>
+int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
+               const pd_params *prm, const T *f0, T *z_cur, T *z_prev, int init, T *f_out,
+               double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, w->joint);
     if (ws_bytes < c.lay.total) return PD_ERR_WORKSPACE;
     const int64_t NC = c.N() * sh->channels;
+    const bool coarse = c.lc <= sh->levels;
     int rc;
     if (init) {
-        if ((rc = analysis_chain<T>(c, f0, MODE_PLAIN, nullptr, nullptr, z_cur, T(0), T(0), nullptr,
-                                    nullptr)) != PD_OK)
-            return rc;
-        PD_TRY_HIP(launch_copy<T>(z_cur, z_prev, NC, st));
+        if ((rc = analysis_plain<T>(c, f0, z_cur)) != PD_OK) return rc;
+        PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, z_prev, NC, st); }));
     }
     if (prm->check_finite) PD_TRY_HIP(hipMemsetAsync(c.flag(), 0, sizeof(int), st));
+    if (stats) PD_TRY_HIP(launch_stats_finalize(c.slots(), nullptr, 1, st));
+    // the coarse kernel finalises the statistics when it runs as one workgroup
+    const bool coarse_finalises = coarse && (w->joint || sh->channels == 1);
     T *zc = z_cur, *zp = z_prev;
     const T tau = (T)prm->tau;
     for (int it = 0; it < prm->iters; ++it) {
         const int i = prm->iter_offset + 1 + it;  // global iteration number
-        // y(i) = z(i-1) + b_{i-1} (z(i-1) - z(i-2)),  b_k = (k-1)/(k+2)
-        const T beta = i >= 2 ? (T)((double)(i - 2) / (double)(i + 1)) : T(0);
+        const T beta = (T)beta_y(i);
+        const bool last = it == prm->iters - 1;
         double *sti = stats ? stats + 3 * (size_t)it : nullptr;
-        if ((rc = synth_chain<T>(c, zc, zp, beta, c.x())) != PD_OK) return rc;
-        if ((rc = blur_step<T>(c, op, c.x(), f0, c.s(), sti)) != PD_OK) return rc;
-        // z(i) overwrites z(i-2) in place (each coefficient read then written by one thread)
-        if ((rc = analysis_chain<T>(c, c.s(), MODE_PROX, zc, zp, zp, beta, tau, w, sti)) != PD_OK)
+        // x = Psi y(i); the coarse part was produced by the previous iteration's coarse kernel
+        if (it == 0) {
+            if ((rc = synth_chain<T>(c, zc, zp, beta, c.x())) != PD_OK) return rc;
+        } else if ((rc = synth_fine<T>(c, zc, zp, beta, c.x())) != PD_OK) {
             return rc;
+        }
+        if ((rc = blur_step<T>(c, op, c.x(), f0, c.s(), sti)) != PD_OK) return rc;
+        // z(i) overwrites z(i-2) in place (each coefficient is read, then written, by one thread)
+        ProxArgs<T> p = prox_args<T>(c, zc, zp, zp, beta, tau, w, sti);
+        if ((rc = analysis_fine<T>(c, c.s(), MODE_PROX, p)) != PD_OK) return rc;
+        if (coarse) {
+            const int ops = COARSE_ANA | COARSE_PROX | (last ? 0 : COARSE_SYN);
+            if ((rc = coarse_step<T>(c, ops, c.s(), c.x(), p, (T)beta_y(i + 1))) != PD_OK) return rc;
+        }
+        if (stats && !coarse_finalises)
+            PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_stats_finalize(c.slots(), sti, 0, st); }));
         T *t = zc;
         zc = zp;
         zp = t;
     }
     if (zc != z_cur) {  // odd number of iterations: swap the two planes
         T *tmp = c.x();
-        PD_TRY_HIP(launch_copy<T>(z_cur, tmp, NC, st));
-        PD_TRY_HIP(launch_copy<T>(z_prev, z_cur, NC, st));
-        PD_TRY_HIP(launch_copy<T>(tmp, z_prev, NC, st));
+        PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, tmp, NC, st); }));
+        PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_prev, z_cur, NC, st); }));
+        PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(tmp, z_prev, NC, st); }));
     }
     if (f_out)
         if ((rc = synth_chain<T>(c, z_cur, z_cur, T(0), f_out)) != PD_OK) return rc;
@@ -268,7 +411,419 @@ int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav,
     return PD_OK;
 }
 
+// ---------------------------------------------------------------- batched --
+// Lock-step solve of many images of uneven sizes: every phase of an iteration
+// (coarse synthesis, fine synthesis level l, blur, fine analysis level l,
+// coarse analysis + prox) is ONE launch over the tiles of all images that
+// have that phase.  Per-image argument blocks live in device tables built
+// once per call; the momentum, the buffer parity and the iteration index are
+// passed by value each iteration.  Same tile code and arithmetic as pd_solve.
+
+struct BImg {
+    pd_shape sh;
+    int lc;
+    int64_t off;          // element offset in the packed image arrays
+    size_t apx[PD_MAXL + 1];
+    size_t slots;
+};
+
+struct BLayout {
+    std::vector<BImg> img;
+    int64_t total;        // packed elements
+    size_t zA, zB, x, s, flag, tab, tab_bytes, total_bytes;
+    int maxfine;
+};
+
+template <typename Args>
+struct Table {
+    std::vector<Args> args;
+    std::vector<int> start{0};
+    size_t off = 0;       // byte offset of args in the table region; start follows
+    void add(const Args &a, int tiles)
+    {
+        args.push_back(a);
+        start.push_back(start.back() + tiles);
+    }
+    int n() const { return (int)args.size(); }
+    int tiles() const { return start.back(); }
+};
+
+size_t table_bytes_upper(int batch, int maxl)
+{
+    // per image at most: 2 coarse SYN + 2 coarse PROX + init coarse; per level
+    // synth (iteration and final) + analysis (plain, prox) + blur, all < 1 KiB
+    return align_up((size_t)batch * (8 + 4 * (size_t)maxl) * 1024 + 64 * 1024);
+}
+
+template <typename T>
+BLayout batched_layout(int batch, const pd_image_desc *d)
+{
+    BLayout L;
+    L.total = 0;
+    L.maxfine = 0;
+    int maxl = 0;
+    for (int b = 0; b < batch; ++b) {
+        BImg im;
+        im.sh = d[b].shape;
+        im.lc = coarse_level<T>(&im.sh, 0);
+        im.off = L.total;
+        L.total += (int64_t)im.sh.n1 * im.sh.n2 * im.sh.channels;
+        L.maxfine = std::max(L.maxfine, im.lc - 1);
+        maxl = std::max(maxl, (int)im.sh.levels);
+        L.img.push_back(im);
+    }
+    const size_t es = sizeof(T), plane = align_up(es * L.total);
+    size_t off = 0;
+    L.zA = off;
+    off += plane;
+    L.zB = off;
+    off += plane;
+    L.x = off;
+    off += plane;
+    L.s = off;
+    off += plane;
+    for (auto &im : L.img) {
+        for (int j = 0; j <= PD_MAXL; ++j) im.apx[j] = 0;
+        for (int j = 1; j < im.sh.levels; ++j) {
+            im.apx[j] = off;
+            off = align_up(off + es * im.sh.channels * (size_t)(im.sh.n1 >> j) * (im.sh.n2 >> j));
+        }
+        im.slots = off;
+        off = align_up(off + 3 * PD_NSLOT * sizeof(double));
+    }
+    L.flag = off;
+    off = align_up(off + 256);
+    L.tab = off;
+    L.tab_bytes = table_bytes_upper(batch, maxl);
+    off += L.tab_bytes;
+    L.total_bytes = off;
+    return L;
+}
+
+template <typename T>
+int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav, int iters, const T *f0p,
+                       T *fop, double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    BLayout L = batched_layout<T>(batch, d);
+    if (ws_bytes < L.total_bytes) return PD_ERR_WORKSPACE;
+    char *ws = (char *)workspace;
+    const Filt<T> f = make_filt<T>(wav);
+    T *zA = (T *)(ws + L.zA), *zB = (T *)(ws + L.zB), *X = (T *)(ws + L.x), *S = (T *)(ws + L.s);
+    int *flag = (int *)(ws + L.flag);
+
+    // tables: init (plain analysis, coarse plain), iteration (coarse syn, synth,
+    // blur, analysis, coarse prox[+syn]), final synthesis into f_out
+    const int MF = L.maxfine;
+    std::vector<Table<AnalysisArgs<T>>> t_init_ana(MF + 1), t_ana(MF + 1);
+    std::vector<Table<SynthArgs<T>>> t_syn(MF + 1), t_fsyn(MF + 1);
+    Table<CoarseArgs<T>> t_init_co, t_cosyn, t_fcosyn, t_coprox_syn, t_coprox;
+    Table<BlurArgs<T>> t_blur;
+    std::vector<double *> slots_tab(batch), stats_tab(batch);
+    std::vector<int> fin_flags(batch, 0);
+    const T *f_zfinal = (iters % 2 == 0) ? zA : zB;  // z(K) after K in-place iterations
+
+    for (int b = 0; b < batch; ++b) {
+        const BImg &im = L.img[b];
+        const pd_shape *sh = &im.sh;
+        Ctx<T> c;
+        c.sh = sh;
+        c.f = f;
+        c.ws = ws;
+        c.st = st;
+        c.lc = im.lc;
+        c.lay.x = c.lay.s = c.lay.flag = c.lay.slots = 0;
+        for (int j = 0; j <= PD_MAXL; ++j) c.lay.apx[j] = im.apx[j];
+        const int64_t N = (int64_t)sh->n1 * sh->n2;
+        const int n1 = sh->n1, n2 = sh->n2, Lv = sh->levels, C = sh->channels;
+        double *slots = stats ? (double *)(ws + im.slots) : nullptr;
+        double *stb = stats ? stats + (size_t)b * iters * 3 : nullptr;
+        slots_tab[b] = slots;
+        stats_tab[b] = stb;
+        pd_weights w{d[b].level_w, nullptr, 0};
+        T *zAb = zA + im.off, *zBb = zB + im.off, *Xb = X + im.off, *Sb = S + im.off;
+        const T *F0b = f0p + im.off;
+        T *FOb = fop + im.off;
+        ProxArgs<T> pp = prox_args<T>(c, zAb, zBb, zBb, T(0), (T)d[b].tau, &w, stb);
+        pp.slots = slots;
+        pp.flag = flag;
+        ProxArgs<T> pplain = prox_args<T>(c, nullptr, nullptr, zAb, T(0), T(0), nullptr, nullptr);
+        pplain.flag = flag;
+        const bool coarse = im.lc <= Lv;
+        const bool cofin = coarse && C == 1;
+        fin_flags[b] = stats && !cofin ? 1 : 0;
+        // fine levels
+        for (int lev = 1; lev <= im.lc - 1; ++lev) {
+            AnalysisArgs<T> a;
+            a.f = f;
+            a.in = lev == 1 ? Sb : c.apx(lev - 1);
+            a.in_pitch = lev == 1 ? n1 : (n1 >> (lev - 1));
+            a.in_plane = lev == 1 ? N : (int64_t)(n1 >> (lev - 1)) * (n2 >> (lev - 1));
+            a.M1c = n1 >> lev;
+            a.M2c = n2 >> lev;
+            a.last = lev == Lv;
+            a.apx_out = lev < Lv ? c.apx(lev) : nullptr;
+            a.apx_plane = (int64_t)(n1 >> lev) * (n2 >> lev);
+            a.band_detail = Lv + 1 - lev;
+            tiles_analysis(a.M1c, a.M2c, &a.tx, &a.ty);
+            const int tiles = a.tx * a.ty * C;
+            a.mode = MODE_PROX;
+            a.p = pp;
+            t_ana[lev].add(a, tiles);
+            a.mode = MODE_PLAIN;
+            a.p = pplain;
+            if (lev == 1) a.in = F0b;
+            t_init_ana[lev].add(a, tiles);
+
+            SynthArgs<T> sa;
+            sa.f = f;
+            sa.zc = zAb;
+            sa.zp = zBb;
+            sa.beta = T(0);
+            sa.plane = N;
+            sa.pitch = n1;
+            sa.apx = lev == Lv ? nullptr : c.apx(lev);
+            sa.apx_plane = (int64_t)(n1 >> lev) * (n2 >> lev);
+            sa.out = lev == 1 ? Xb : c.apx(lev - 1);
+            sa.out_pitch = lev == 1 ? n1 : (n1 >> (lev - 1));
+            sa.out_plane = lev == 1 ? N : (int64_t)(n1 >> (lev - 1)) * (n2 >> (lev - 1));
+            sa.M1c = n1 >> lev;
+            sa.M2c = n2 >> lev;
+            tiles_synth(sa.M1c, sa.M2c, &sa.tx, &sa.ty);
+            t_syn[lev].add(sa, sa.tx * sa.ty * C);
+            sa.zc = sa.zp = f_zfinal + im.off;
+            if (lev == 1) sa.out = FOb;
+            t_fsyn[lev].add(sa, sa.tx * sa.ty * C);
+        }
+        BlurArgs<T> ba;
+        ba.x = Xb;
+        ba.f0 = F0b;
+        ba.s = Sb;
+        ba.taps = (const T *)d[b].op.taps;
+        ba.n1 = n1;
+        ba.n2 = n2;
+        ba.C = C;
+        ba.R = d[b].op.radius;
+        ba.plane = N;
+        ba.slots = slots;
+        tiles_blur(n1, n2, &ba.tx, &ba.ty);
+        t_blur.add(ba, ba.tx * ba.ty * C);
+        if (coarse) {
+            CoarseArgs<T> ca;
+            ca.f = f;
+            ca.m1 = n1 >> (im.lc - 1);
+            ca.m2 = n2 >> (im.lc - 1);
+            ca.nlev = Lv - im.lc + 1;
+            ca.band_top = Lv + 1 - im.lc;
+            ca.apx_in = im.lc == 1 ? Sb : c.apx(im.lc - 1);
+            ca.apx_in_plane = im.lc == 1 ? N : (int64_t)ca.m1 * ca.m2;
+            ca.apx_out = im.lc == 1 ? Xb : c.apx(im.lc - 1);
+            ca.apx_out_plane = ca.apx_in_plane;
+            ca.beta_next = T(0);
+            ca.finalize = cofin ? 1 : 0;
+            ca.ops = COARSE_ANA | COARSE_PROX | COARSE_SYN;
+            ca.p = pp;
+            t_coprox_syn.add(ca, C);
+            ca.ops = COARSE_ANA | COARSE_PROX;
+            t_coprox.add(ca, C);
+            ca.ops = COARSE_SYN;
+            ca.finalize = 0;
+            t_cosyn.add(ca, C);
+            ca.p.zc = ca.p.zp = f_zfinal + im.off;
+            if (im.lc == 1) ca.apx_out = FOb;
+            t_fcosyn.add(ca, C);
+            ca.ops = COARSE_ANA;
+            ca.p = pplain;
+            if (im.lc == 1) ca.apx_in = F0b;
+            ca.apx_out = nullptr;
+            t_init_co.add(ca, C);
+        }
+    }
+
+    // upload every table into the workspace table region
+    std::vector<char> host;
+    auto place = [&](auto &t) {
+        if (t.n() == 0) return;
+        using A = typename std::decay_t<decltype(t.args)>::value_type;
+        size_t o = align_up(host.size());
+        t.off = o;
+        size_t sa = t.args.size() * sizeof(A);
+        size_t ss = t.start.size() * sizeof(int);
+        host.resize(align_up(o + sa) + ss);
+        std::memcpy(host.data() + o, t.args.data(), sa);
+        std::memcpy(host.data() + align_up(o + sa), t.start.data(), ss);
+    };
+    for (auto &t : t_init_ana) place(t);
+    for (auto &t : t_ana) place(t);
+    for (auto &t : t_syn) place(t);
+    for (auto &t : t_fsyn) place(t);
+    place(t_init_co);
+    place(t_cosyn);
+    place(t_fcosyn);
+    place(t_coprox_syn);
+    place(t_coprox);
+    place(t_blur);
+    size_t o_sl = align_up(host.size());
+    host.resize(o_sl + batch * sizeof(double *));
+    std::memcpy(host.data() + o_sl, slots_tab.data(), batch * sizeof(double *));
+    size_t o_st = align_up(host.size());
+    host.resize(o_st + batch * sizeof(double *));
+    std::memcpy(host.data() + o_st, stats_tab.data(), batch * sizeof(double *));
+    size_t o_fl = align_up(host.size());
+    host.resize(o_fl + batch * sizeof(int));
+    std::memcpy(host.data() + o_fl, fin_flags.data(), batch * sizeof(int));
+    if (host.size() > L.tab_bytes) return PD_ERR_UNSUPPORTED;
+    char *tab = ws + L.tab;
+    PD_TRY_HIP(hipMemcpyAsync(tab, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    // the pageable source must stay valid until the copy has been consumed
+    PD_TRY_HIP(hipStreamSynchronize(st));
+
+    auto targs = [&](auto &t) {
+        using A = typename std::decay_t<decltype(t.args)>::value_type;
+        return (const A *)(tab + t.off);
+    };
+    auto tstart = [&](auto &t) {
+        using A = typename std::decay_t<decltype(t.args)>::value_type;
+        return (const int *)(tab + align_up(t.off + t.args.size() * sizeof(A)));
+    };
+    size_t colds = 0;
+    for (auto &im : L.img)
+        if (im.lc <= im.sh.levels)
+            colds = std::max(colds, coarse_lds_bytes<T>(im.sh.n1 >> (im.lc - 1), im.sh.n2 >> (im.lc - 1), 1));
+
+    auto run_coarse = [&](Table<CoarseArgs<T>> &t, Dyn<T> dy) -> int {
+        if (t.n() == 0) return PD_OK;
+        PD_TRY_HIP(timed(PD_K_COARSE, 0, st, [&] {
+            return launch_coarse_b<T>(targs(t), tstart(t), t.n(), t.tiles(), colds, dy, st);
+        }));
+        return PD_OK;
+    };
+    auto run_synth = [&](std::vector<Table<SynthArgs<T>>> &ts, Dyn<T> dy) -> int {
+        for (int lev = MF; lev >= 1; --lev) {
+            auto &t = ts[lev];
+            if (t.n() == 0) continue;
+            PD_TRY_HIP(timed(PD_K_SYNTH, lev, st,
+                             [&] { return launch_synth_b<T>(targs(t), tstart(t), t.n(), t.tiles(), dy, st); }));
+        }
+        return PD_OK;
+    };
+    auto run_ana = [&](std::vector<Table<AnalysisArgs<T>>> &ts, Dyn<T> dy) -> int {
+        for (int lev = 1; lev <= MF; ++lev) {
+            auto &t = ts[lev];
+            if (t.n() == 0) continue;
+            PD_TRY_HIP(timed(PD_K_ANALYSIS, lev, st, [&] {
+                return launch_analysis_b<T>(targs(t), tstart(t), t.n(), t.tiles(), false, dy, st);
+            }));
+        }
+        return PD_OK;
+    };
+
+    int rc;
+    Dyn<T> d0{T(0), T(0), 0, 0};
+    // init: z(0) = Psi^* f0 into zA, copied to zB
+    if ((rc = run_ana(t_init_ana, d0)) != PD_OK) return rc;
+    if ((rc = run_coarse(t_init_co, d0)) != PD_OK) return rc;
+    PD_TRY_HIP(launch_copy<T>(zA, zB, L.total, st));
+    if (stats)
+        for (int b = 0; b < batch; ++b) PD_TRY_HIP(launch_stats_finalize(slots_tab[b], nullptr, 1, st));
+    const bool any_fin = std::any_of(fin_flags.begin(), fin_flags.end(), [](int v) { return v != 0; });
+    for (int it = 0; it < iters; ++it) {
+        const int i = 1 + it;
+        Dyn<T> dy{(T)beta_y(i), (T)beta_y(i + 1), it & 1, it};
+        if (it == 0 && (rc = run_coarse(t_cosyn, dy)) != PD_OK) return rc;
+        if ((rc = run_synth(t_syn, dy)) != PD_OK) return rc;
+        PD_TRY_HIP(timed(PD_K_BLUR, 0, st, [&] {
+            return launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), st);
+        }));
+        if ((rc = run_ana(t_ana, dy)) != PD_OK) return rc;
+        if ((rc = run_coarse(it == iters - 1 ? t_coprox : t_coprox_syn, dy)) != PD_OK) return rc;
+        if (any_fin)
+            PD_TRY_HIP(launch_stats_finalize_b((double *const *)(tab + o_sl), (double *const *)(tab + o_st),
+                                               (const int *)(tab + o_fl), batch, it, st));
+    }
+    // f = Psi z(K)
+    Dyn<T> dz{T(0), T(0), 0, 0};
+    if ((rc = run_coarse(t_fcosyn, dz)) != PD_OK) return rc;
+    if ((rc = run_synth(t_fsyn, dz)) != PD_OK) return rc;
+    return PD_OK;
+}
+
 }  // namespace
+
+extern "C" size_t pd_batched_workspace_size(int32_t batch, const pd_image_desc *descs, int32_t dtype)
+{
+    if (batch < 1 || !descs || check_dtype(dtype) != PD_OK) return 0;
+    for (int b = 0; b < batch; ++b)
+        if (check_shape(&descs[b].shape) != PD_OK) return 0;
+    return dtype == PD_F64 ? batched_layout<double>(batch, descs).total_bytes
+                           : batched_layout<float>(batch, descs).total_bytes;
+}
+
+extern "C" int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32_t dtype,
+                                const pd_wavelet *wav, int32_t iters, const void *f0_packed,
+                                void *f_out_packed, double *stats, void *workspace,
+                                size_t ws_bytes, void *stream)
+{
+    int rc;
+    if (batch < 1 || !descs || !f0_packed || !f_out_packed || !workspace || iters < 0) return PD_ERR_ARG;
+    if ((rc = check_dtype(dtype)) || (rc = check_wavelet(wav))) return rc;
+    for (int b = 0; b < batch; ++b) {
+        const pd_image_desc &d = descs[b];
+        if ((rc = check_shape(&d.shape)) || (rc = check_op(&d.op, &d.shape))) return rc;
+        if (d.op.kind != PD_OP_ROWBLUR) return PD_ERR_UNSUPPORTED;
+        if (!d.level_w || d.offset < 0) return PD_ERR_ARG;
+        for (int k = 0; k <= d.shape.levels; ++k)
+            if (!std::isfinite(d.level_w[k]) || d.level_w[k] < 0.0) return PD_ERR_ARG;
+        if (!std::isfinite(d.tau) || d.tau <= 0.0) return PD_ERR_TAU;
+    }
+    // images must be packed back to back in order (offset = running sum)
+    int64_t run = 0;
+    for (int b = 0; b < batch; ++b) {
+        if (descs[b].offset != run) return PD_ERR_ARG;
+        run += (int64_t)descs[b].shape.n1 * descs[b].shape.n2 * descs[b].shape.channels;
+    }
+    if (ws_bytes < pd_batched_workspace_size(batch, descs, dtype)) return PD_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == PD_F32)
+        return solve_batched_impl<float>(batch, descs, wav, iters, (const float *)f0_packed, (float *)f_out_packed,
+                                         stats, workspace, ws_bytes, st);
+    return solve_batched_impl<double>(batch, descs, wav, iters, (const double *)f0_packed,
+                                      (double *)f_out_packed, stats, workspace, ws_bytes, st);
+}
+
+
+extern "C" int pd_timing_enable(int32_t enable)
+{
+    clear_timing();
+    g_timing = enable != 0;
+    return PD_OK;
+}
+
+extern "C" int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *launches,
+                              double *total_ms, int32_t *rows)
+{
+    if (!rows || max_rows < 0) return PD_ERR_ARG;
+    std::map<std::pair<int, int>, std::pair<int64_t, double>> agg;
+    for (auto &t : g_launches) {
+        if (hipEventSynchronize(t.b) != hipSuccess) return PD_ERR_HIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) return PD_ERR_HIP;
+        auto &e = agg[{t.kclass, t.level}];
+        e.first += 1;
+        e.second += ms;
+    }
+    int r = 0;
+    for (auto &kv : agg) {
+        if (r < max_rows) {
+            if (kclass) kclass[r] = kv.first.first;
+            if (level) level[r] = kv.first.second;
+            if (launches) launches[r] = kv.second.first;
+            if (total_ms) total_ms[r] = kv.second.second;
+        }
+        ++r;
+    }
+    *rows = r;
+    return PD_OK;
+}
 
 extern "C" size_t pd_workspace_size(const pd_shape *shape, int32_t dtype)
 {
@@ -307,16 +862,10 @@ extern "C" int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wa
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
-        Ctx<T> c;
-        c.sh = shape;
-        c.f = make_filt<T>(wav);
-        c.ws = (char *)workspace;
-        c.lay = layout(shape, sizeof(T));
-        c.st = st;
+        Ctx<T> c = make_ctx<T>(shape, wav, workspace, st, 0);
         if (ws_bytes < c.lay.total) return PD_ERR_WORKSPACE;
         if (inverse) return synth_chain<T>(c, (const T *)in, (const T *)in, T(0), (T *)out);
-        return analysis_chain<T>(c, (const T *)in, MODE_PLAIN, nullptr, nullptr, (T *)out, T(0),
-                                 T(0), nullptr, nullptr);
+        return analysis_plain<T>(c, (const T *)in, (T *)out);
     };
     return dtype == PD_F32 ? run(float(0)) : run(double(0));
 }
@@ -346,69 +895,11 @@ extern "C" int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operat
         a.C = shape->channels;
         a.R = op->radius;
         a.plane = (int64_t)shape->n1 * shape->n2;
-        a.stats = nullptr;
+        a.slots = nullptr;
         PD_TRY_HIP(launch_blur_single<T>(a, transpose, st));
         return PD_OK;
     };
     return dtype == PD_F32 ? run(float(0)) : run(double(0));
-}
-
-// ---------------------------------------------------------------- batched --
-extern "C" size_t pd_batched_workspace_size(int32_t batch, const pd_image_desc *descs, int32_t dtype)
-{
-    if (batch < 1 || !descs || check_dtype(dtype) != PD_OK) return 0;
-    size_t mx = 0;
-    for (int b = 0; b < batch; ++b) {
-        if (check_shape(&descs[b].shape) != PD_OK) return 0;
-        size_t es = dtype == PD_F64 ? 8 : 4;
-        size_t need = layout(&descs[b].shape, es).total +
-                      align_up(es * descs[b].shape.channels * (size_t)descs[b].shape.n1 * descs[b].shape.n2);
-        mx = need > mx ? need : mx;
-    }
-    return mx;
-}
-
-extern "C" int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32_t dtype,
-                                const pd_wavelet *wav, int32_t iters, const void *f0_packed,
-                                void *f_out_packed, double *stats, void *workspace,
-                                size_t ws_bytes, void *stream)
-{
-    int rc;
-    if (batch < 1 || !descs || !f0_packed || !f_out_packed || !workspace || iters < 0) return PD_ERR_ARG;
-    if ((rc = check_dtype(dtype)) || (rc = check_wavelet(wav))) return rc;
-    for (int b = 0; b < batch; ++b) {
-        const pd_image_desc &d = descs[b];
-        if ((rc = check_shape(&d.shape)) || (rc = check_op(&d.op, &d.shape))) return rc;
-        if (!d.level_w || d.offset < 0) return PD_ERR_ARG;
-        if (!std::isfinite(d.tau) || d.tau <= 0.0) return PD_ERR_TAU;
-    }
-    if (ws_bytes < pd_batched_workspace_size(batch, descs, dtype)) return PD_ERR_WORKSPACE;
-    // per-image loop over the single-image path: z(i-1) lives in f_out, z(i-2) in the workspace tail
-    const size_t es = dtype == PD_F64 ? 8 : 4;
-    for (int b = 0; b < batch; ++b) {
-        const pd_image_desc &d = descs[b];
-        const size_t lay = layout(&d.shape, es).total;
-        char *zprev = (char *)workspace + lay;
-        char *zc = (char *)f_out_packed + d.offset * es;
-        const char *f0 = (const char *)f0_packed + d.offset * es;
-        pd_weights w{d.level_w, nullptr, 0};
-        pd_params p{d.tau, iters, 0, 0};
-        double *sb = stats ? stats + (size_t)b * iters * 3 : nullptr;
-        rc = pd_solve(&d.shape, dtype, &d.op, wav, &w, &p, f0, zc, zprev, 1, nullptr, sb,
-                      workspace, lay, stream);
-        if (rc) return rc;
-        // f = Psi z in place via the x buffer
-        Layout l = layout(&d.shape, es);
-        char *x = (char *)workspace + l.x;
-        rc = pd_fwt(&d.shape, dtype, wav, 1, zc, x, workspace, lay, stream);
-        if (rc) return rc;
-        const int64_t NC = (int64_t)d.shape.n1 * d.shape.n2 * d.shape.channels;
-        if (dtype == PD_F32)
-            PD_TRY_HIP(launch_copy<float>((const float *)x, (float *)zc, NC, (hipStream_t)stream));
-        else
-            PD_TRY_HIP(launch_copy<double>((const double *)x, (double *)zc, NC, (hipStream_t)stream));
-    }
-    return PD_OK;
 }
 
 // --------------------------------------------------------------- backward --

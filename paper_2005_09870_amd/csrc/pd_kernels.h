@@ -8,6 +8,7 @@
 #define PD_MAXC 4
 #define PD_MAXL 16
 #define PD_MAX_RADIUS 9
+#define PD_NSLOT 256  // partial-sum slots per statistic (spreads FP64 atomics)
 
 namespace pd {
 
@@ -37,13 +38,31 @@ struct SynthArgs {
     int out_pitch;
     int64_t out_plane;
     int M1c, M2c;
+    int tx, ty;             // tiles along x1, x2 (batched launches)
 };
 
 enum { MODE_PLAIN = 0, MODE_PROX = 1 };
 
-// One analysis level: fine input M1 x M2 -> four coarse M1c x M2c bands.
-// MODE_PLAIN stores the detail bands (and, if last, the approximation band)
-// of the input in zn.  MODE_PROX treats them as the gradient g and stores
+// Prox / weight parameters shared by the analysis and coarse kernels.
+template <typename T>
+struct ProxArgs {
+    const T *zc, *zp;
+    T *zn;
+    T beta, tau;
+    int64_t plane;
+    int pitch;
+    const T *wmap;          // per-coefficient weights or nullptr
+    T wlev[PD_MAXL + 1];    // per-band weights
+    int joint, C;
+    double *slots;          // [3][PD_NSLOT] partial sums (nullptr: no statistics):
+                            // 1/2||r||^2, sum w|y|, sum (z-y)^2
+    double *stats;          // the iteration's 3 doubles (written by the finaliser)
+    int *flag;              // set to 1 if a prox argument is not finite
+};
+
+// One analysis level: fine input 2*M1c x 2*M2c -> four coarse M1c x M2c
+// bands.  MODE_PLAIN stores the detail bands (and, if last, the approximation
+// band) in zn.  MODE_PROX treats them as the gradient g and stores
 // z = Prox(y - tau g) in zn with y = zc + beta (zc - zp).  If !last the
 // approximation band goes to apx_out (dense, stride apx_plane).
 template <typename T>
@@ -57,17 +76,30 @@ struct AnalysisArgs {
     T *apx_out;
     int64_t apx_plane;
     int mode;
-    const T *zc, *zp;
-    T *zn;
-    T beta, tau;
-    int64_t plane;
-    int pitch;
-    const T *wmap;          // per-coefficient weights or nullptr
-    T wlev[PD_MAXL + 1];    // per-band weights
     int band_detail;        // band index k of this level's detail bands
-    int joint, C;
-    double *stats;          // [sum w|y|, sum (z-y)^2] at stats+1, stats+2
-    int *flag;              // set to 1 if a prox argument is not finite
+    int tx, ty;             // tiles along x1, x2 (batched launches)
+    ProxArgs<T> p;
+};
+
+// All levels lc..L in one workgroup per channel (per image in joint mode):
+// the approximation of level lc-1 (m1 x m2, dense) is analysed, the prox and
+// momentum are applied to the coarse block [0,m2) x [0,m1) of the Mallat
+// plane, and/or the block is synthesised back to a level lc-1 approximation.
+enum { COARSE_ANA = 1, COARSE_PROX = 2, COARSE_SYN = 4 };
+template <typename T>
+struct CoarseArgs {
+    Filt<T> f;
+    int ops;                // COARSE_* bits
+    int m1, m2;             // size of the level lc-1 approximation
+    int nlev;               // number of levels in the block (L - lc + 1)
+    int band_top;           // band index k of the finest level in the block (L+1-lc)
+    const T *apx_in;        // analysis input (dense m2 x m1 per channel)
+    int64_t apx_in_plane;
+    T *apx_out;             // synthesis output (dense m2 x m1 per channel)
+    int64_t apx_out_plane;
+    T beta_next;            // momentum of the next iteration's y (COARSE_PROX|COARSE_SYN)
+    int finalize;           // this workgroup is the image's only one: finalise statistics
+    ProxArgs<T> p;          // in PLAIN analysis (ops == ANA) zn receives coefficients
 };
 
 // Fused r = H x - f0, s = H^T r (or a single pass for the building block).
@@ -78,13 +110,41 @@ struct BlurArgs {
     const T *taps;
     int n1, n2, C, R;
     int64_t plane;
-    double *stats;          // 1/2 ||r||^2 at stats[0]
+    double *slots;          // [3][PD_NSLOT] partial sums; 1/2 ||r||^2 goes to row 0
+    int tx, ty;             // tiles along x1, x2 (batched launches)
+};
+
+// Per-iteration values of a lock-step batched launch.
+template <typename T>
+struct Dyn {
+    T beta, beta_next;      // momentum of y(i) and of y(i+1)
+    int parity;             // 1: the table's zc/zp are swapped this iteration
+    int it;                 // iteration index within the call (statistics row)
 };
 
 template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s);
 template <typename T> hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s);
+template <typename T> size_t coarse_lds_bytes(int m1, int m2, int chans);
 template <typename T> hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s);
 template <typename T> hipError_t launch_blur_single(const BlurArgs<T> &a, int transpose, hipStream_t s);
 template <typename T> hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_synth_b(const SynthArgs<T> *tab, const int *start, int n, int tiles, Dyn<T> d, hipStream_t s);
+template <typename T>
+hipError_t launch_analysis_b(const AnalysisArgs<T> *tab, const int *start, int n, int tiles, bool joint, Dyn<T> d,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, int groups, size_t lds, Dyn<T> d,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, hipStream_t s);
+hipError_t launch_stats_finalize_b(double *const *slots, double *const *stats, const int *flags, int n, int it,
+                                   hipStream_t s);
+void tiles_synth(int M1c, int M2c, int *tx, int *ty);
+void tiles_analysis(int M1c, int M2c, int *tx, int *ty);
+void tiles_blur(int n1, int n2, int *tx, int *ty);
+// stats[q] += sum of slots[q][*], slots zeroed (q = 0..2); zero_only: just zero
+hipError_t launch_stats_finalize(double *slots, double *stats, int zero_only, hipStream_t s);
 
 }  // namespace pd

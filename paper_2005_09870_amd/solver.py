@@ -231,3 +231,25 @@ def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, tau
     C.check(rc, "pd_solve_batched")
     outs = [fo[o:o + n].view_as(t) for o, n, t in zip(offs, sizes, f0s)]
     return outs, st
+
+
+# ------------------------------------------------------------- diagnostics ---
+def pd_timing_enable(enable: bool = True) -> None:
+    C.check(C.load().pd_timing_enable(1 if enable else 0), "pd_timing_enable")
+
+
+def pd_timing_read() -> list[dict]:
+    """Per (kernel class, level): launches and total milliseconds, measured by
+    HIP events the library recorded on the launch stream."""
+    L = C.load()
+    rows = ctypes.c_int32()
+    C.check(L.pd_timing_read(0, None, None, None, None, ctypes.byref(rows)), "pd_timing_read")
+    n = rows.value
+    kc = (ctypes.c_int32 * max(n, 1))()
+    lv = (ctypes.c_int32 * max(n, 1))()
+    la = (ctypes.c_int64 * max(n, 1))()
+    ms = (ctypes.c_double * max(n, 1))()
+    C.check(L.pd_timing_read(n, kc, lv, la, ms, ctypes.byref(rows)), "pd_timing_read")
+    return [{"kernel": C.KCLASS_NAMES.get(kc[i], str(kc[i])), "kclass": kc[i], "level": lv[i],
+             "launches": la[i], "total_ms": ms[i], "avg_us": 1e3 * ms[i] / max(la[i], 1)}
+            for i in range(n)]
