@@ -6,7 +6,10 @@ include/pd.h); this package only marshals torch device tensors into it.
 """
 from ._lib import PDError, load  # noqa: F401
 from .solver import (  # noqa: F401
+    FistaSolve,
     Operator,
+    pd_backward,
+    solve_autograd,
     lipschitz,
     pd_apply_op,
     pd_fwt,

@@ -109,7 +109,7 @@ Layout layout(const pd_shape *s, size_t es)
     l.flag = off;
     off = align_up(off + 256);
     l.slots = off;
-    off = align_up(off + 3 * PD_NSLOT * sizeof(double));
+    off = align_up(off + (size_t)PD_RING * 3 * PD_NSLOT * sizeof(double));
     l.total = off;
     return l;
 }
@@ -169,7 +169,8 @@ struct Ctx {
     T *x() const { return (T *)(ws + lay.x); }
     T *s() const { return (T *)(ws + lay.s); }
     int *flag() const { return (int *)(ws + lay.flag); }
-    double *slots() const { return (double *)(ws + lay.slots); }
+    double *ring() const { return (double *)(ws + lay.slots); }
+    double *slots(int it) const { return ring() + (size_t)(it % PD_RING) * 3 * PD_NSLOT; }
 };
 
 // First level lc such that the level lc-1 approximation fits the coarse
@@ -189,7 +190,7 @@ int coarse_level(const pd_shape *sh, int joint)
 
 template <typename T>
 ProxArgs<T> prox_args(const Ctx<T> &c, const T *zc, const T *zp, T *zn, T beta, T tau,
-                      const pd_weights *w, double *stats)
+                      const pd_weights *w, double *slots)
 {
     ProxArgs<T> p;
     p.zc = zc;
@@ -209,8 +210,7 @@ ProxArgs<T> prox_args(const Ctx<T> &c, const T *zc, const T *zp, T *zn, T beta, 
         p.joint = w->joint ? 1 : 0;
     }
     p.C = c.sh->channels;
-    p.slots = stats ? c.slots() : nullptr;
-    p.stats = stats;
+    p.slots = slots;
     p.flag = c.flag();
     return p;
 }
@@ -236,7 +236,6 @@ int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T>
     a.beta_next = beta_next;
     a.p = p;
     const int groups = p.joint ? 1 : c.sh->channels;
-    a.finalize = groups == 1 ? 1 : 0;
     PD_TRY_HIP(timed(PD_K_COARSE, lc, c.st, [&] { return launch_coarse<T>(a, groups, c.st); }));
     return PD_OK;
 }
@@ -316,7 +315,8 @@ int analysis_plain(const Ctx<T> &c, const T *in, T *out)
 }
 
 template <typename T>
-int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T *s, double *stats)
+int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T *s, double *slots,
+              T *racc = nullptr, T rscale = T(0))
 {
     BlurArgs<T> a;
     a.x = x;
@@ -328,7 +328,9 @@ int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T
     a.C = c.sh->channels;
     a.R = op->radius;
     a.plane = c.N();
-    a.slots = stats ? c.slots() : nullptr;
+    a.slots = slots;
+    a.racc = racc;
+    a.rscale = rscale;
     PD_TRY_HIP(timed(PD_K_BLUR, 0, c.st, [&] { return launch_blur<T>(a, op->kind == PD_OP_IDENTITY, c.st); }));
     return PD_OK;
 }
@@ -349,31 +351,26 @@ Ctx<T> make_ctx(const pd_shape *sh, const pd_wavelet *wav, void *workspace, hipS
 // Momentum of y(i) = z(i-1) + b (z(i-1) - z(i-2)):  b_{i-1} = (i-2)/(i+1), 0 for i = 1.
 inline double beta_y(int i) { return i >= 2 ? (double)(i - 2) / (double)(i + 1) : 0.0; }
 
+// Iterations i = i_first .. i_first+count-1 of the recursion from the state
+// (zc, zp) = (z(i_first-1), z(i_first-2)); on return the pointers hold
+// (z(last), z(last-1)).  z(i) is written in place of z(i-2).  stats (nullable)
+// receives 3 doubles per iteration; seg (nullable) receives a copy of every
+// z(i) (count planes), for the reverse sweep.
 template <typename T>
-int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
-               const pd_params *prm, const T *f0, T *z_cur, T *z_prev, int init, T *f_out,
-               double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
+int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *&zc, T *&zp,
+            int i_first, int count, double *stats, T *seg)
 {
-    Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, w->joint);
-    if (ws_bytes < c.lay.total) return PD_ERR_WORKSPACE;
-    const int64_t NC = c.N() * sh->channels;
+    const pd_shape *sh = c.sh;
+    const hipStream_t st = c.st;
     const bool coarse = c.lc <= sh->levels;
+    const int64_t NC = c.N() * sh->channels;
     int rc;
-    if (init) {
-        if ((rc = analysis_plain<T>(c, f0, z_cur)) != PD_OK) return rc;
-        PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, z_prev, NC, st); }));
-    }
-    if (prm->check_finite) PD_TRY_HIP(hipMemsetAsync(c.flag(), 0, sizeof(int), st));
-    if (stats) PD_TRY_HIP(launch_stats_finalize(c.slots(), nullptr, 1, st));
-    // the coarse kernel finalises the statistics when it runs as one workgroup
-    const bool coarse_finalises = coarse && (w->joint || sh->channels == 1);
-    T *zc = z_cur, *zp = z_prev;
-    const T tau = (T)prm->tau;
-    for (int it = 0; it < prm->iters; ++it) {
-        const int i = prm->iter_offset + 1 + it;  // global iteration number
+    if (stats && count > 0) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
+    for (int it = 0; it < count; ++it) {
+        const int i = i_first + it;  // global iteration number
         const T beta = (T)beta_y(i);
-        const bool last = it == prm->iters - 1;
-        double *sti = stats ? stats + 3 * (size_t)it : nullptr;
+        const bool last = it == count - 1;
+        double *sti = stats ? c.slots(it) : nullptr;
         // x = Psi y(i); the coarse part was produced by the previous iteration's coarse kernel
         if (it == 0) {
             if ((rc = synth_chain<T>(c, zc, zp, beta, c.x())) != PD_OK) return rc;
@@ -388,12 +385,35 @@ int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav,
             const int ops = COARSE_ANA | COARSE_PROX | (last ? 0 : COARSE_SYN);
             if ((rc = coarse_step<T>(c, ops, c.s(), c.x(), p, (T)beta_y(i + 1))) != PD_OK) return rc;
         }
-        if (stats && !coarse_finalises)
-            PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_stats_finalize(c.slots(), sti, 0, st); }));
+        if (stats && ((it + 1) % PD_RING == 0 || last)) {  // fold the ring into stats
+            const int cnt = (it % PD_RING) + 1, it0 = it + 1 - cnt;
+            PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_stats_finalize(c.ring(), stats, it0, cnt, st); }));
+        }
+        if (seg) PD_TRY_HIP(launch_copy<T>(zp, seg + (int64_t)it * NC, NC, st));
         T *t = zc;
         zc = zp;
         zp = t;
     }
+    return PD_OK;
+}
+
+template <typename T>
+int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
+               const pd_params *prm, const T *f0, T *z_cur, T *z_prev, int init, T *f_out,
+               double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
+{
+    Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, w->joint);
+    if (ws_bytes < c.lay.total) return PD_ERR_WORKSPACE;
+    const int64_t NC = c.N() * sh->channels;
+    int rc;
+    if (init) {
+        if ((rc = analysis_plain<T>(c, f0, z_cur)) != PD_OK) return rc;
+        PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, z_prev, NC, st); }));
+    }
+    if (prm->check_finite) PD_TRY_HIP(hipMemsetAsync(c.flag(), 0, sizeof(int), st));
+    T *zc = z_cur, *zp = z_prev;
+    if ((rc = iterate<T>(c, op, w, (T)prm->tau, f0, zc, zp, prm->iter_offset + 1, prm->iters, stats, nullptr)) != PD_OK)
+        return rc;
     if (zc != z_cur) {  // odd number of iterations: swap the two planes
         T *tmp = c.x();
         PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, tmp, NC, st); }));
@@ -489,7 +509,7 @@ BLayout batched_layout(int batch, const pd_image_desc *d)
             off = align_up(off + es * im.sh.channels * (size_t)(im.sh.n1 >> j) * (im.sh.n2 >> j));
         }
         im.slots = off;
-        off = align_up(off + 3 * PD_NSLOT * sizeof(double));
+        off = align_up(off + (size_t)PD_RING * 3 * PD_NSLOT * sizeof(double));
     }
     L.flag = off;
     off = align_up(off + 256);
@@ -519,7 +539,6 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     Table<CoarseArgs<T>> t_init_co, t_cosyn, t_fcosyn, t_coprox_syn, t_coprox;
     Table<BlurArgs<T>> t_blur;
     std::vector<double *> slots_tab(batch), stats_tab(batch);
-    std::vector<int> fin_flags(batch, 0);
     const T *f_zfinal = (iters % 2 == 0) ? zA : zB;  // z(K) after K in-place iterations
 
     for (int b = 0; b < batch; ++b) {
@@ -531,7 +550,8 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         c.ws = ws;
         c.st = st;
         c.lc = im.lc;
-        c.lay.x = c.lay.s = c.lay.flag = c.lay.slots = 0;
+        c.lay.x = c.lay.s = c.lay.flag = 0;
+        c.lay.slots = im.slots;
         for (int j = 0; j <= PD_MAXL; ++j) c.lay.apx[j] = im.apx[j];
         const int64_t N = (int64_t)sh->n1 * sh->n2;
         const int n1 = sh->n1, n2 = sh->n2, Lv = sh->levels, C = sh->channels;
@@ -543,14 +563,11 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         T *zAb = zA + im.off, *zBb = zB + im.off, *Xb = X + im.off, *Sb = S + im.off;
         const T *F0b = f0p + im.off;
         T *FOb = fop + im.off;
-        ProxArgs<T> pp = prox_args<T>(c, zAb, zBb, zBb, T(0), (T)d[b].tau, &w, stb);
-        pp.slots = slots;
+        ProxArgs<T> pp = prox_args<T>(c, zAb, zBb, zBb, T(0), (T)d[b].tau, &w, slots);
         pp.flag = flag;
         ProxArgs<T> pplain = prox_args<T>(c, nullptr, nullptr, zAb, T(0), T(0), nullptr, nullptr);
         pplain.flag = flag;
         const bool coarse = im.lc <= Lv;
-        const bool cofin = coarse && C == 1;
-        fin_flags[b] = stats && !cofin ? 1 : 0;
         // fine levels
         for (int lev = 1; lev <= im.lc - 1; ++lev) {
             AnalysisArgs<T> a;
@@ -605,6 +622,8 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         ba.R = d[b].op.radius;
         ba.plane = N;
         ba.slots = slots;
+        ba.racc = nullptr;
+        ba.rscale = T(0);
         tiles_blur(n1, n2, &ba.tx, &ba.ty);
         t_blur.add(ba, ba.tx * ba.ty * C);
         if (coarse) {
@@ -619,14 +638,12 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
             ca.apx_out = im.lc == 1 ? Xb : c.apx(im.lc - 1);
             ca.apx_out_plane = ca.apx_in_plane;
             ca.beta_next = T(0);
-            ca.finalize = cofin ? 1 : 0;
             ca.ops = COARSE_ANA | COARSE_PROX | COARSE_SYN;
             ca.p = pp;
             t_coprox_syn.add(ca, C);
             ca.ops = COARSE_ANA | COARSE_PROX;
             t_coprox.add(ca, C);
             ca.ops = COARSE_SYN;
-            ca.finalize = 0;
             t_cosyn.add(ca, C);
             ca.p.zc = ca.p.zp = f_zfinal + im.off;
             if (im.lc == 1) ca.apx_out = FOb;
@@ -668,9 +685,6 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     size_t o_st = align_up(host.size());
     host.resize(o_st + batch * sizeof(double *));
     std::memcpy(host.data() + o_st, stats_tab.data(), batch * sizeof(double *));
-    size_t o_fl = align_up(host.size());
-    host.resize(o_fl + batch * sizeof(int));
-    std::memcpy(host.data() + o_fl, fin_flags.data(), batch * sizeof(int));
     if (host.size() > L.tab_bytes) return PD_ERR_UNSUPPORTED;
     char *tab = ws + L.tab;
     PD_TRY_HIP(hipMemcpyAsync(tab, host.data(), host.size(), hipMemcpyHostToDevice, st));
@@ -724,21 +738,23 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     if ((rc = run_coarse(t_init_co, d0)) != PD_OK) return rc;
     PD_TRY_HIP(launch_copy<T>(zA, zB, L.total, st));
     if (stats)
-        for (int b = 0; b < batch; ++b) PD_TRY_HIP(launch_stats_finalize(slots_tab[b], nullptr, 1, st));
-    const bool any_fin = std::any_of(fin_flags.begin(), fin_flags.end(), [](int v) { return v != 0; });
+        for (int b = 0; b < batch; ++b)
+            PD_TRY_HIP(launch_fill<double>(slots_tab[b], 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
     for (int it = 0; it < iters; ++it) {
         const int i = 1 + it;
-        Dyn<T> dy{(T)beta_y(i), (T)beta_y(i + 1), it & 1, it};
+        Dyn<T> dy{(T)beta_y(i), (T)beta_y(i + 1), it & 1, it % PD_RING};
         if (it == 0 && (rc = run_coarse(t_cosyn, dy)) != PD_OK) return rc;
         if ((rc = run_synth(t_syn, dy)) != PD_OK) return rc;
         PD_TRY_HIP(timed(PD_K_BLUR, 0, st, [&] {
-            return launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), st);
+            return launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), it % PD_RING, st);
         }));
         if ((rc = run_ana(t_ana, dy)) != PD_OK) return rc;
         if ((rc = run_coarse(it == iters - 1 ? t_coprox : t_coprox_syn, dy)) != PD_OK) return rc;
-        if (any_fin)
-            PD_TRY_HIP(launch_stats_finalize_b((double *const *)(tab + o_sl), (double *const *)(tab + o_st),
-                                               (const int *)(tab + o_fl), batch, it, st));
+        if (stats && ((it + 1) % PD_RING == 0 || it == iters - 1)) {
+            const int cnt = (it % PD_RING) + 1, it0 = it + 1 - cnt;
+            PD_TRY_HIP(launch_stats_finalize_b((double *const *)(tab + o_sl), (double *const *)(tab + o_st), batch,
+                                               it0, cnt, st));
+        }
     }
     // f = Psi z(K)
     Dyn<T> dz{T(0), T(0), 0, 0};
@@ -896,6 +912,8 @@ extern "C" int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operat
         a.R = op->radius;
         a.plane = (int64_t)shape->n1 * shape->n2;
         a.slots = nullptr;
+        a.racc = nullptr;
+        a.rscale = T(0);
         PD_TRY_HIP(launch_blur_single<T>(a, transpose, st));
         return PD_OK;
     };
@@ -903,19 +921,136 @@ extern "C" int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operat
 }
 
 // --------------------------------------------------------------- backward --
+// Reverse mode of pd_solve (init = Psi^* f0) with segment checkpointing:
+// forward pass storing (z(sC), z(sC-1)) at the start of every segment of C
+// iterations; then, last segment first, the segment's z(i) are recomputed from
+// its checkpoint by the same launch sequence as the forward solve (bitwise the
+// same iterates) and the adjoint recursion is run backwards through it:
+//   zbar(K) = Psi^* fbar
+//   vbar = zbar 1{z(i) != 0};  wbar -= tau zbar sign z(i)
+//   ybar = vbar - tau Psi^* H^T H Psi vbar;  f0bar += tau H Psi vbar
+//   zbar(i-1) = zbarm + (1+b) ybar,  zbarm = -b ybar,  b = (i-2)/(i+1)
+//   f0bar += Psi (ybar(1) + zbarm)                       (adjoint of the init)
+namespace {
+
+struct BwdLayout {
+    Layout fwd;
+    int nseg;
+    size_t zc, zp, ck, seg, zbar, zbarm, vbar, gbar, total;
+};
+
+BwdLayout bwd_layout(const pd_shape *sh, size_t es, int iters, int C)
+{
+    BwdLayout b;
+    b.fwd = layout(sh, es);
+    b.nseg = iters > 0 ? (iters + C - 1) / C : 0;
+    const size_t plane = align_up(es * (size_t)sh->n1 * sh->n2 * sh->channels);
+    size_t off = b.fwd.total;
+    b.zc = off;
+    off += plane;
+    b.zp = off;
+    off += plane;
+    b.ck = off;
+    off += plane * 2 * (size_t)b.nseg;
+    b.seg = off;
+    off += plane * (size_t)(iters > 0 ? std::min(C, iters) : 0);
+    b.zbar = off;
+    off += plane;
+    b.zbarm = off;
+    off += plane;
+    b.vbar = off;
+    off += plane;
+    b.gbar = off;
+    off += plane;
+    b.total = off;
+    return b;
+}
+
+template <typename T>
+int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
+                  const pd_params *prm, const T *f0, const T *gf, T *gf0, T *gw, int C, void *workspace,
+                  size_t ws_bytes, hipStream_t st)
+{
+    const int K = prm->iters;
+    BwdLayout L = bwd_layout(sh, sizeof(T), K, C);
+    if (ws_bytes < L.total) return PD_ERR_WORKSPACE;
+    Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, 0);
+    char *ws = (char *)workspace;
+    const int64_t NC = c.N() * sh->channels;
+    const size_t plane = align_up(sizeof(T) * (size_t)NC);
+    T *zA = (T *)(ws + L.zc), *zB = (T *)(ws + L.zp);
+    T *zbar = (T *)(ws + L.zbar), *zbarm = (T *)(ws + L.zbarm);
+    T *vbar = (T *)(ws + L.vbar), *gbar = (T *)(ws + L.gbar);
+    auto ck = [&](int sidx, int k) { return (T *)(ws + L.ck + plane * (2 * (size_t)sidx + k)); };
+    T *seg = (T *)(ws + L.seg);
+    const T tau = (T)prm->tau;
+    int rc;
+
+    // forward with checkpoints
+    if ((rc = analysis_plain<T>(c, f0, zA)) != PD_OK) return rc;
+    PD_TRY_HIP(launch_copy<T>(zA, zB, NC, st));
+    {
+        T *zc = zA, *zp = zB;
+        for (int sidx = 0; sidx < L.nseg; ++sidx) {
+            PD_TRY_HIP(launch_copy<T>(zc, ck(sidx, 0), NC, st));
+            PD_TRY_HIP(launch_copy<T>(zp, ck(sidx, 1), NC, st));
+            const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
+            if (sidx == L.nseg - 1) break;  // the last segment is recomputed first anyway
+            if ((rc = iterate<T>(c, op, w, tau, f0, zc, zp, i0, cnt, nullptr, nullptr)) != PD_OK) return rc;
+        }
+    }
+    // seeds
+    if ((rc = analysis_plain<T>(c, gf, zbar)) != PD_OK) return rc;  // zbar(K) = Psi^* fbar
+    PD_TRY_HIP(launch_fill<T>(zbarm, T(0), NC, st));
+    if (gf0) PD_TRY_HIP(launch_fill<T>(gf0, T(0), NC, st));
+    if (gw) PD_TRY_HIP(launch_fill<T>(gw, T(0), NC, st));
+
+    for (int sidx = L.nseg - 1; sidx >= 0; --sidx) {
+        const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
+        T *zc = ck(sidx, 0), *zp = ck(sidx, 1);
+        if ((rc = iterate<T>(c, op, w, tau, f0, zc, zp, i0, cnt, nullptr, seg)) != PD_OK) return rc;
+        for (int j = cnt - 1; j >= 0; --j) {
+            const int i = i0 + j;
+            PD_TRY_HIP(launch_rev_mask<T>(zbar, seg + (int64_t)j * NC, vbar, gw, tau, NC, st));
+            if ((rc = synth_chain<T>(c, vbar, vbar, T(0), c.x())) != PD_OK) return rc;         // Psi vbar
+            if ((rc = blur_step<T>(c, op, c.x(), nullptr, c.s(), nullptr, gf0, tau)) != PD_OK) return rc;
+            if ((rc = analysis_plain<T>(c, c.s(), gbar)) != PD_OK) return rc;                   // Psi^* H^T H Psi vbar
+            const T b = (T)beta_y(i);  // b_{i-1}
+            PD_TRY_HIP(launch_rev_combine<T>(vbar, gbar, zbar, zbarm, tau, b, i == 1 ? 1 : 0, NC, st));
+        }
+    }
+    // f0bar += Psi initbar (initbar = zbar after the i = 1 step, or Psi^* fbar when K = 0)
+    if (gf0) {
+        if ((rc = synth_chain<T>(c, zbar, zbar, T(0), c.x())) != PD_OK) return rc;
+        PD_TRY_HIP(launch_add<T>(c.x(), gf0, NC, st));
+    }
+    return PD_OK;
+}
+
+}  // namespace
+
 extern "C" size_t pd_backward_workspace_size(const pd_shape *shape, int32_t dtype, int32_t iters,
                                              int32_t checkpoint_every)
 {
-    (void)shape;
-    (void)dtype;
-    (void)iters;
-    (void)checkpoint_every;
-    return 0;
+    if (check_shape(shape) != PD_OK || check_dtype(dtype) != PD_OK || iters < 0 || checkpoint_every < 1) return 0;
+    return bwd_layout(shape, dtype == PD_F64 ? 8 : 4, iters, checkpoint_every).total;
 }
 
-extern "C" int pd_backward(const pd_shape *, int32_t, const pd_operator *, const pd_wavelet *,
-                           const pd_weights *, const pd_params *, const void *, const void *,
-                           void *, void *, int32_t, void *, size_t, void *)
+extern "C" int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                           const pd_weights *w, const pd_params *prm, const void *f0, const void *grad_f,
+                           void *grad_f0, void *grad_w, int32_t checkpoint_every, void *workspace,
+                           size_t ws_bytes, void *stream)
 {
-    return PD_ERR_UNSUPPORTED;
+    int rc;
+    if ((rc = check_shape(shape)) || (rc = check_dtype(dtype)) || (rc = check_op(op, shape)) ||
+        (rc = check_wavelet(wav)) || (rc = check_weights(w, shape)) || (rc = check_params(prm)))
+        return rc;
+    if (!f0 || !grad_f || !workspace || checkpoint_every < 1) return PD_ERR_ARG;
+    if (w->joint || prm->iter_offset != 0) return PD_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == PD_F32)
+        return backward_impl<float>(shape, op, wav, w, prm, (const float *)f0, (const float *)grad_f,
+                                    (float *)grad_f0, (float *)grad_w, checkpoint_every, workspace, ws_bytes, st);
+    return backward_impl<double>(shape, op, wav, w, prm, (const double *)f0, (const double *)grad_f,
+                                 (double *)grad_f0, (double *)grad_w, checkpoint_every, workspace, ws_bytes, st);
 }

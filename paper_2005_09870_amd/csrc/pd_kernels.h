@@ -8,7 +8,8 @@
 #define PD_MAXC 4
 #define PD_MAXL 16
 #define PD_MAX_RADIUS 9
-#define PD_NSLOT 256  // partial-sum slots per statistic (spreads FP64 atomics)
+#define PD_NSLOT 64   // partial-sum slots per statistic (spreads FP64 atomics)
+#define PD_RING 64    // iterations whose partial sums are kept before a finalise
 
 namespace pd {
 
@@ -54,9 +55,8 @@ struct ProxArgs {
     const T *wmap;          // per-coefficient weights or nullptr
     T wlev[PD_MAXL + 1];    // per-band weights
     int joint, C;
-    double *slots;          // [3][PD_NSLOT] partial sums (nullptr: no statistics):
-                            // 1/2||r||^2, sum w|y|, sum (z-y)^2
-    double *stats;          // the iteration's 3 doubles (written by the finaliser)
+    double *slots;          // this iteration's [3][PD_NSLOT] partial sums (nullptr: no
+                            // statistics): 1/2||r||^2, sum w|y|, sum (z-y)^2
     int *flag;              // set to 1 if a prox argument is not finite
 };
 
@@ -98,7 +98,6 @@ struct CoarseArgs {
     T *apx_out;             // synthesis output (dense m2 x m1 per channel)
     int64_t apx_out_plane;
     T beta_next;            // momentum of the next iteration's y (COARSE_PROX|COARSE_SYN)
-    int finalize;           // this workgroup is the image's only one: finalise statistics
     ProxArgs<T> p;          // in PLAIN analysis (ops == ANA) zn receives coefficients
 };
 
@@ -112,6 +111,8 @@ struct BlurArgs {
     int64_t plane;
     double *slots;          // [3][PD_NSLOT] partial sums; 1/2 ||r||^2 goes to row 0
     int tx, ty;             // tiles along x1, x2 (batched launches)
+    T *racc;                // reverse mode: racc += rscale * r (nullptr: off); f0 may be nullptr
+    T rscale;
 };
 
 // Per-iteration values of a lock-step batched launch.
@@ -119,7 +120,7 @@ template <typename T>
 struct Dyn {
     T beta, beta_next;      // momentum of y(i) and of y(i+1)
     int parity;             // 1: the table's zc/zp are swapped this iteration
-    int it;                 // iteration index within the call (statistics row)
+    int ring;               // statistics ring entry of this iteration
 };
 
 template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s);
@@ -138,13 +139,23 @@ template <typename T>
 hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, int groups, size_t lds, Dyn<T> d,
                            hipStream_t s);
 template <typename T>
-hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, hipStream_t s);
-hipError_t launch_stats_finalize_b(double *const *slots, double *const *stats, const int *flags, int n, int it,
+hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s);
+// stats[it0+j][q] += sum of ring entry (it0+j) % PD_RING, then zeroed, for
+// j < count; batched: one image per grid row, ring/stats bases from tables.
+hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, int n, int it0, int count,
                                    hipStream_t s);
 void tiles_synth(int M1c, int M2c, int *tx, int *ty);
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty);
 void tiles_blur(int n1, int n2, int *tx, int *ty);
-// stats[q] += sum of slots[q][*], slots zeroed (q = 0..2); zero_only: just zero
-hipError_t launch_stats_finalize(double *slots, double *stats, int zero_only, hipStream_t s);
+hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s);
+template <typename T> hipError_t launch_fill(T *dst, T v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
+                              hipStream_t s);
+template <typename T> hipError_t launch_add(const T *x, T *y, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C, int levels, hipStream_t s);
 
 }  // namespace pd

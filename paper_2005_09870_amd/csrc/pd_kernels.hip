@@ -488,34 +488,6 @@ __device__ void coarse_synthesis(T *A, T *B, int pitch, int m1, int m2, int nlev
     }
 }
 
-// stats[q] += sum_s slots[q][s]; slots zeroed.  Called by a whole workgroup
-// of NTH threads; contains barriers.
-template <int NTH>
-__device__ void finalize_slots(double *slots, double *stats)
-{
-    __shared__ double red[3][NTH / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int e = threadIdx.x; e < PD_NSLOT; e += NTH) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-            v[q] += __hip_atomic_exchange(slots + q * PD_NSLOT + e, 0.0, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        double a = v[q];
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-        if (lane == 0) red[q][wv] = a;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3 && stats) {
-        double a = 0.0;
-        for (int k = 0; k < NTH / 64; ++k) a += red[threadIdx.x][k];
-        stats[threadIdx.x] += a;
-    }
-}
-
 template <typename T>
 __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
 {
@@ -626,17 +598,8 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
             }
         }
         if (bad) atomicOr(p.flag, 1);
-        if (p.slots) {
-            block_slot_add<2, NTC>(st, p.slots + PD_NSLOT);  // contains a barrier
-            __syncthreads();
-            // last kernel of the iteration: the image's only coarse workgroup finalises
-            if (a.finalize) {
-                __threadfence();
-                finalize_slots<NTC>(p.slots, p.stats);
-            }
-        } else {
-            __syncthreads();
-        }
+        if (p.slots) block_slot_add<2, NTC>(st, p.slots + PD_NSLOT);  // contains a barrier
+        else __syncthreads();
     }
     if (!(a.ops & COARSE_SYN)) return;
     // 3. synthesis of the block back to the level lc-1 approximation
@@ -650,14 +613,49 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
     }
 }
 
-// Statistics finaliser for iterations without a single coarse workgroup.
-__global__ __launch_bounds__(256) void k_stats_finalize(double *slots, double *stats, int zero_only)
+// Statistics finaliser: workgroup (j, img) sums ring entry (it0+j) % PD_RING
+// of image img into stats[it0+j][0..2] and zeroes the entry.
+__device__ void finalize_entry(double *slots, double *stats)
 {
-    if (zero_only) {
-        for (int e = threadIdx.x; e < 3 * PD_NSLOT; e += 256) slots[e] = 0.0;
-        return;
+    __shared__ double red[3][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < PD_NSLOT; e += 256) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            v[q] += slots[q * PD_NSLOT + e];
+            slots[q * PD_NSLOT + e] = 0.0;
+        }
     }
-    finalize_slots<256>(slots, stats);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double a = v[q];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+        if (lane == 0) red[q][wv] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) stats[threadIdx.x] += red[threadIdx.x][0] + red[threadIdx.x][1] +
+                                               red[threadIdx.x][2] + red[threadIdx.x][3];
+}
+
+__global__ __launch_bounds__(256) void k_stats_finalize(double *ring, double *stats, int it0)
+{
+    const int it = it0 + blockIdx.x;
+    finalize_entry(ring + (size_t)(it % PD_RING) * 3 * PD_NSLOT, stats + 3 * (size_t)it);
+}
+
+__global__ __launch_bounds__(256) void k_stats_finalize_b(double *const *__restrict__ ring,
+                                                           double *const *__restrict__ stats, int it0)
+{
+    const int it = it0 + blockIdx.x, img = blockIdx.y;
+    finalize_entry(ring[img] + (size_t)(it % PD_RING) * 3 * PD_NSLOT, stats[img] + 3 * (size_t)it);
+}
+
+template <typename T>
+__global__ void k_fill(T *dst, T v, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = v;
 }
 
 // ===========================================================================
@@ -696,7 +694,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
     const int64_t ch = bz;
     const int o1 = bx * BT1, o2 = by * BT2;
     const T *x = a.x + ch * a.plane;
-    const T *f0 = a.f0 + ch * a.plane;
+    const T *f0 = a.f0 ? a.f0 + ch * a.plane : nullptr;
     const T *__restrict__ taps = a.taps;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -759,7 +757,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 #pragma unroll
         for (int k = 0; k < RVH; ++k) {
             acc[k] = T(0);
-            f0v[k] = f0[(int64_t)wrap(o2 - RM + r0 + k, n2) * n1 + q1];
+            f0v[k] = a.f0 ? f0[(int64_t)wrap(o2 - RM + r0 + k, n2) * n1 + q1] : T(0);
         }
 #pragma unroll
         for (int m = 0; m < RVH + 2 * RM; ++m) {
@@ -778,7 +776,13 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
             const int pr = r0 + k, pc = lane;
             bool own = pr >= RM && pr < RM + BT2 && pc >= RM && pc < RM + BT1 &&
                        (o2 - RM + pr) < n2 && (o1 - RM + pc) < n1;
-            if (own) st[0] += 0.5 * (double)rv * (double)rv;
+            if (own) {
+                st[0] += 0.5 * (double)rv * (double)rv;
+                if (a.racc) {  // reverse mode: accumulate rscale * H x
+                    T *ra = a.racc + ch * a.plane + (int64_t)(o2 - RM + pr) * n1 + (o1 - RM + pc);
+                    *ra = fma(a.rscale, rv, *ra);
+                }
+            }
         }
     }
     __syncthreads();
@@ -834,9 +838,10 @@ __global__ __launch_bounds__(NT) void k_identity(BlurArgs<T> a)
     double st[1] = {0.0};
     const int64_t total = (int64_t)a.n1 * a.n2 * a.C;
     for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        T rv = a.x[e] - a.f0[e];
+        T rv = a.x[e] - (a.f0 ? a.f0[e] : T(0));
         a.s[e] = rv;
         st[0] += 0.5 * (double)rv * (double)rv;
+        if (a.racc) a.racc[e] = fma(a.rscale, rv, a.racc[e]);
     }
     if (a.slots) block_slot_add<1, NT>(st, a.slots);
 }
@@ -871,6 +876,64 @@ __global__ __launch_bounds__(NT) void k_blur_single(BlurArgs<T> a, int transpose
             }
         }
         s[e] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode of the iteration (adjoint of Appendix A.1's recursion).
+// With z(i) = S_{tau w}(v(i)):  vbar = zbar 1{z(i) != 0},
+// wbar -= tau zbar sign(z(i)) 1{z(i) != 0}  (z != 0 exactly when |v| > tau w,
+// and then sign z = sign v; the kink gets derivative 0).
+template <typename T>
+__global__ void k_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const T zv = z[e], zb = zbar[e];
+        const bool act = zv != T(0);
+        vbar[e] = act ? zb : T(0);
+        if (wbar && act) wbar[e] -= tau * zb * (zv > T(0) ? T(1) : T(-1));
+    }
+}
+
+// ybar = vbar - tau gbar; with b = b_{i-1}:  zbar <- zbarm + (1+b) ybar,
+// zbarm <- -b ybar  (i >= 2); for i = 1 zbar <- ybar + zbarm (the init's adjoint).
+template <typename T>
+__global__ void k_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const T yb = vbar[e] - tau * gbar[e];
+        if (first) {
+            zbar[e] = yb + zbarm[e];
+        } else {
+            zbar[e] = zbarm[e] + (T(1) + b) * yb;
+            zbarm[e] = -b * yb;
+        }
+    }
+}
+
+// y += x
+template <typename T>
+__global__ void k_add(const T *x, T *y, int64_t n)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] += x[e];
+}
+
+// Per-coefficient weight map from per-band weights (Mallat layout).
+template <typename T>
+__global__ void k_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C, int levels)
+{
+    const int64_t N = (int64_t)n1 * n2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * C; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = e % N;
+        const int r = (int)(q / n1), c = (int)(q - (int64_t)r * n1);
+        int band = 0;
+        for (int lev = 1; lev <= levels; ++lev)
+            if (r >= (n2 >> lev) || c >= (n1 >> lev)) {
+                band = levels + 1 - lev;
+                break;
+            }
+        w[e] = wlev_dev[band];
     }
 }
 
@@ -925,7 +988,7 @@ __device__ __forceinline__ void apply_dyn(ProxArgs<T> &p, const Dyn<T> &d)
     }
     p.zn = const_cast<T *>(p.zp);  // z(i) is written in place of z(i-2)
     p.beta = d.beta;
-    if (p.stats) p.stats += 3 * (int64_t)d.it;
+    if (p.slots) p.slots += (size_t)d.ring * 3 * PD_NSLOT;
 }
 
 template <typename T>
@@ -981,24 +1044,15 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_blur_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
-                                                int n)
+                                                int n, int ring)
 {
     const int img = locate(start, n, blockIdx.x);
     BlurArgs<T> a = tab[img];
+    if (a.slots) a.slots += (size_t)ring * 3 * PD_NSLOT;
     int loc = blockIdx.x - start[img];
     const int bx = loc % a.tx;
     loc /= a.tx;
     blur_body<T>(a, bx, loc % a.ty, loc / a.ty);
-}
-
-// Batched statistics finaliser: workgroup i finalises image i if flagged.
-__global__ __launch_bounds__(256) void k_stats_finalize_b(double *const *__restrict__ slots,
-                                                           double *const *__restrict__ stats, const int *flags,
-                                                           int it)
-{
-    const int img = blockIdx.x;
-    if (!flags[img] || !slots[img]) return;
-    finalize_slots<256>(slots[img], stats[img] ? stats[img] + 3 * (int64_t)it : nullptr);
 }
 
 // ------------------------------------------------------------ launchers ---
@@ -1098,26 +1152,79 @@ hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, in
 }
 
 template <typename T>
-hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, hipStream_t s)
+hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_blur_b<T>, dim3(tiles), dim3(NT), 0, s, tab, start, n);
+    hipLaunchKernelGGL(k_blur_b<T>, dim3(tiles), dim3(NT), 0, s, tab, start, n, ring);
     return hipGetLastError();
 }
 
-hipError_t launch_stats_finalize_b(double *const *slots, double *const *stats, const int *flags, int n, int it,
+hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, int n, int it0, int count,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stats_finalize_b, dim3(n), dim3(256), 0, s, slots, stats, flags, it);
+    hipLaunchKernelGGL(k_stats_finalize_b, dim3(count, n), dim3(256), 0, s, ring, stats, it0);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_fill(T *dst, T v, int64_t n, hipStream_t s)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(256), 0, s, dst, v, n);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
+template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
+
+static inline int ew_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+template <typename T>
+hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rev_mask<T>, dim3(ew_blocks(n)), dim3(256), 0, s, zbar, z, vbar, wbar, tau, n);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rev_combine<T>, dim3(ew_blocks(n)), dim3(256), 0, s, vbar, gbar, zbar, zbarm, tau, b, first, n);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_add(const T *x, T *y, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add<T>, dim3(ew_blocks(n)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C, int levels, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_expand_weights<T>, dim3(ew_blocks((int64_t)n1 * n2 * C)), dim3(256), 0, s, w, wlev_dev, n1,
+                       n2, C, levels);
+    return hipGetLastError();
+}
+#define PD_INST_REV(T)                                                                                  \
+    template hipError_t launch_rev_mask<T>(const T *, const T *, T *, T *, T, int64_t, hipStream_t);    \
+    template hipError_t launch_rev_combine<T>(const T *, const T *, T *, T *, T, T, int, int64_t,       \
+                                              hipStream_t);                                             \
+    template hipError_t launch_add<T>(const T *, T *, int64_t, hipStream_t);                            \
+    template hipError_t launch_expand_weights<T>(T *, const T *, int, int, int, int, hipStream_t);
+PD_INST_REV(float)
+PD_INST_REV(double)
 
 void tiles_synth(int M1c, int M2c, int *tx, int *ty) { *tx = (M1c + SP - 1) / SP; *ty = (M2c + SP - 1) / SP; }
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty) { *tx = (M1c + TC - 1) / TC; *ty = (M2c + TC - 1) / TC; }
 void tiles_blur(int n1, int n2, int *tx, int *ty) { *tx = (n1 + BT1 - 1) / BT1; *ty = (n2 + BT2 - 1) / BT2; }
 
-hipError_t launch_stats_finalize(double *slots, double *stats, int zero_only, hipStream_t s)
+hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stats_finalize, dim3(1), dim3(256), 0, s, slots, stats, zero_only);
+    hipLaunchKernelGGL(k_stats_finalize, dim3(count), dim3(256), 0, s, ring, stats, it0);
     return hipGetLastError();
 }
 
@@ -1134,7 +1241,7 @@ hipError_t launch_stats_finalize(double *slots, double *stats, int zero_only, hi
                                              hipStream_t);                                                      \
     template hipError_t launch_coarse_b<T>(const CoarseArgs<T> *, const int *, int, int, size_t, Dyn<T>,       \
                                            hipStream_t);                                                        \
-    template hipError_t launch_blur_b<T>(const BlurArgs<T> *, const int *, int, int, hipStream_t);
+    template hipError_t launch_blur_b<T>(const BlurArgs<T> *, const int *, int, int, int, hipStream_t);
 PD_INST(float)
 PD_INST(double)
 

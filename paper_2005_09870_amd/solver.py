@@ -253,3 +253,62 @@ def pd_timing_read() -> list[dict]:
     return [{"kernel": C.KCLASS_NAMES.get(kc[i], str(kc[i])), "kclass": kc[i], "level": lv[i],
              "launches": la[i], "total_ms": ms[i], "avg_us": 1e3 * ms[i] / max(la[i], 1)}
             for i in range(n)]
+
+
+# ---------------------------------------------------------------- backward ---
+def pd_backward(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
+                grad_f: torch.Tensor, level_w=None, coeff_w: torch.Tensor | None = None,
+                checkpoint_every: int = 20, want_f0: bool = True, want_w: bool = True):
+    """Reverse mode of pd_solve (init = Psi^* f0): returns (dL/df0, dL/dw) for
+    dL/df = grad_f.  dL/dw is per coefficient (Mallat layout)."""
+    _check_dev(f0, grad_f, coeff_w)
+    dt = _dtype_code(f0.dtype)
+    shape = _shape(f0, levels)
+    wav, hh = _wavelet(h)
+    lw = None if level_w is None else np.ascontiguousarray(np.asarray(level_w, dtype=np.float64))
+    w = C.pd_weights(_dptr(lw) if lw is not None else None,
+                     None if coeff_w is None else coeff_w.data_ptr(), 0)
+    prm = C.pd_params(float(tau), int(iters), 0, 0)
+    gf0 = torch.empty_like(f0) if want_f0 else None
+    gw = torch.empty_like(f0) if want_w else None
+    L = C.load()
+    need = L.pd_backward_workspace_size(ctypes.byref(shape), dt, int(iters), int(checkpoint_every))
+    if need == 0:
+        raise C.PDError(C.PD_ERR_ARG, "pd_backward_workspace_size")
+    ws = workspace(need, f0.device)
+    opc = op.c()
+    rc = L.pd_backward(ctypes.byref(shape), dt, ctypes.byref(opc), ctypes.byref(wav), ctypes.byref(w),
+                       ctypes.byref(prm), _ptr(f0), _ptr(grad_f.contiguous()), _ptr(gf0), _ptr(gw),
+                       int(checkpoint_every), _ptr(ws), ws.numel(), _stream(f0.device))
+    C.check(rc, "pd_backward")
+    return gf0, gw
+
+
+class FistaSolve(torch.autograd.Function):
+    """f = Psi z(K) of pd_solve as a differentiable function of the observation
+    f0 and the per-coefficient weights w; the backward pass is pd_backward."""
+
+    @staticmethod
+    def forward(ctx, f0, w, op, h, levels, tau, iters, checkpoint_every):
+        f0 = f0.contiguous()
+        w = w.contiguous()
+        out = pd_solve(f0, op, h, levels, tau, iters, coeff_w=w)["f"]
+        ctx.save_for_backward(f0, w)
+        ctx.cfg = (op, h, levels, tau, iters, checkpoint_every)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        f0, w = ctx.saved_tensors
+        op, h, levels, tau, iters, ce = ctx.cfg
+        gf0, gw = pd_backward(f0, op, h, levels, tau, iters, grad_f.contiguous(), coeff_w=w,
+                              checkpoint_every=ce, want_f0=ctx.needs_input_grad[0],
+                              want_w=ctx.needs_input_grad[1])
+        return gf0, gw, None, None, None, None, None, None
+
+
+def solve_autograd(f0: torch.Tensor, theta: torch.Tensor, op: Operator, h, levels: int, tau: float,
+                   iters: int, checkpoint_every: int = 20) -> torch.Tensor:
+    """Differentiable solve with weights w = softplus(theta) (per coefficient)."""
+    w = torch.nn.functional.softplus(theta)
+    return FistaSolve.apply(f0, w, op, h, levels, tau, iters, checkpoint_every)
