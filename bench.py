@@ -174,6 +174,94 @@ def batched_vs_per_image(torch, P, SI, h, iters, count):
             "speedup": round(res["batched"] / res["per_image"], 3), "bitwise_equal": same}
 
 
+def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20):
+    """16 x 256^2, per-coefficient weights softplus(theta), 200 unrolled
+    iterations, L = 1/2 ||f - clean||^2: forward solve + pd_backward per image
+    (checkpoint every 20 iterations).  Mpixel-iter/s = count n^2 iters / time."""
+    cases = SI.case_grad(count, n=n)
+    dev = "cuda"
+    op = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    tau = P.step_size(op, n, n, device=dev)
+    items = []
+    for c in cases:
+        clean = torch.as_tensor(c.clean, dtype=torch.float32, device=dev)
+        f0 = (P.pd_apply_op(clean, op) + torch.as_tensor(c.noise, dtype=torch.float32, device=dev)).contiguous()
+        th = torch.as_tensor(c.theta, dtype=torch.float32, device=dev)
+        items.append((f0, th, clean, c.levels))
+
+    def run():
+        gs = []
+        for f0, th, clean, L in items:
+            f0r = f0.clone().requires_grad_(True)
+            thr = th.clone().requires_grad_(True)
+            f = P.solve_autograd(f0r, thr, op, h, L, tau, iters, checkpoint_every=ce)
+            loss = 0.5 * ((f - clean) ** 2).sum()
+            loss.backward()
+            gs.append((f0r.grad, thr.grad))
+        return gs
+
+    run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return {"workload": f"{count} x {n}^2 FP32, softplus weights, {iters} iterations, checkpoint {ce}",
+            "fwd_bwd_mpx_it_s": round(count * n * n * iters / dt / 1e6, 1), "ms": round(1e3 * dt, 2)}
+
+
+def colour_case(torch, P, SI, h, iters, n=2048):
+    """2048 x 2048 x 3, joint (group) shrinkage across channels, noise 0.1 + 5%
+    salt-and-pepper, lambda 0.1: forward solve Mpixel-iter/s (pixels x
+    channels) and the dominant kernel's HBM roofline."""
+    c = SI.case_colour(n=n)
+    dev = "cuda"
+    op = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    clean = torch.as_tensor(c.clean, dtype=torch.float32, device=dev)
+    f0 = P.pd_apply_op(clean, op) + torch.as_tensor(c.noise, dtype=torch.float32, device=dev)
+    m = torch.as_tensor(c.sp_mask, device=dev)
+    v = torch.as_tensor(c.sp_val, dtype=torch.float32, device=dev)
+    f0 = torch.where(m[None], v[None].expand_as(f0), f0).contiguous()
+    tau = P.step_size(op, n, n, device=dev)
+    shape = P.solver._shape(f0, c.levels)
+    ws = P.solver.workspace(P.pd_workspace_size(shape, f0.dtype), f0.device)
+
+    def run(k):
+        return P.pd_solve(f0, op, h, c.levels, tau, k, level_w=c.level_w, joint=True, ws=ws, stats=True)
+
+    run(5)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    run(iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    P.solver.pd_timing_enable(True)
+    run(20)
+    torch.cuda.synchronize()
+    rows = P.solver.pd_timing_read()
+    P.solver.pd_timing_enable(False)
+    for rw in rows:
+        rw["alg_bytes_per_launch"] = alg_bytes(rw["kernel"], rw["level"], n, n, 3, 4, False)
+    dom = max(rows, key=lambda rw: rw["total_ms"])
+    ach = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
+    return {"workload": f"{n}x{n}x3 FP32 joint shrinkage, {iters} iterations",
+            "mpx_it_s": round(3 * n * n * iters / dt / 1e6, 1), "ms_per_iter": round(1e3 * dt / iters, 4),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom["kernel"] +
+                         (f" level {dom['level']}" if dom["level"] else ""), "avg_us": round(dom["avg_us"], 3)},
+            "kernels_us": {f"{rw['kernel']}/{rw['level']}": round(rw["avg_us"], 2) for rw in rows}}
+
+
+def copy_calibration(torch, nbytes=256 << 20):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +272,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=100)
     ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-colour", action="store_true")
+    ap.add_argument("--colour-iters", type=int, default=300)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU sharding is not "
@@ -197,6 +290,10 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
+    if args.calibrate_copy:
+        nb = copy_calibration(torch)
+        print(json.dumps({"copy_bytes": nb, "repeats": 3}))
+        return
     h = P.pd_symmlet(6)
     case, op, f0, tau = make_problem(torch, P, SI)
     n = case.n1
@@ -232,6 +329,12 @@ def main():
     if not args.no_batched:
         log(f"[bench] batched vs per-image: {args.batched_count} images, {args.batched_iters} iterations")
         line["batched"] = batched_vs_per_image(torch, P, SI, h, args.batched_iters, args.batched_count)
+    if not args.no_grad:
+        log("[bench] fwd+bwd: 16 x 256^2, 200 iterations")
+        line["fwd_bwd"] = fwd_bwd(torch, P, SI, h)
+    if not args.no_colour:
+        log(f"[bench] colour 2048^2 x 3, {args.colour_iters} iterations")
+        line["colour_2048x3"] = colour_case(torch, P, SI, h, args.colour_iters)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(SI)

@@ -393,99 +393,172 @@ __device__ __forceinline__ int wrapc(int a, int M, int mask)
 }
 __device__ __forceinline__ int pmask(int M) { return (M & (M - 1)) == 0 ? M - 1 : -1; }
 
-template <typename T>
-__device__ void coarse_analysis(T *A, T *B, int pitch, int m1, int m2, int nlev, const Filt<T> &f)
+// Index split e -> (e / w, e % w) with a shift when w is a power of two.
+__device__ __forceinline__ void split(int e, int w, int &q, int &r)
 {
-    int M1 = m1, M2 = m2;
-    for (int lev = 0; lev < nlev; ++lev) {
-        const int h1 = M1 / 2, h2 = M2 / 2;
-        const int k1 = pmask(M1), k2 = pmask(M2);
-        for (int e = threadIdx.x; e < M2 * h1; e += NTC) {  // along x1
-            int r = e / h1, l = e - r * h1;
-            const T *row = A + r * pitch;
-            T x[22];  // inputs 2l-10 .. 2l+11
-#pragma unroll
-            for (int k = 0; k < 22; ++k) x[k] = row[wrapc(2 * l + k - 10, M1, k1)];
-            T lo = T(0), hi = T(0);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                lo = fma(f.h[k], x[k + 10], lo);
-                hi = fma(f.g[k], x[k], hi);
-            }
-            B[r * pitch + l] = lo;
-            B[r * pitch + h1 + l] = hi;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < h2 * M1; e += NTC) {  // along x2
-            int l = e / M1, c = e - l * M1;
-            T x[22];
-#pragma unroll
-            for (int k = 0; k < 22; ++k) x[k] = B[wrapc(2 * l + k - 10, M2, k2) * pitch + c];
-            T lo = T(0), hi = T(0);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                lo = fma(f.h[k], x[k + 10], lo);
-                hi = fma(f.g[k], x[k], hi);
-            }
-            A[l * pitch + c] = lo;
-            A[(h2 + l) * pitch + c] = hi;
-        }
-        __syncthreads();
-        M1 = h1;
-        M2 = h2;
+    if ((w & (w - 1)) == 0) {
+        const int sh = __builtin_ctz(w);
+        q = e >> sh;
+        r = e & (w - 1);
+    } else {
+        q = e / w;
+        r = e - q * w;
     }
 }
 
-// One thread per output pair (2p, 2p+1) along each axis.
-template <typename T>
-__device__ void coarse_synthesis(T *A, T *B, int pitch, int m1, int m2, int nlev, const Filt<T> &f)
+// Orders the LDS accesses of one wave: all lanes' writes before any later read.
+__device__ __forceinline__ void wave_sync()
 {
-    for (int lev = nlev - 1; lev >= 0; --lev) {
-        const int M1c = m1 >> (lev + 1), M2c = m2 >> (lev + 1);
-        const int M1 = 2 * M1c, M2 = 2 * M2c;
-        const int k1 = pmask(M1c), k2 = pmask(M2c);
-        for (int e = threadIdx.x; e < M2c * M1; e += NTC) {  // along x2
-            int pp = e / M1, c = e - pp * M1;
-            T lo[6], hi[6];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Levels whose input holds at most this many values run on one wave with
+// wave-level ordering only (no workgroup barriers on the critical path).
+constexpr int WAVE_LEVEL_MAX = 256;
+
+// One analysis level (rows then columns) over `nthr` threads (thread index
+// `t`), M1 x M2 input in A -> Mallat bands in A, B as scratch.
+template <typename T, bool WAVE>
+__device__ __forceinline__ void ana_level(T *A, T *B, int pitch, int M1, int M2, const Filt<T> &f, int t,
+                                          int nthr)
+{
+    const int h1 = M1 / 2, h2 = M2 / 2;
+    const int k1 = pmask(M1), k2 = pmask(M2);
+    for (int e = t; e < M2 * h1; e += nthr) {  // along x1
+        int r, l;
+        split(e, h1, r, l);
+        const T *row = A + r * pitch;
+        T x[22];  // inputs 2l-10 .. 2l+11
 #pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                lo[j] = A[wrapc(pp - 5 + j, M2c, k2) * pitch + c];
-                hi[j] = A[(M2c + wrapc(pp + j, M2c, k2)) * pitch + c];
-            }
+        for (int k = 0; k < 22; ++k) x[k] = row[wrapc(2 * l + k - 10, M1, k1)];
+        T lo = T(0), hi = T(0);
 #pragma unroll
-            for (int par = 0; par < 2; ++par) {
-                T acc = T(0);
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
-                    acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
-                }
-                B[(2 * pp + par) * pitch + c] = acc;
-            }
+        for (int k = 0; k < 12; ++k) {
+            lo = fma(f.h[k], x[k + 10], lo);
+            hi = fma(f.g[k], x[k], hi);
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < M2 * M1c; e += NTC) {  // along x1
-            int n = e / M1c, pp = e - n * M1c;
-            const T *row = B + n * pitch;
-            T lo[6], hi[6];
+        B[r * pitch + l] = lo;
+        B[r * pitch + h1 + l] = hi;
+    }
+    if (WAVE) wave_sync();
+    else __syncthreads();
+    for (int e = t; e < h2 * M1; e += nthr) {  // along x2
+        int l, c;
+        split(e, M1, l, c);
+        T x[22];
+#pragma unroll
+        for (int k = 0; k < 22; ++k) x[k] = B[wrapc(2 * l + k - 10, M2, k2) * pitch + c];
+        T lo = T(0), hi = T(0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            lo = fma(f.h[k], x[k + 10], lo);
+            hi = fma(f.g[k], x[k], hi);
+        }
+        A[l * pitch + c] = lo;
+        A[(h2 + l) * pitch + c] = hi;
+    }
+    if (WAVE) wave_sync();
+    else __syncthreads();
+}
+
+// One synthesis level: coarse M1c x M2c bands in A -> 2 M1c x 2 M2c in A.
+template <typename T, bool WAVE>
+__device__ __forceinline__ void syn_level(T *A, T *B, int pitch, int M1c, int M2c, const Filt<T> &f, int t,
+                                          int nthr)
+{
+    const int M1 = 2 * M1c, M2 = 2 * M2c;
+    const int k1 = pmask(M1c), k2 = pmask(M2c);
+    for (int e = t; e < M2c * M1; e += nthr) {  // along x2
+        int pp, c;
+        split(e, M1, pp, c);
+        T lo[6], hi[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            lo[j] = A[wrapc(pp - 5 + j, M2c, k2) * pitch + c];
+            hi[j] = A[(M2c + wrapc(pp + j, M2c, k2)) * pitch + c];
+        }
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T acc = T(0);
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                lo[j] = row[wrapc(pp - 5 + j, M1c, k1)];
-                hi[j] = row[M1c + wrapc(pp + j, M1c, k1)];
+                acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
+                acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
             }
+            B[(2 * pp + par) * pitch + c] = acc;
+        }
+    }
+    if (WAVE) wave_sync();
+    else __syncthreads();
+    for (int e = t; e < M2 * M1c; e += nthr) {  // along x1
+        int n, pp;
+        split(e, M1c, n, pp);
+        const T *row = B + n * pitch;
+        T lo[6], hi[6];
 #pragma unroll
-            for (int par = 0; par < 2; ++par) {
-                T acc = T(0);
+        for (int j = 0; j < 6; ++j) {
+            lo[j] = row[wrapc(pp - 5 + j, M1c, k1)];
+            hi[j] = row[M1c + wrapc(pp + j, M1c, k1)];
+        }
 #pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
-                    acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
-                }
-                A[n * pitch + 2 * pp + par] = acc;
+        for (int par = 0; par < 2; ++par) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
+                acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
+            }
+            A[n * pitch + 2 * pp + par] = acc;
+        }
+    }
+    if (WAVE) wave_sync();
+    else __syncthreads();
+}
+
+// Analysis of all nlev levels of the block; the small ones on wave 0 alone.
+// Ends with a workgroup barrier.
+template <typename T>
+__device__ void coarse_analysis(T *A, T *B, int pitch, int m1, int m2, int nlev, const Filt<T> &f)
+{
+    int M1 = m1, M2 = m2, lev = 0;
+    for (; lev < nlev && M1 * M2 > WAVE_LEVEL_MAX; ++lev) {
+        ana_level<T, false>(A, B, pitch, M1, M2, f, threadIdx.x, NTC);
+        M1 /= 2;
+        M2 /= 2;
+    }
+    if (lev < nlev) {
+        if (threadIdx.x < 64) {
+            for (; lev < nlev; ++lev) {
+                ana_level<T, true>(A, B, pitch, M1, M2, f, threadIdx.x, 64);
+                M1 /= 2;
+                M2 /= 2;
             }
         }
         __syncthreads();
     }
+}
+
+// Synthesis of all nlev levels of the block (coarse to fine); the small ones
+// on wave 0 alone.  Ends with a workgroup barrier.
+template <typename T>
+__device__ void coarse_synthesis(T *A, T *B, int pitch, int m1, int m2, int nlev, const Filt<T> &f)
+{
+    int lev = nlev - 1;
+    if (threadIdx.x < 64) {
+        for (; lev >= 0; --lev) {
+            const int M1c = m1 >> (lev + 1), M2c = m2 >> (lev + 1);
+            if (4 * M1c * M2c > WAVE_LEVEL_MAX) break;
+            syn_level<T, true>(A, B, pitch, M1c, M2c, f, threadIdx.x, 64);
+        }
+    } else {
+        for (; lev >= 0; --lev)
+            if (4 * (m1 >> (lev + 1)) * (m2 >> (lev + 1)) > WAVE_LEVEL_MAX) break;
+    }
+    __syncthreads();
+    for (; lev >= 0; --lev)
+        syn_level<T, false>(A, B, pitch, m1 >> (lev + 1), m2 >> (lev + 1), f, threadIdx.x, NTC);
 }
 
 template <typename T>
