@@ -88,7 +88,7 @@ Filt<T> make_filt(const pd_wavelet *w)
 // Workspace: approximation pyramid (levels 1..L-1), x, s, flag.
 struct Layout {
     size_t apx[PD_MAXL + 1];
-    size_t x, s, flag, slots, total;
+    size_t x, s, flag, slots, tail, total;
 };
 
 Layout layout(const pd_shape *s, size_t es)
@@ -110,6 +110,8 @@ Layout layout(const pd_shape *s, size_t es)
     off = align_up(off + 256);
     l.slots = off;
     off = align_up(off + (size_t)PD_RING * 3 * PD_NSLOT * sizeof(double));
+    l.tail = off;
+    off = align_up(off + 2 * PD_TAIL_MAX * PD_TAIL_MAX * es);
     l.total = off;
     return l;
 }
@@ -154,7 +156,23 @@ void clear_timing()
 
 // Largest approximation (per side) the coarse kernel holds in LDS.
 constexpr int COARSE_MAX = 64;
-constexpr size_t COARSE_LDS_MAX = 64 * 1024;
+constexpr size_t COARSE_LDS_MAX = 156 * 1024;
+
+// The coarse block's last levels (input <= PD_TAIL_MAX values) are applied as
+// one orthogonal matrix.  kw = levels done pass by pass before the tail.
+struct TailShape {
+    int kw, tM1, tM2, nt;
+};
+
+TailShape tail_shape(int m1, int m2, int nlev)
+{
+    TailShape t{0, m1, m2, nlev};
+    while (t.kw < nlev && (m1 >> t.kw) * (m2 >> t.kw) > PD_TAIL_MAX) ++t.kw;
+    t.tM1 = m1 >> t.kw;
+    t.tM2 = m2 >> t.kw;
+    t.nt = nlev - t.kw;
+    return t;
+}
 
 template <typename T>
 struct Ctx {
@@ -164,6 +182,8 @@ struct Ctx {
     Layout lay;
     hipStream_t st;
     int lc;  // first level handled by the coarse kernel (levels + 1: none)
+    TailShape ts;
+    const T *tail;  // device copy of the tail matrices (nullptr: none)
     int64_t N() const { return (int64_t)sh->n1 * sh->n2; }
     T *apx(int j) const { return (T *)(ws + lay.apx[j]); }
     T *x() const { return (T *)(ws + lay.x); }
@@ -186,6 +206,70 @@ int coarse_level(const pd_shape *sh, int joint)
             return lc;
     }
     return sh->levels + 1;
+}
+
+// Host analysis (Sections 2.1-2.2, same index conventions as the kernels) of
+// a tM2 x tM1 array over nt levels, in place.
+void host_analysis(std::vector<double> &x, int M1, int M2, int nt, const Filt<double> &f)
+{
+    int m1 = M1, m2 = M2;
+    std::vector<double> t(std::max(M1, M2));
+    auto md = [](int a, int n) { int r = a % n; return r < 0 ? r + n : r; };
+    for (int lev = 0; lev < nt; ++lev) {
+        for (int r = 0; r < m2; ++r) {
+            for (int l = 0; l < m1 / 2; ++l) {
+                double lo = 0.0, hi = 0.0;
+                for (int k = 0; k < 12; ++k) {
+                    lo += f.h[k] * x[(size_t)r * M1 + md(2 * l + k, m1)];
+                    hi += f.g[k] * x[(size_t)r * M1 + md(2 * l + k - 10, m1)];
+                }
+                t[l] = lo;
+                t[m1 / 2 + l] = hi;
+            }
+            for (int c = 0; c < m1; ++c) x[(size_t)r * M1 + c] = t[c];
+        }
+        for (int c = 0; c < m1; ++c) {
+            for (int l = 0; l < m2 / 2; ++l) {
+                double lo = 0.0, hi = 0.0;
+                for (int k = 0; k < 12; ++k) {
+                    lo += f.h[k] * x[(size_t)md(2 * l + k, m2) * M1 + c];
+                    hi += f.g[k] * x[(size_t)md(2 * l + k - 10, m2) * M1 + c];
+                }
+                t[l] = lo;
+                t[m2 / 2 + l] = hi;
+            }
+            for (int r = 0; r < m2; ++r) x[(size_t)r * M1 + c] = t[r];
+        }
+        m1 /= 2;
+        m2 /= 2;
+    }
+}
+
+// [2][tn][tn]: the tail's analysis matrix (row i = output i) and its transpose.
+// Cached per (shape, filter, dtype); the cache keeps the host copy alive for
+// asynchronous uploads.
+template <typename T>
+const std::vector<T> &tail_matrices(const TailShape &ts, const pd_wavelet *wav)
+{
+    static std::map<std::vector<double>, std::vector<T>> cache;
+    std::vector<double> key{(double)ts.tM1, (double)ts.tM2, (double)ts.nt};
+    for (int k = 0; k < wav->len; ++k) key.push_back(wav->h[k]);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int tn = ts.tM1 * ts.tM2;
+    const Filt<double> f = make_filt<double>(wav);
+    std::vector<T> m(2 * (size_t)tn * tn);
+    std::vector<double> x(tn);
+    for (int j = 0; j < tn; ++j) {
+        std::fill(x.begin(), x.end(), 0.0);
+        x[j] = 1.0;
+        host_analysis(x, ts.tM1, ts.tM2, ts.nt, f);
+        for (int i = 0; i < tn; ++i) {
+            m[(size_t)i * tn + j] = (T)x[i];                      // analysis: out i <- in j
+            m[(size_t)tn * tn + (size_t)j * tn + i] = (T)x[i];    // transpose
+        }
+    }
+    return cache.emplace(key, std::move(m)).first->second;
 }
 
 template <typename T>
@@ -234,6 +318,11 @@ int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T>
     a.apx_out = lc == 1 ? out : c.apx(lc - 1);
     a.apx_out_plane = a.apx_in_plane;
     a.beta_next = beta_next;
+    a.kw = c.ts.kw;
+    a.tM1 = c.ts.tM1;
+    a.tM2 = c.ts.tM2;
+    a.tail = c.tail;
+    if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
     a.p = p;
     const int groups = p.joint ? 1 : c.sh->channels;
     PD_TRY_HIP(timed(PD_K_COARSE, lc, c.st, [&] { return launch_coarse<T>(a, groups, c.st); }));
@@ -345,6 +434,17 @@ Ctx<T> make_ctx(const pd_shape *sh, const pd_wavelet *wav, void *workspace, hipS
     c.lay = layout(sh, sizeof(T));
     c.st = st;
     c.lc = coarse_level<T>(sh, joint);
+    c.tail = nullptr;
+    c.ts = TailShape{0, 0, 0, 0};
+    if (c.lc <= sh->levels) {
+        c.ts = tail_shape(sh->n1 >> (c.lc - 1), sh->n2 >> (c.lc - 1), sh->levels - c.lc + 1);
+        if (c.ts.nt > 0 && workspace) {
+            const std::vector<T> &m = tail_matrices<T>(c.ts, wav);
+            T *dst = (T *)(c.ws + c.lay.tail);
+            if (hipMemcpyAsync(dst, m.data(), m.size() * sizeof(T), hipMemcpyHostToDevice, st) == hipSuccess)
+                c.tail = dst;
+        }
+    }
     return c;
 }
 
@@ -540,6 +640,9 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     Table<BlurArgs<T>> t_blur;
     std::vector<double *> slots_tab(batch), stats_tab(batch);
     const T *f_zfinal = (iters % 2 == 0) ? zA : zB;  // z(K) after K in-place iterations
+    // host image of the table region: tail matrices first (deduplicated), then the tables
+    std::vector<char> host;
+    std::map<std::vector<int>, size_t> tail_off;
 
     for (int b = 0; b < batch; ++b) {
         const BImg &im = L.img[b];
@@ -638,6 +741,26 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
             ca.apx_out = im.lc == 1 ? Xb : c.apx(im.lc - 1);
             ca.apx_out_plane = ca.apx_in_plane;
             ca.beta_next = T(0);
+            const TailShape ts = tail_shape(ca.m1, ca.m2, ca.nlev);
+            ca.kw = ts.kw;
+            ca.tM1 = ts.tM1;
+            ca.tM2 = ts.tM2;
+            ca.tail = nullptr;
+            if (ts.nt > 0) {
+                std::vector<int> key{ts.tM1, ts.tM2, ts.nt};
+                auto itk = tail_off.find(key);
+                size_t o;
+                if (itk == tail_off.end()) {
+                    const std::vector<T> &m = tail_matrices<T>(ts, wav);
+                    o = align_up(host.size());
+                    host.resize(o + m.size() * sizeof(T));
+                    std::memcpy(host.data() + o, m.data(), m.size() * sizeof(T));
+                    tail_off[key] = o;
+                } else {
+                    o = itk->second;
+                }
+                ca.tail = (const T *)(ws + L.tab + o);
+            }
             ca.ops = COARSE_ANA | COARSE_PROX | COARSE_SYN;
             ca.p = pp;
             t_coprox_syn.add(ca, C);
@@ -657,7 +780,6 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     }
 
     // upload every table into the workspace table region
-    std::vector<char> host;
     auto place = [&](auto &t) {
         if (t.n() == 0) return;
         using A = typename std::decay_t<decltype(t.args)>::value_type;

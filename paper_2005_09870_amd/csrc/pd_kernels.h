@@ -10,6 +10,7 @@
 #define PD_MAX_RADIUS 9
 #define PD_NSLOT 64   // partial-sum slots per statistic (spreads FP64 atomics)
 #define PD_RING 64    // iterations whose partial sums are kept before a finalise
+#define PD_TAIL_MAX 64 // coarse levels whose input has at most this many values are one matrix apply
 
 namespace pd {
 
@@ -98,6 +99,10 @@ struct CoarseArgs {
     T *apx_out;             // synthesis output (dense m2 x m1 per channel)
     int64_t apx_out_plane;
     T beta_next;            // momentum of the next iteration's y (COARSE_PROX|COARSE_SYN)
+    int kw;                 // levels of the block done level by level (input > PD_TAIL_MAX values)
+    int tM1, tM2;           // input size of the remaining levels (the tail), tM1*tM2 <= PD_TAIL_MAX
+    const T *tail;          // [2][tn][tn], tn = tM1*tM2: the tail's analysis matrix (row = output,
+                            // Mallat position) then its transpose (synthesis); nullptr if kw == nlev
     ProxArgs<T> p;          // in PLAIN analysis (ops == ANA) zn receives coefficients
 };
 
@@ -113,6 +118,16 @@ struct BlurArgs {
     int tx, ty;             // tiles along x1, x2 (batched launches)
     T *racc;                // reverse mode: racc += rscale * r (nullptr: off); f0 may be nullptr
     T rscale;
+};
+
+// Values that change from iteration to iteration, passed by value so that the
+// argument blocks themselves can be read in place (kernarg or device table).
+template <typename T>
+struct Live {
+    const T *zc, *zp;       // z(i-1), z(i-2)
+    T *zn;                  // z(i) (in place of z(i-2))
+    T beta, beta_next;      // momentum of y(i) and of y(i+1)
+    double *slots;          // this iteration's statistic slots (nullptr: off)
 };
 
 // Per-iteration values of a lock-step batched launch.

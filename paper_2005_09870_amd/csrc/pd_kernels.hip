@@ -34,6 +34,52 @@ __device__ __forceinline__ int wrap(int a, int n)
     return r < 0 ? r + n : r;
 }
 
+// Cross-lane sums on the DPP network (no LDS round trip).  dpp_row_sum:
+// every lane of a 16-lane row receives the row's sum, added pairwise as
+// (lane ^ 1), (lane ^ 2), mirror in 8, mirror in 16, so all lanes of the row
+// hold the same bits.  wave_sum: the sum of the four row sums, uniform.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename T>
+__device__ __forceinline__ T dpp_row_sum(T x)
+{
+    if constexpr (sizeof(T) == 4) {
+        x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+        x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+        x += dpp_f<0x141>(x);  // row_half_mirror
+        x += dpp_f<0x140>(x);  // row_mirror
+    } else {
+        x += dpp_d<0xB1>(x);
+        x += dpp_d<0x4E>(x);
+        x += dpp_d<0x141>(x);
+        x += dpp_d<0x140>(x);
+    }
+    return x;
+}
+__device__ __forceinline__ double lane_d(double x, int l)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x = dpp_row_sum(x);
+    return (lane_d(x, 0) + lane_d(x, 16)) + (lane_d(x, 32) + lane_d(x, 48));
+}
+
 // Block-wide sums of NV doubles; thread q adds sum q to row q of the
 // [NV][PD_NSLOT] slot array at a slot chosen by the block index, so that
 // concurrent workgroups rarely hit the same address.  Contains a barrier.
@@ -44,8 +90,7 @@ __device__ void block_slot_add(double (&v)[NV], double *slots)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        double a = v[q];
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+        const double a = wave_sum(v[q]);
         if (lane == 0) red[q][wv] = a;
     }
     __syncthreads();
@@ -91,7 +136,7 @@ constexpr int SF = 2 * SP;      // fine tile
 static_assert((2 * SR) % (NT / 64) == 0, "synthesis load rows per wave");
 
 template <typename T>
-__device__ __forceinline__ void synth_body(const SynthArgs<T> &a, int bx, int by, int bz)
+__device__ __forceinline__ void synth_body(const SynthArgs<T> &a, const Live<T> &lv, int bx, int by, int bz)
 {
     __shared__ T sB[4][SR][SR + 1];   // LL, HL (hi x1), LH (hi x2), HH
     __shared__ T sLH[2][SF][SR + 1];  // after x2 synthesis: low / high along x1
@@ -99,8 +144,8 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, int bx, int by
     const int M1 = 2 * M1c, M2 = 2 * M2c;
     const int64_t ch = bz;
     const int p01 = bx * SP, p02 = by * SP;
-    const T *zc = a.zc + ch * a.plane;
-    const T *zp = a.zp + ch * a.plane;
+    const T *zc = lv.zc + ch * a.plane;
+    const T *zp = lv.zp + ch * a.plane;
     const T *apx = a.apx ? a.apx + ch * a.apx_plane : nullptr;
     const int tid = threadIdx.x;
 
@@ -115,6 +160,8 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, int bx, int by
     const int q1 = lok ? wrap(p01 - 5 + lc_, M1c) : 0;
     const int col = q1 + (hi1 ? M1c : 0);
     constexpr int RPW = (2 * SR) / (NT / 64);  // 13 wave-rows per wave
+    // Every load is issued unconditionally (no data-dependent branch between
+    // a load and its use): the approximation band reads apx twice when given.
     T va[RPW], vb[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
@@ -122,24 +169,19 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, int bx, int by
         const bool bottom = R >= SR;
         const int r = bottom ? R - SR : R;
         const int q2 = wrap(p02 - 5 + r, M2c);
-        va[i] = T(0);
-        vb[i] = T(0);
-        if (!lok) continue;
-        if (!bottom && !hi1 && apx) {
-            va[i] = apx[(int64_t)q2 * M1c + q1];
-            vb[i] = va[i];
-        } else {
-            const int64_t idx = (int64_t)(q2 + (bottom ? M2c : 0)) * a.pitch + col;
-            va[i] = zc[idx];
-            vb[i] = zp[idx];
-        }
+        const bool from_apx = !bottom && !hi1 && apx;
+        const int64_t idx = !lok ? 0
+                            : from_apx ? (int64_t)q2 * M1c + q1
+                                       : (int64_t)(q2 + (bottom ? M2c : 0)) * a.pitch + col;
+        va[i] = (from_apx ? apx : zc)[idx];
+        vb[i] = (from_apx ? apx : zp)[idx];
     }
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
         const int R = wv + i * (NT / 64);
         const bool bottom = R >= SR;
         const int r = bottom ? R - SR : R;
-        if (lok) sB[(hi1 ? 1 : 0) + (bottom ? 2 : 0)][r][lc_] = va[i] + a.beta * (va[i] - vb[i]);
+        if (lok) sB[(hi1 ? 1 : 0) + (bottom ? 2 : 0)][r][lc_] = va[i] + lv.beta * (va[i] - vb[i]);
     }
     __syncthreads();
 
@@ -210,9 +252,13 @@ constexpr int TC = 16;
 constexpr int AR = 2 * TC + 20;  // fine region incl. halo
 static_assert(AR % (NT / 64) == 0 && AR <= 64, "analysis load rows per wave");
 
-template <typename T, bool JOINT>
-__device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, int by, int bz)
+// NCH = 0: one channel with scalar (or per-coefficient) weights; NCH >= 1:
+// the joint colour prox over NCH channels handled by one workgroup.
+template <typename T, int NCH>
+__device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Live<T> &lv, int bx, int by, int bz)
 {
+    constexpr bool JOINT = NCH > 0;
+    constexpr int NC = JOINT ? NCH : 1;
     __shared__ T sIn[AR][AR + 4];  // pitch 56: aligned 16-byte reads
     __shared__ T sRow[2][AR][TC + 1];  // low / high along x1
     const int M1c = a.M1c, M2c = a.M2c;
@@ -220,7 +266,6 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
     const int c01 = bx * TC, c02 = by * TC;
     const int tid = threadIdx.x;
     const ProxArgs<T> &p = a.p;
-    const int nch = JOINT ? p.C : 1;
     const int ch0 = JOINT ? 0 : bz;
 
     const int lane = tid & 63;
@@ -231,9 +276,41 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
     const int src = tid / (TC * (TC / 2));
     const int rem = tid - src * (TC * (TC / 2));
     const int rblk = rem / TC, l1 = rem - rblk * TC;
-    T res[JOINT ? PD_MAXC : 1][4];  // [ch][ (h, g) x 2 rows ]
+    T res[NC][4];  // [ch][ (h, g) x 2 rows ]
 
-    for (int cc = 0; cc < nch; ++cc) {
+    // outputs of this thread (band, row) in its column, and the prox operands
+    // for them: loaded first (clamped, unconditional) so that they arrive
+    // while the tile is transformed.  z(i) is written in place of z(i-2) only
+    // at the thread's own positions, after these reads.
+    const int g1 = c01 + l1;
+    const bool prox = a.mode == MODE_PROX;
+    T zcr[NC][4], zpr[NC][4], wr[4];
+    int64_t idxs[4];
+    bool valid[4], toapx[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int q = o >> 1, hx2 = o & 1;
+        const int b = src + 2 * hx2;  // bit 0: high along x1, bit 1: high along x2
+        const int g2 = c02 + 2 * rblk + q;
+        valid[o] = g2 < M2c && g1 < M1c;
+        toapx[o] = b == 0 && !a.last;
+        idxs[o] = (int64_t)(g2 + (hx2 ? M2c : 0)) * p.pitch + g1 + (src ? M1c : 0);
+        const bool use = valid[o] && !toapx[o] && prox;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int64_t ci = use ? (int64_t)(ch0 + cc) * p.plane + idxs[o] : 0;
+            const T u = (use ? lv.zc : a.in)[ci];
+            const T v = (use ? lv.zp : a.in)[ci];
+            zcr[cc][o] = use ? u : T(0);
+            zpr[cc][o] = use ? v : T(0);
+        }
+        const bool usew = use && p.wmap;
+        const T wv_ = (usew ? p.wmap : a.in)[usew ? (int64_t)ch0 * p.plane + idxs[o] : 0];
+        wr[o] = usew ? wv_ : T(0);
+    }
+
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
         const int ch = ch0 + cc;
         const T *in = a.in + (int64_t)ch * a.in_plane;
         // load: lane = fine column (52 of 64 lanes), wave = fine rows
@@ -243,9 +320,9 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
         for (int i = 0; i < RPW; ++i) {
             const int r = wv + i * (NT / 64);
             const T *rowp = in + (int64_t)wrap(2 * c02 - 10 + r, M2) * a.in_pitch;
-            v[i] = lok ? rowp[qc] : T(0);
+            v[i] = rowp[qc];
         }
-        if (JOINT && cc > 0) __syncthreads();  // previous channel's passes are done
+        if (cc > 0) __syncthreads();  // previous channel's passes are done
 #pragma unroll
         for (int i = 0; i < RPW; ++i)
             if (lok) sIn[wv + i * (NT / 64)][lane] = v[i];
@@ -288,37 +365,9 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
         }
     }
 
-    // epilogue: outputs (band, row) for this thread's column; every load is
-    // issued before the first store (z(i) is written in place of z(i-2))
+    // epilogue: stores and prox
     double st[2] = {0.0, 0.0};
     bool bad = false;
-    const int g1 = c01 + l1;
-    const bool prox = a.mode == MODE_PROX;
-    T zcr[JOINT ? PD_MAXC : 1][4], zpr[JOINT ? PD_MAXC : 1][4], wr[4];
-    int64_t idxs[4];
-    bool valid[4], toapx[4];
-#pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const int q = o >> 1, hx2 = o & 1;
-        const int b = src + 2 * hx2;  // bit 0: high along x1, bit 1: high along x2
-        const int g2 = c02 + 2 * rblk + q;
-        valid[o] = g2 < M2c && g1 < M1c;
-        toapx[o] = b == 0 && !a.last;
-        idxs[o] = (int64_t)(g2 + (hx2 ? M2c : 0)) * p.pitch + g1 + (src ? M1c : 0);
-        wr[o] = T(0);
-        for (int cc = 0; cc < nch; ++cc) {
-            zcr[cc][o] = T(0);
-            zpr[cc][o] = T(0);
-        }
-        if (valid[o] && !toapx[o] && prox) {
-            for (int cc = 0; cc < nch; ++cc) {
-                const int64_t ci = (int64_t)(ch0 + cc) * p.plane + idxs[o];
-                zcr[cc][o] = p.zc[ci];
-                zpr[cc][o] = p.zp[ci];
-            }
-            if (p.wmap) wr[o] = p.wmap[(int64_t)ch0 * p.plane + idxs[o]];
-        }
-    }
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         const int q = o >> 1, hx2 = o & 1;
@@ -326,26 +375,29 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
         if (!valid[o]) continue;
         if (toapx[o]) {
             const int g2 = c02 + 2 * rblk + q;
-            for (int cc = 0; cc < nch; ++cc)
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc)
                 a.apx_out[(int64_t)(ch0 + cc) * a.apx_plane + (int64_t)g2 * M1c + g1] = res[cc][2 * q + hx2];
             continue;
         }
         const int64_t idx = idxs[o];
         if (!prox) {
-            for (int cc = 0; cc < nch; ++cc) p.zn[(int64_t)(ch0 + cc) * p.plane + idx] = res[cc][2 * q + hx2];
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) lv.zn[(int64_t)(ch0 + cc) * p.plane + idx] = res[cc][2 * q + hx2];
             continue;
         }
         const int band = (b == 0) ? 0 : a.band_detail;
         if (!JOINT) {
             T w = p.wmap ? wr[o] : p.wlev[band];
-            T y = zcr[0][o] + p.beta * (zcr[0][o] - zpr[0][o]);
-            p.zn[(int64_t)ch0 * p.plane + idx] = prox1(y, res[0][2 * q + hx2], p.tau, w, st, bad);
+            T y = zcr[0][o] + lv.beta * (zcr[0][o] - zpr[0][o]);
+            lv.zn[(int64_t)ch0 * p.plane + idx] = prox1(y, res[0][2 * q + hx2], p.tau, w, st, bad);
         } else {
-            T yv[PD_MAXC], vv[PD_MAXC];
+            T yv[NC], vv[NC];
             T nv = T(0);
             double ny = 0.0;
-            for (int cc = 0; cc < nch; ++cc) {
-                yv[cc] = zcr[cc][o] + p.beta * (zcr[cc][o] - zpr[cc][o]);
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                yv[cc] = zcr[cc][o] + lv.beta * (zcr[cc][o] - zpr[cc][o]);
                 vv[cc] = yv[cc] - p.tau * res[cc][2 * q + hx2];
                 nv = fma(vv[cc], vv[cc], nv);
                 ny += (double)yv[cc] * (double)yv[cc];
@@ -356,15 +408,16 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
             sc = sc > T(0) ? sc : T(0);
             bad |= !isfinite(nrm);
             st[0] += (double)w * sqrt(ny);
-            for (int cc = 0; cc < nch; ++cc) {
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
                 T z = vv[cc] * sc;
-                p.zn[(int64_t)cc * p.plane + idx] = z;
+                lv.zn[(int64_t)cc * p.plane + idx] = z;
                 st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
             }
         }
     }
     if (a.mode == MODE_PROX) {
-        if (p.slots) block_slot_add<2, NT>(st, p.slots + PD_NSLOT);
+        if (lv.slots) block_slot_add<2, NT>(st, lv.slots + PD_NSLOT);
         if (bad) atomicOr(p.flag, 1);
     }
 }
@@ -380,18 +433,30 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, int bx, 
 // every other kernel of the iteration).
 // ===========================================================================
 constexpr int NTC = 1024;
+static_assert(NTC / 16 >= PD_TAIL_MAX, "tail_apply: 16 threads per output");
 constexpr int CPT = 4;  // block elements per thread (64 x 64 / 1024)
 
-// a mod M for a > -M*16 without integer division: a power-of-two M (mask =
-// M-1, uniform per level) takes one AND; otherwise a few conditional steps.
-__device__ __forceinline__ int wrapc(int a, int M, int mask)
-{
-    if (mask >= 0) return a & mask;
-    while (a < 0) a += M;
-    while (a >= M) a -= M;
-    return a;
-}
-__device__ __forceinline__ int pmask(int M) { return (M & (M - 1)) == 0 ? M - 1 : -1; }
+// LDS geometry of the coarse kernel for blocks up to CM x CM.  The filter
+// passes read periodic neighbours from halo copies written together with each
+// value, so their inner loops use fixed offsets and no index wrapping.  Each
+// pass computes two neighbouring outputs per task; the second of a pair that
+// falls outside an odd-sized band is computed from in-bounds values and dropped.
+//   A  the Mallat block (home of the coefficients), pitch PA
+//   C  analysis input rows, wrapped columns HA to the left and HA+2 to the
+//      right (pitch PC); later the synthesis rows with HS wrapped columns
+//      before the low band and HS+1 after the high band (E, pitch PE)
+//   B  analysis row-pass output with HA wrapped rows above and HA+2 below
+//      (pitch PB); later the synthesis inputs D[lev]: the level's Mallat block
+//      with HS wrapped rows above its low band and HS+1 below its high band
+// The odd pitches PC and PE keep lane-per-row accesses free of bank conflicts.
+template <typename T>
+struct CGeom {
+    static constexpr int CM = sizeof(T) == 4 ? 64 : 32;
+    static constexpr int HA = 10, HS = 5;
+    static constexpr int PA = CM + 1, PB = CM + 1;
+    static constexpr int PC = CM + 2 * HA + 3, PE = CM + 2 * HS + 3;
+    static constexpr int DR = 2 * HS + 1;  // halo rows of one D level
+};
 
 // Index split e -> (e / w, e % w) with a shift when w is a power of two.
 __device__ __forceinline__ void split(int e, int w, int &q, int &r)
@@ -406,221 +471,362 @@ __device__ __forceinline__ void split(int e, int w, int &q, int &r)
     }
 }
 
-// Orders the LDS accesses of one wave: all lanes' writes before any later read.
-__device__ __forceinline__ void wave_sync()
+// f(p) for every p = i + t n (t integer) with lo <= p < hi, given lo <= i < hi.
+template <typename F>
+__device__ __forceinline__ void copies(int i, int n, int lo, int hi, F &&f)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int p = i - n; p >= lo; p -= n) f(p);
+    f(i);
+    for (int p = i + n; p < hi; p += n) f(p);
 }
 
-// Levels whose input holds at most this many values run on one wave with
-// wave-level ordering only (no workgroup barriers on the critical path).
-constexpr int WAVE_LEVEL_MAX = 256;
-
-// One analysis level (rows then columns) over `nthr` threads (thread index
-// `t`), M1 x M2 input in A -> Mallat bands in A, B as scratch.
-template <typename T, bool WAVE>
-__device__ __forceinline__ void ana_level(T *A, T *B, int pitch, int M1, int M2, const Filt<T> &f, int t,
-                                          int nthr)
-{
-    const int h1 = M1 / 2, h2 = M2 / 2;
-    const int k1 = pmask(M1), k2 = pmask(M2);
-    for (int e = t; e < M2 * h1; e += nthr) {  // along x1
-        int r, l;
-        split(e, h1, r, l);
-        const T *row = A + r * pitch;
-        T x[22];  // inputs 2l-10 .. 2l+11
-#pragma unroll
-        for (int k = 0; k < 22; ++k) x[k] = row[wrapc(2 * l + k - 10, M1, k1)];
-        T lo = T(0), hi = T(0);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            lo = fma(f.h[k], x[k + 10], lo);
-            hi = fma(f.g[k], x[k], hi);
-        }
-        B[r * pitch + l] = lo;
-        B[r * pitch + h1 + l] = hi;
-    }
-    if (WAVE) wave_sync();
-    else __syncthreads();
-    for (int e = t; e < h2 * M1; e += nthr) {  // along x2
-        int l, c;
-        split(e, M1, l, c);
-        T x[22];
-#pragma unroll
-        for (int k = 0; k < 22; ++k) x[k] = B[wrapc(2 * l + k - 10, M2, k2) * pitch + c];
-        T lo = T(0), hi = T(0);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            lo = fma(f.h[k], x[k + 10], lo);
-            hi = fma(f.g[k], x[k], hi);
-        }
-        A[l * pitch + c] = lo;
-        A[(h2 + l) * pitch + c] = hi;
-    }
-    if (WAVE) wave_sync();
-    else __syncthreads();
-}
-
-// One synthesis level: coarse M1c x M2c bands in A -> 2 M1c x 2 M2c in A.
-template <typename T, bool WAVE>
-__device__ __forceinline__ void syn_level(T *A, T *B, int pitch, int M1c, int M2c, const Filt<T> &f, int t,
-                                          int nthr)
-{
-    const int M1 = 2 * M1c, M2 = 2 * M2c;
-    const int k1 = pmask(M1c), k2 = pmask(M2c);
-    for (int e = t; e < M2c * M1; e += nthr) {  // along x2
-        int pp, c;
-        split(e, M1, pp, c);
-        T lo[6], hi[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            lo[j] = A[wrapc(pp - 5 + j, M2c, k2) * pitch + c];
-            hi[j] = A[(M2c + wrapc(pp + j, M2c, k2)) * pitch + c];
-        }
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            T acc = T(0);
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
-                acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
-            }
-            B[(2 * pp + par) * pitch + c] = acc;
-        }
-    }
-    if (WAVE) wave_sync();
-    else __syncthreads();
-    for (int e = t; e < M2 * M1c; e += nthr) {  // along x1
-        int n, pp;
-        split(e, M1c, n, pp);
-        const T *row = B + n * pitch;
-        T lo[6], hi[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            lo[j] = row[wrapc(pp - 5 + j, M1c, k1)];
-            hi[j] = row[M1c + wrapc(pp + j, M1c, k1)];
-        }
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            T acc = T(0);
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
-                acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
-            }
-            A[n * pitch + 2 * pp + par] = acc;
-        }
-    }
-    if (WAVE) wave_sync();
-    else __syncthreads();
-}
-
-// Analysis of all nlev levels of the block; the small ones on wave 0 alone.
-// Ends with a workgroup barrier.
+// First row of D[lev] (level block M2 = m2 >> lev rows).
 template <typename T>
-__device__ void coarse_analysis(T *A, T *B, int pitch, int m1, int m2, int nlev, const Filt<T> &f)
+__device__ __forceinline__ int drow_base(int m2, int lev)
 {
-    int M1 = m1, M2 = m2, lev = 0;
-    for (; lev < nlev && M1 * M2 > WAVE_LEVEL_MAX; ++lev) {
-        ana_level<T, false>(A, B, pitch, M1, M2, f, threadIdx.x, NTC);
-        M1 /= 2;
-        M2 /= 2;
-    }
-    if (lev < nlev) {
-        if (threadIdx.x < 64) {
-            for (; lev < nlev; ++lev) {
-                ana_level<T, true>(A, B, pitch, M1, M2, f, threadIdx.x, 64);
-                M1 /= 2;
-                M2 /= 2;
+    int b = 0;
+    for (int j = 0; j < lev; ++j) b += (m2 >> j) + CGeom<T>::DR;
+    return b;
+}
+
+// Writes block value v at (r, c) of D[lev] (level block M2 rows, bands Mc2 = M2/2).
+template <typename T>
+__device__ __forceinline__ void put_d(T *D, int M2, int r, int c, T v)
+{
+    using G = CGeom<T>;
+    const int Mc2 = M2 >> 1;
+    if (r < Mc2)
+        copies(r + G::HS, Mc2, 0, Mc2 + G::HS, [&](int p) { D[p * G::PB + c] = v; });
+    else
+        copies(r + G::HS, Mc2, Mc2 + G::HS, M2 + G::DR, [&](int p) { D[p * G::PB + c] = v; });
+}
+
+// One analysis level (Section 2.1 filters, rows then columns): the M1 x M2
+// approximation in C -> detail bands in A; the approximation band goes to C
+// (next level, wrapped columns) or, if `last`, to A.
+template <typename T>
+__device__ __forceinline__ void ana_level(T *A, T *B, T *C, int M1, int M2, const Filt<T> &f, bool last)
+{
+    using G = CGeom<T>;
+    const int h1 = M1 / 2, h2 = M2 / 2;
+    const int q1 = (h1 + 1) / 2, q2 = (h2 + 1) / 2;  // output pairs per row / column
+    for (int e = threadIdx.x; e < M2 * q1; e += NTC) {  // along x1; lane = row
+        int r, j;
+        split(e, M2, j, r);
+        const int l = 2 * j;
+        const T *row = C + r * G::PC + 2 * l;  // row[k] = input column 2l+k-10
+        T x[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) x[k] = row[k];
+        T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            lo0 = fma(f.h[k], x[k + 10], lo0);
+            hi0 = fma(f.g[k], x[k], hi0);
+            lo1 = fma(f.h[k], x[k + 12], lo1);
+            hi1 = fma(f.g[k], x[k + 2], hi1);
+        }
+        const bool two = l + 1 < h1;
+        copies(r + G::HA, M2, 0, M2 + 2 * G::HA + 2, [&](int p) {
+            T *br = B + p * G::PB;
+            br[l] = lo0;
+            br[h1 + l] = hi0;
+            if (two) {
+                br[l + 1] = lo1;
+                br[h1 + l + 1] = hi1;
             }
+        });
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < q2 * M1; e += NTC) {  // along x2; lane = column
+        int j, c;
+        split(e, M1, j, c);
+        const int l = 2 * j;
+        const T *col = B + 2 * l * G::PB + c;  // col[k PB] = row 2l+k-10
+        T x[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) x[k] = col[k * G::PB];
+        T lo0 = T(0), hi0 = T(0), lo1 = T(0), hi1 = T(0);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            lo0 = fma(f.h[k], x[k + 10], lo0);
+            hi0 = fma(f.g[k], x[k], hi0);
+            lo1 = fma(f.h[k], x[k + 12], lo1);
+            hi1 = fma(f.g[k], x[k + 2], hi1);
+        }
+        const bool two = l + 1 < h2;
+        if (c < h1 && !last) {
+            copies(c + G::HA, h1, 0, h1 + 2 * G::HA + 2, [&](int p) {
+                C[l * G::PC + p] = lo0;
+                if (two) C[(l + 1) * G::PC + p] = lo1;
+            });
+        } else {
+            A[l * G::PA + c] = lo0;
+            if (two) A[(l + 1) * G::PA + c] = lo1;
+        }
+        A[(h2 + l) * G::PA + c] = hi0;
+        if (two) A[(h2 + l + 1) * G::PA + c] = hi1;
+    }
+    __syncthreads();
+}
+
+// Two synthesis outputs (parities 0, 1) of one position pp from lo[j] =
+// low band at pp-5+j and hi[j] = high band at pp+j (j = 0..5).
+template <typename T>
+__device__ __forceinline__ void syn_pair(const Filt<T> &f, const T *lo, const T *hi, T &o0, T &o1)
+{
+    T a0 = T(0), a1 = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        a0 = fma(f.h[10 - 2 * j], lo[j], a0);
+        a0 = fma(f.g[10 - 2 * j], hi[j], a0);
+        a1 = fma(f.h[11 - 2 * j], lo[j], a1);
+        a1 = fma(f.g[11 - 2 * j], hi[j], a1);
+    }
+    o0 = a0;
+    o1 = a1;
+}
+
+// One synthesis level: the M1 x M2 Mallat block in D (bands M1/2 x M2/2) ->
+// the M1 x M2 approximation, written to D of the next finer level (its
+// approximation band, that level has M2n = 2 M2 rows) or, for the finest
+// level (Dn == nullptr), to A.
+template <typename T>
+__device__ __forceinline__ void syn_level(const T *D, T *E, T *Dn, int M2n, T *A, int M1, int M2, const Filt<T> &f)
+{
+    using G = CGeom<T>;
+    const int M1c = M1 / 2, M2c = M2 / 2;
+    const int q2 = (M2c + 1) / 2, q1 = (M1c + 1) / 2;
+    for (int e = threadIdx.x; e < q2 * M1; e += NTC) {  // along x2; lane = column
+        int j0, c;
+        split(e, M1, j0, c);
+        const int pp = 2 * j0;
+        const T *lo_p = D + pp * G::PB + c;                  // rows pp-5 .. pp+1 of the low band
+        const T *hi_p = D + (M2c + G::HS + pp) * G::PB + c;  // rows pp .. pp+6 of the high band
+        T lo[7], hi[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            lo[j] = lo_p[j * G::PB];
+            hi[j] = hi_p[j * G::PB];
+        }
+        T o[4];
+        syn_pair<T>(f, lo, hi, o[0], o[1]);
+        syn_pair<T>(f, lo + 1, hi + 1, o[2], o[3]);
+        const int nout = pp + 1 < M2c ? 4 : 2;
+        const bool low = c < M1c;
+        copies(c + G::HS, M1c, low ? 0 : M1c + G::HS, low ? M1c + G::HS : M1 + G::DR, [&](int p) {
+            for (int q = 0; q < 4; ++q)
+                if (q < nout) E[(2 * pp + q) * G::PE + p] = o[q];
+        });
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < M2 * q1; e += NTC) {  // along x1; lane = row
+        int n, j0;
+        split(e, M2, j0, n);
+        const int pp = 2 * j0;
+        const T *row = E + n * G::PE;
+        T lo[7], hi[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            lo[j] = row[pp + j];
+            hi[j] = row[M1c + G::HS + pp + j];
+        }
+        T o[4];
+        syn_pair<T>(f, lo, hi, o[0], o[1]);
+        syn_pair<T>(f, lo + 1, hi + 1, o[2], o[3]);
+        const int nout = pp + 1 < M1c ? 4 : 2;
+        if (Dn) {
+            // approximation band of the finer level: low band rows, wrapped above
+            copies(n + G::HS, M2, 0, M2 + G::HS, [&](int p) {
+                for (int q = 0; q < 4; ++q)
+                    if (q < nout) Dn[p * G::PB + 2 * pp + q] = o[q];
+            });
+        } else {
+            for (int q = 0; q < 4; ++q)
+                if (q < nout) A[n * G::PA + 2 * pp + q] = o[q];
+        }
+    }
+    __syncthreads();
+    (void)M2n;
+}
+
+// The tail: out = Mat in over the tM2 x tM1 approximation at the top-left of A
+// (tn <= PD_TAIL_MAX values), 16 threads per output, fixed summation order.
+template <typename T>
+__device__ void tail_apply(T *A, int tM1, int tM2, const T *Mat)
+{
+    using G = CGeom<T>;
+    const int tn = tM1 * tM2;
+    const int i = threadIdx.x >> 4, q = threadIdx.x & 15;
+    T acc = T(0);
+    if (i < tn) {
+        const T *row = Mat + i * tn;
+        for (int j = q; j < tn; j += 16) {
+            int r, c;
+            split(j, tM1, r, c);
+            acc = fma(row[j], A[r * G::PA + c], acc);
+        }
+    }
+    acc = dpp_row_sum(acc);  // the 16 threads of an output form one DPP row
+    __syncthreads();         // every read of A is done
+    if (i < tn && q == 0) {
+        int r, c;
+        split(i, tM1, r, c);
+        A[r * G::PA + c] = acc;
+    }
+    __syncthreads();
+}
+
+// Analysis of the block in A: kw levels pass by pass, then the tail as one matrix.
+template <typename T>
+__device__ void coarse_analysis(T *A, T *B, T *C, int m1, int m2, int nlev, const Filt<T> &f, int kw, int tM1,
+                                int tM2, const T *Mat)
+{
+    using G = CGeom<T>;
+    if (kw > 0) {
+        for (int e = threadIdx.x; e < m1 * m2; e += NTC) {
+            int r, c;
+            split(e, m1, r, c);
+            const T v = A[r * G::PA + c];
+            copies(c + G::HA, m1, 0, m1 + 2 * G::HA + 2, [&](int p) { C[r * G::PC + p] = v; });
         }
         __syncthreads();
     }
+    for (int lev = 0; lev < kw; ++lev) ana_level<T>(A, B, C, m1 >> lev, m2 >> lev, f, lev == kw - 1);
+    if (kw < nlev) tail_apply<T>(A, tM1, tM2, Mat);
 }
 
-// Synthesis of all nlev levels of the block (coarse to fine); the small ones
-// on wave 0 alone.  Ends with a workgroup barrier.
+// Synthesis of the block in A: the tail (transposed matrix), then kw levels
+// coarse to fine; the result replaces the block in A.
 template <typename T>
-__device__ void coarse_synthesis(T *A, T *B, int pitch, int m1, int m2, int nlev, const Filt<T> &f)
+__device__ void coarse_synthesis(T *A, T *D, T *E, int m1, int m2, int nlev, const Filt<T> &f, int kw, int tM1,
+                                 int tM2, const T *MatT)
 {
-    int lev = nlev - 1;
-    if (threadIdx.x < 64) {
-        for (; lev >= 0; --lev) {
-            const int M1c = m1 >> (lev + 1), M2c = m2 >> (lev + 1);
-            if (4 * M1c * M2c > WAVE_LEVEL_MAX) break;
-            syn_level<T, true>(A, B, pitch, M1c, M2c, f, threadIdx.x, 64);
-        }
-    } else {
-        for (; lev >= 0; --lev)
-            if (4 * (m1 >> (lev + 1)) * (m2 >> (lev + 1)) > WAVE_LEVEL_MAX) break;
+    if (kw < nlev) tail_apply<T>(A, tM1, tM2, MatT);
+    if (kw == 0) return;
+    using G = CGeom<T>;
+    // every coefficient of the block goes to the input of the level that reads it
+    for (int e = threadIdx.x; e < m1 * m2; e += NTC) {
+        int r, c;
+        split(e, m1, r, c);
+        int lev = kw - 1;
+        for (int j = 0; j < kw - 1; ++j)
+            if (r >= (m2 >> (j + 1)) || c >= (m1 >> (j + 1))) {
+                lev = j;
+                break;
+            }
+        put_d<T>(D + drow_base<T>(m2, lev) * G::PB, m2 >> lev, r, c, A[r * G::PA + c]);
     }
     __syncthreads();
-    for (; lev >= 0; --lev)
-        syn_level<T, false>(A, B, pitch, m1 >> (lev + 1), m2 >> (lev + 1), f, threadIdx.x, NTC);
+    for (int lev = kw - 1; lev >= 0; --lev) {
+        const T *Dl = D + drow_base<T>(m2, lev) * G::PB;
+        T *Dn = lev > 0 ? D + drow_base<T>(m2, lev - 1) * G::PB : nullptr;
+        syn_level<T>(Dl, E, Dn, lev > 0 ? (m2 >> (lev - 1)) : 0, A, m1 >> lev, m2 >> lev, f);
+    }
 }
 
+// LDS layout of the coarse kernel (elements): A per channel, C/E, B/D, tail matrices.
 template <typename T>
-__device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
+struct CLayout {
+    int a, c, b, mat, total;
+    __host__ __device__ CLayout(int m1, int m2, int nch)
+    {
+        using G = CGeom<T>;
+        a = 0;
+        c = a + nch * m2 * G::PA;
+        b = c + m2 * G::PC;
+        int drows = 0;  // levels done pass by pass hold more than PD_TAIL_MAX values
+        for (int j = 0; (m1 >> j) * (m2 >> j) > PD_TAIL_MAX; ++j) drows += (m2 >> j) + G::DR;
+        const int brows = m2 + 2 * G::HA + 2;
+        mat = b + (drows > brows ? drows : brows) * G::PB + 8;  // + 8: reads past a dropped pair
+        total = mat + 2 * PD_TAIL_MAX * PD_TAIL_MAX;
+    }
+};
+
+// NCH: channels handled by the workgroup (the joint colour prox couples them).
+template <typename T, int NCH>
+__device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T> &lv, int bz)
 {
+    using G = CGeom<T>;
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
     const ProxArgs<T> &p = a.p;
-    const int m1 = a.m1, m2 = a.m2, pitch = m1 + 1;
-    const int nch = p.joint ? p.C : 1;
-    const int ch0 = p.joint ? 0 : bz;
-    T *B = lds + (size_t)nch * m2 * pitch;
+    const int m1 = a.m1, m2 = a.m2;
+    const int ch0 = NCH > 1 ? 0 : bz;
+    const CLayout<T> L(m1, m2, NCH);
+    T *Cb = lds + L.c;
+    T *B = lds + L.b;
+    T *Mat = lds + L.mat;  // [2][tn][tn] tail matrices
+    const int tn = a.tM1 * a.tM2;
     const int cnt = m1 * m2;  // <= CPT * NTC
     const int tid = threadIdx.x;
     const bool ana = (a.ops & COARSE_ANA) != 0, prox = (a.ops & COARSE_PROX) != 0;
+    const bool need_z = !ana || prox;
+    auto home = [&](int cc) { return lds + L.a + cc * m2 * G::PA; };
 
-    // 1. all global loads: analysis input (or y for synthesis only), and the
-    //    state/weights the prox needs, for this thread's block elements
-    T zcr[PD_MAXC][CPT], zpr[PD_MAXC][CPT], wr[CPT];
-    for (int cc = 0; cc < nch; ++cc) {
-        T *A = lds + (size_t)cc * m2 * pitch;
-        const int64_t ch = ch0 + cc;
-        T v[CPT];
+    // 1. every global load at once (clamped indices, no data-dependent branch):
+    //    analysis input or y's state, prox state and weights, tail matrices
+    int rr[CPT], cr[CPT];
+    int64_t gi[CPT];
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int e = tid + k * NTC;
-            v[k] = T(0);
-            zcr[cc][k] = T(0);
-            zpr[cc][k] = T(0);
-            if (e < cnt) {
-                const int r = e / m1, c = e - r * m1;
-                const int64_t idx = ch * p.plane + (int64_t)r * p.pitch + c;
-                if (ana) v[k] = a.apx_in[ch * a.apx_in_plane + e];
-                if (!ana || prox) {
-                    zcr[cc][k] = p.zc[idx];
-                    zpr[cc][k] = p.zp[idx];
-                }
-                if (cc == 0) wr[k] = (prox && p.wmap) ? p.wmap[idx] : T(0);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int e = tid + k * NTC;
-            if (e < cnt) {
-                const int r = e / m1, c = e - r * m1;
-                A[r * pitch + c] = ana ? v[k] : zcr[cc][k] + p.beta * (zcr[cc][k] - zpr[cc][k]);
-            }
-        }
+    for (int k = 0; k < CPT; ++k) {
+        const int e = tid + k * NTC;
+        split(e < cnt ? e : 0, m1, rr[k], cr[k]);
+        gi[k] = (int64_t)rr[k] * p.pitch + cr[k];
     }
+    // an unused source is replaced by element 0 of a buffer this launch reads anyway
+    const T *any = ana ? a.apx_in : lv.zc;
+    auto ld = [&](const T *src, bool use, int64_t i) {
+        const T x = (use ? src : any)[use ? i : 0];
+        return use ? x : T(0);
+    };
+    T v[NCH][CPT], zcr[NCH][CPT], zpr[NCH][CPT], wr[CPT];
+#pragma unroll
+    for (int cc = 0; cc < NCH; ++cc)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int e = tid + k * NTC;
+            const int64_t ch = ch0 + cc;
+            v[cc][k] = ld(a.apx_in, ana, ch * a.apx_in_plane + (e < cnt ? e : 0));
+            zcr[cc][k] = ld(lv.zc, need_z, ch * p.plane + gi[k]);
+            zpr[cc][k] = ld(lv.zp, need_z, ch * p.plane + gi[k]);
+        }
+    const bool use_w = prox && p.wmap;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) wr[k] = ld(p.wmap, use_w, (int64_t)ch0 * p.plane + gi[k]);
+    constexpr int MPT = 2 * PD_TAIL_MAX * PD_TAIL_MAX / NTC;
+    T mv[MPT];
+    const int nm = a.tail ? 2 * tn * tn : 0;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int e = tid + k * NTC;
+        mv[k] = ld(a.tail, nm > 0, e < nm ? e : 0);
+    }
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int e = tid + k * NTC;
+        if (e < nm) Mat[e] = mv[k];
+    }
+#pragma unroll
+    for (int cc = 0; cc < NCH; ++cc)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            if (tid + k * NTC < cnt)
+                home(cc)[rr[k] * G::PA + cr[k]] =
+                    ana ? v[cc][k] : zcr[cc][k] + lv.beta * (zcr[cc][k] - zpr[cc][k]);
     __syncthreads();
 
     if (ana) {
-        for (int cc = 0; cc < nch; ++cc)
-            coarse_analysis<T>(lds + (size_t)cc * m2 * pitch, B, pitch, m1, m2, a.nlev, a.f);
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc)
+            coarse_analysis<T>(home(cc), B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat);
         if (!prox) {  // plain forward transform
-            for (int cc = 0; cc < nch; ++cc) {
-                const T *A = lds + (size_t)cc * m2 * pitch;
-                for (int e = tid; e < cnt; e += NTC) {
-                    int r = e / m1, c = e - r * m1;
-                    p.zn[(int64_t)(ch0 + cc) * p.plane + (int64_t)r * p.pitch + c] = A[r * pitch + c];
-                }
-            }
+#pragma unroll
+            for (int cc = 0; cc < NCH; ++cc)
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+                    if (tid + k * NTC < cnt)
+                        lv.zn[(int64_t)(ch0 + cc) * p.plane + gi[k]] = home(cc)[rr[k] * G::PA + cr[k]];
             return;
         }
         // 2. gradient step + prox + momentum on the coarse block
@@ -628,9 +834,8 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
-            const int e = tid + k * NTC;
-            if (e >= cnt) continue;
-            const int r = e / m1, c = e - r * m1;
+            if (tid + k * NTC >= cnt) continue;
+            const int r = rr[k], c = cr[k];
             // band index: finest level of the block whose detail region holds (r, c)
             int band = 0;
             for (int lev = 0; lev < a.nlev; ++lev)
@@ -638,21 +843,22 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
                     band = a.band_top - lev;
                     break;
                 }
-            const int64_t idx = (int64_t)r * p.pitch + c;
-            if (!p.joint) {
-                T *A = lds;
+            const int li = r * G::PA + c;
+            if (NCH == 1 && !p.joint) {
+                T *A = home(0);
                 T w = p.wmap ? wr[k] : p.wlev[band];
-                T y = zcr[0][k] + p.beta * (zcr[0][k] - zpr[0][k]);
-                T z = prox1(y, A[r * pitch + c], p.tau, w, st, bad);
-                p.zn[(int64_t)ch0 * p.plane + idx] = z;
-                A[r * pitch + c] = z + a.beta_next * (z - zcr[0][k]);
+                T y = zcr[0][k] + lv.beta * (zcr[0][k] - zpr[0][k]);
+                T z = prox1(y, A[li], p.tau, w, st, bad);
+                lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
+                A[li] = z + lv.beta_next * (z - zcr[0][k]);
             } else {
-                T yv[PD_MAXC], vv[PD_MAXC];
+                T yv[NCH], vv[NCH];
                 T nv = T(0);
                 double ny = 0.0;
-                for (int cc = 0; cc < nch; ++cc) {
-                    yv[cc] = zcr[cc][k] + p.beta * (zcr[cc][k] - zpr[cc][k]);
-                    vv[cc] = yv[cc] - p.tau * lds[(size_t)cc * m2 * pitch + r * pitch + c];
+#pragma unroll
+                for (int cc = 0; cc < NCH; ++cc) {
+                    yv[cc] = zcr[cc][k] + lv.beta * (zcr[cc][k] - zpr[cc][k]);
+                    vv[cc] = yv[cc] - p.tau * home(cc)[li];
                     nv = fma(vv[cc], vv[cc], nv);
                     ny += (double)yv[cc] * (double)yv[cc];
                 }
@@ -662,26 +868,29 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, int bz)
                 sc = sc > T(0) ? sc : T(0);
                 bad |= !isfinite(nrm);
                 st[0] += (double)w * sqrt(ny);
-                for (int cc = 0; cc < nch; ++cc) {
+#pragma unroll
+                for (int cc = 0; cc < NCH; ++cc) {
                     T z = vv[cc] * sc;
-                    p.zn[(int64_t)cc * p.plane + idx] = z;
+                    lv.zn[(int64_t)cc * p.plane + gi[k]] = z;
                     st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
-                    lds[(size_t)cc * m2 * pitch + r * pitch + c] = z + a.beta_next * (z - zcr[cc][k]);
+                    home(cc)[li] = z + lv.beta_next * (z - zcr[cc][k]);
                 }
             }
         }
         if (bad) atomicOr(p.flag, 1);
-        if (p.slots) block_slot_add<2, NTC>(st, p.slots + PD_NSLOT);  // contains a barrier
+        if (lv.slots) block_slot_add<2, NTC>(st, lv.slots + PD_NSLOT);  // contains a barrier
         else __syncthreads();
     }
     if (!(a.ops & COARSE_SYN)) return;
     // 3. synthesis of the block back to the level lc-1 approximation
-    for (int cc = 0; cc < nch; ++cc) {
-        T *A = lds + (size_t)cc * m2 * pitch;
-        coarse_synthesis<T>(A, B, pitch, m1, m2, a.nlev, a.f);
-        for (int e = tid; e < cnt; e += NTC) {
-            int r = e / m1, c = e - r * m1;
-            a.apx_out[(int64_t)(ch0 + cc) * a.apx_out_plane + e] = A[r * pitch + c];
+#pragma unroll
+    for (int cc = 0; cc < NCH; ++cc) {
+        T *A = home(cc);
+        coarse_synthesis<T>(A, B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat + tn * tn);
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int e = tid + k * NTC;
+            if (e < cnt) a.apx_out[(int64_t)(ch0 + cc) * a.apx_out_plane + e] = A[rr[k] * G::PA + cr[k]];
         }
     }
 }
@@ -756,60 +965,42 @@ constexpr int TP = 68;                 // LDS pitch of t, r, u (multiple of 4)
 static_assert(BX2 % (NT / 64) == 0 && BX1 <= 128 && BX1 > 64, "blur load rows/columns");
 constexpr int RVH = 5;                 // rows per column task in the r pass (50 = 10 x 5)
 constexpr int UVH = 4;                 // rows per column task in the u pass (32 = 8 x 4)
+constexpr int RB_PER_WAVE = (BR2 / RVH + NT / 64 - 1) / (NT / 64);  // r-pass row blocks per wave
 
 template <typename T>
-__device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, int bz)
+struct BlurLds {
+    T sA[BX2 * XP];           // x, later r (BR2 x TP)
+    T sB[BX2 * TP];           // t, later u (BT2 x TP)
+    T sK[BX2][2 * RM + 2];    // profiles of the rows of x / t
+    int rmax[NT / 64];        // per wave: largest |d| with a non-zero profile entry
+};
+
+// RT: compile-time bound on the half-width of every profile this tile reads
+// (taps beyond it are zero), so only |d| <= RT is visited.
+template <typename T, int RT>
+__device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, int bz, BlurLds<T> &lds,
+                                          const T (&f0pre)[RB_PER_WAVE][RVH])
 {
-    __shared__ T sA[BX2 * XP];           // x, later r (BR2 x TP)
-    __shared__ T sB[BX2 * TP];           // t, later u (BT2 x TP)
-    __shared__ T sK[BX2][2 * RM + 2];    // profiles of the rows of x / t
-    const int n1 = a.n1, n2 = a.n2, R = a.R, W = 2 * R + 1;
+    T *__restrict__ sA = lds.sA;
+    T *__restrict__ sB = lds.sB;
+    T(*__restrict__ sK)[2 * RM + 2] = lds.sK;
+    const int n1 = a.n1, n2 = a.n2;
     const int64_t ch = bz;
     const int o1 = bx * BT1, o2 = by * BT2;
-    const T *x = a.x + ch * a.plane;
-    const T *f0 = a.f0 ? a.f0 + ch * a.plane : nullptr;
-    const T *__restrict__ taps = a.taps;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-    {
-        // load: lane = column (two chunks: 64 + 18), wave = rows (17 each)
-        constexpr int RPW = BX2 / (NT / 64);
-        const int qa = wrap(o1 - 2 * RM + lane, n1);
-        const bool okb = 64 + lane < BX1;
-        const int qb = okb ? wrap(o1 - 2 * RM + 64 + lane, n1) : 0;
-        T va[RPW], vb[RPW];
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int r = wv + i * (NT / 64);
-            const T *rowp = x + (int64_t)wrap(o2 - 2 * RM + r, n2) * n1;
-            va[i] = rowp[qa];
-            vb[i] = okb ? rowp[qb] : T(0);
-        }
-        for (int e = tid; e < BX2 * (2 * RM + 1); e += NT) {
-            int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
-            int row = wrap(o2 - 2 * RM + r, n2);
-            sK[r][d + RM] = (d >= -R && d <= R) ? taps[(int64_t)row * W + d + R] : T(0);
-        }
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int r = wv + i * (NT / 64);
-            sA[r * XP + lane] = va[i];
-            if (okb) sA[r * XP + 64 + lane] = vb[i];
-        }
-    }
-    __syncthreads();
 
     // t: rows [0, BX2) (pixel row o2-2RM+r), columns [0, BW) (pixel col o1-RM+c)
     for (int t = tid; t < BX2 * (BW / 4); t += NT) {
         int r = t / (BW / 4), blk = t - r * (BW / 4);
         T xv[4 + 2 * RM];
 #pragma unroll
-        for (int j = 0; j < 4 + 2 * RM; ++j) xv[j] = sA[r * XP + 4 * blk + j];
+        for (int j = 0; j < 4 + 2 * RM; ++j)
+            xv[j] = (j >= RM - RT && j < RM + RT + 4) ? sA[r * XP + 4 * blk + j] : T(0);
         T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int m = 0; m <= 2 * RM; ++m) {
+        for (int m = RM - RT; m <= RM + RT; ++m) {
             T k = sK[r][2 * RM - m];  // d = RM - m
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = fma(k, xv[q + m], acc[q]);
@@ -822,29 +1013,27 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
     // r: rows [0, BR2) (pixel row o2-RM+r), lane = column; the source t row of
     // output row r0+k and offset m is r0+m with profile index k+2RM-m.
     double st[1] = {0.0};
-    for (int blk = wv; blk < BR2 / RVH; blk += NT / 64) {
+#pragma unroll
+    for (int j = 0; j < RB_PER_WAVE; ++j) {
+        const int blk = wv + j * (NT / 64);
+        if (blk >= BR2 / RVH) break;
         const int r0 = blk * RVH;
         T acc[RVH];
-        T f0v[RVH];
-        const int q1 = wrap(o1 - RM + lane, n1);
 #pragma unroll
-        for (int k = 0; k < RVH; ++k) {
-            acc[k] = T(0);
-            f0v[k] = a.f0 ? f0[(int64_t)wrap(o2 - RM + r0 + k, n2) * n1 + q1] : T(0);
-        }
+        for (int k = 0; k < RVH; ++k) acc[k] = T(0);
 #pragma unroll
-        for (int m = 0; m < RVH + 2 * RM; ++m) {
+        for (int m = RM - RT; m < RVH + RM + RT; ++m) {
             const T tv = sB[(r0 + m) * TP + lane];
             const T *kr = &sK[r0 + m][RM];  // profile of source row r0+m (broadcast reads)
 #pragma unroll
             for (int k = 0; k < RVH; ++k) {
                 const int d = k + RM - m;  // displacement x2 - y2
-                if (d >= -RM && d <= RM) acc[k] = fma(kr[d], tv, acc[k]);
+                if (d >= -RT && d <= RT) acc[k] = fma(kr[d], tv, acc[k]);
             }
         }
 #pragma unroll
         for (int k = 0; k < RVH; ++k) {
-            T rv = acc[k] - f0v[k];
+            T rv = acc[k] - f0pre[j][k];
             sA[(r0 + k) * TP + lane] = rv;
             const int pr = r0 + k, pc = lane;
             bool own = pr >= RM && pr < RM + BT2 && pc >= RM && pc < RM + BT1 &&
@@ -865,13 +1054,14 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
         const int q0 = blk * UVH;
         T rv[UVH + 2 * RM];
 #pragma unroll
-        for (int j = 0; j < UVH + 2 * RM; ++j) rv[j] = sA[(q0 + j) * TP + lane];
+        for (int j = 0; j < UVH + 2 * RM; ++j)
+            rv[j] = (j >= RM - RT && j < UVH + RM + RT) ? sA[(q0 + j) * TP + lane] : T(0);
 #pragma unroll
         for (int k = 0; k < UVH; ++k) {
             const T *kr = &sK[q0 + k + 2 * RM][RM];  // profile of output row o2+q0+k
             T acc = T(0);
 #pragma unroll
-            for (int d = -RM; d <= RM; ++d) acc = fma(kr[d], rv[k + RM + d], acc);
+            for (int d = -RT; d <= RT; ++d) acc = fma(kr[d], rv[k + RM + d], acc);
             sB[(q0 + k) * TP + lane] = acc;
         }
     }
@@ -885,11 +1075,11 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 #pragma unroll
         for (int j = 0; j < 4 + 2 * RM; ++j) {
             int c = 4 * blk + j;
-            uv[j] = c < BW ? sB[q * TP + c] : T(0);
+            uv[j] = (c < BW && j >= RM - RT && j < RM + RT + 4) ? sB[q * TP + c] : T(0);
         }
         T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int m = 0; m <= 2 * RM; ++m) {
+        for (int m = RM - RT; m <= RM + RT; ++m) {
             T k = sK[q + 2 * RM][m];  // d = m - RM
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[j] = fma(k, uv[j + m], acc[j]);
@@ -902,6 +1092,86 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
         }
     }
     if (a.slots) block_slot_add<1, NT>(st, a.slots);
+}
+
+// Stages the x tile and the row profiles in LDS, then runs the passes with
+// the taps bounded by the widest profile the tile reads.
+template <typename T>
+__device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, int bz)
+{
+    __shared__ BlurLds<T> lds;
+    T *__restrict__ sA = lds.sA;
+    T(*__restrict__ sK)[2 * RM + 2] = lds.sK;
+    const int n1 = a.n1, n2 = a.n2, R = a.R, W = 2 * R + 1;
+    const int o1 = bx * BT1, o2 = by * BT2;
+    const T *x = a.x + (int64_t)bz * a.plane;
+    const T *__restrict__ taps = a.taps;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int rad = 0;
+    T f0pre[RB_PER_WAVE][RVH];
+    {
+        // load: lane = column (two chunks: 64 + 18), wave = rows (17 each)
+        constexpr int RPW = BX2 / (NT / 64);
+        const int qa = wrap(o1 - 2 * RM + lane, n1);
+        const bool okb = 64 + lane < BX1;
+        const int qb = okb ? wrap(o1 - 2 * RM + 64 + lane, n1) : 0;
+        T va[RPW], vb[RPW];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = wv + i * (NT / 64);
+            const T *rowp = x + (int64_t)wrap(o2 - 2 * RM + r, n2) * n1;
+            va[i] = rowp[qa];
+            vb[i] = okb ? rowp[qb] : T(0);
+        }
+        constexpr int KE = BX2 * (2 * RM + 1), KPT = (KE + NT - 1) / NT;
+        T kv[KPT];
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) {  // all profile loads in flight together
+            const int e = tid + i * NT;
+            const int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
+            const bool ok = e < KE && d >= -R && d <= R;
+            const T k = taps[ok ? (int64_t)wrap(o2 - 2 * RM + r, n2) * W + d + R : 0];
+            kv[i] = ok ? k : T(0);
+        }
+        // f0 for the r pass (rows of the wave's row blocks, lane = column)
+        const T *f0s = a.f0 ? a.f0 + (int64_t)bz * a.plane : x;
+        const int fq1 = wrap(o1 - RM + lane, n1);
+#pragma unroll
+        for (int j = 0; j < RB_PER_WAVE; ++j)
+#pragma unroll
+            for (int k = 0; k < RVH; ++k) {
+                const int rr = (wv + j * (NT / 64)) * RVH + k;
+                const T f = f0s[rr < BR2 ? (int64_t)wrap(o2 - RM + rr, n2) * n1 + fq1 : 0];
+                f0pre[j][k] = a.f0 ? f : T(0);
+            }
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) {
+            const int e = tid + i * NT;
+            const int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
+            if (e < KE) sK[r][d + RM] = kv[i];
+            if (kv[i] != T(0)) rad = max(rad, abs(d));
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rad = max(rad, __shfl_xor(rad, off));
+        if (lane == 0) lds.rmax[wv] = rad;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int r = wv + i * (NT / 64);
+            sA[r * XP + lane] = va[i];
+            if (okb) sA[r * XP + 64 + lane] = vb[i];
+        }
+    }
+    __syncthreads();
+    int rt = lds.rmax[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) rt = max(rt, lds.rmax[w]);
+    rt = __builtin_amdgcn_readfirstlane(rt);
+    if (rt <= 4)
+        blur_body<T, 4>(a, bx, by, bz, lds, f0pre);
+    else
+        blur_body<T, RM>(a, bx, by, bz, lds, f0pre);
 }
 
 // H = Id: s = r = x - f0.
@@ -1025,20 +1295,56 @@ __global__ void k_copy(const T *src, T *dst, int64_t n)
 // copies that image's argument block from device memory and applies the
 // per-iteration values (momentum, which buffer holds z(i-1), iteration).
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_synth(SynthArgs<T> a) { synth_body<T>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
-
-template <typename T, bool JOINT>
-__global__ __launch_bounds__(NT) void k_analysis(AnalysisArgs<T> a)
+// Tile of this workgroup in XCD-aware order.  Workgroups are dealt to the 8
+// XCDs round-robin by linear index, so workgroup b (on XCD b % 8) takes tile
+// (b % 8) * per + b / 8: each XCD works through one contiguous run of tiles
+// and neighbouring tiles share their halos in that XCD's L2.  Returns -1 for
+// the padding workgroups of the last run.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int total)
 {
-    analysis_body<T, JOINT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+    const int b = blockIdx.x, per = (total + NXCD - 1) / NXCD;
+    const int t = (b % NXCD) * per + b / NXCD;
+    return t < total ? t : -1;
+}
+__host__ __device__ inline int xcd_grid(int total) { return NXCD * ((total + NXCD - 1) / NXCD); }
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_synth(SynthArgs<T> a)
+{
+    const Live<T> lv{a.zc, a.zp, nullptr, a.beta, T(0), nullptr};
+    const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
+    if (t < 0) return;
+    synth_body<T>(a, lv, t % a.tx, t / a.tx, blockIdx.y);
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTC) void k_coarse(CoarseArgs<T> a) { coarse_body<T>(a, blockIdx.x); }
+__device__ __forceinline__ Live<T> live_of(const ProxArgs<T> &p, T beta_next)
+{
+    return Live<T>{p.zc, p.zp, p.zn, p.beta, beta_next, p.slots};
+}
+
+template <typename T, int NCH>
+__global__ __launch_bounds__(NT) void k_analysis(AnalysisArgs<T> a)
+{
+    const int t = xcd_tile(a.tx * a.ty);  // channel group = blockIdx.y
+    if (t < 0) return;
+    analysis_body<T, NCH>(a, live_of<T>(a.p, T(0)), t % a.tx, t / a.tx, blockIdx.y);
+}
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_blur(BlurArgs<T> a) { blur_body<T>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+__global__ __launch_bounds__(NTC) void k_coarse(CoarseArgs<T> a) { coarse_body<T, 1>(a, live_of<T>(a.p, a.beta_next), blockIdx.x); }
+// joint colour: all NCH channels in one workgroup
+template <typename T, int NCH>
+__global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a) { coarse_body<T, NCH>(a, live_of<T>(a.p, a.beta_next), 0); }
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_blur(BlurArgs<T> a)
+{
+    const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
+    if (t < 0) return;
+    blur_tile<T>(a, t % a.tx, t / a.tx, blockIdx.y);
+}
 
 __device__ __forceinline__ int locate(const int *__restrict__ start, int n, int blk)
 {
@@ -1051,48 +1357,46 @@ __device__ __forceinline__ int locate(const int *__restrict__ start, int n, int 
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
+// Live values of a batched iteration: the table holds z(0) in zc and its copy
+// in zp; odd iterations swap them, z(i) goes in place of z(i-2).
 template <typename T>
-__device__ __forceinline__ void apply_dyn(ProxArgs<T> &p, const Dyn<T> &d)
+__device__ __forceinline__ Live<T> live_dyn(const ProxArgs<T> &p, const Dyn<T> &d)
 {
-    if (d.parity) {
-        const T *t = p.zc;
-        p.zc = p.zp;
-        p.zp = t;
-    }
-    p.zn = const_cast<T *>(p.zp);  // z(i) is written in place of z(i-2)
-    p.beta = d.beta;
-    if (p.slots) p.slots += (size_t)d.ring * 3 * PD_NSLOT;
+    const T *zc = d.parity ? p.zp : p.zc, *zp = d.parity ? p.zc : p.zp;
+    return Live<T>{zc, zp, const_cast<T *>(zp), d.beta, d.beta_next,
+                   p.slots ? p.slots + (size_t)d.ring * 3 * PD_NSLOT : nullptr};
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_synth_b(const SynthArgs<T> *__restrict__ tab, const int *__restrict__ start,
                                                  int n, Dyn<T> d)
 {
-    const int img = locate(start, n, blockIdx.x);
-    SynthArgs<T> a = tab[img];
-    if (d.parity) {
-        const T *t = a.zc;
-        a.zc = a.zp;
-        a.zp = t;
-    }
-    a.beta = d.beta;
-    int loc = blockIdx.x - start[img];
-    const int bx = loc % a.tx;
-    loc /= a.tx;
-    synth_body<T>(a, bx, loc % a.ty, loc / a.ty);
+    const int g = xcd_tile(start[n]);
+    if (g < 0) return;
+    const int img = locate(start, n, g);
+    const SynthArgs<T> &a = tab[img];
+    const Live<T> lv{d.parity ? a.zp : a.zc, d.parity ? a.zc : a.zp, nullptr, d.beta, T(0), nullptr};
+    int loc = g - start[img];
+    const int tx = a.tx, ty = a.ty;
+    const int bx = loc % tx;
+    loc /= tx;
+    synth_body<T>(a, lv, bx, loc % ty, loc / ty);
 }
 
-template <typename T, bool JOINT>
+template <typename T>
 __global__ __launch_bounds__(NT) void k_analysis_b(const AnalysisArgs<T> *__restrict__ tab,
                                                     const int *__restrict__ start, int n, Dyn<T> d)
 {
-    const int img = locate(start, n, blockIdx.x);
-    AnalysisArgs<T> a = tab[img];
-    if (a.mode == MODE_PROX) apply_dyn<T>(a.p, d);
-    int loc = blockIdx.x - start[img];
-    const int bx = loc % a.tx;
-    loc /= a.tx;
-    analysis_body<T, JOINT>(a, bx, loc % a.ty, loc / a.ty);
+    const int g = xcd_tile(start[n]);
+    if (g < 0) return;
+    const int img = locate(start, n, g);
+    const AnalysisArgs<T> &a = tab[img];
+    const Live<T> lv = a.mode == MODE_PROX ? live_dyn<T>(a.p, d) : live_of<T>(a.p, T(0));
+    int loc = g - start[img];
+    const int tx = a.tx, ty = a.ty;
+    const int bx = loc % tx;
+    loc /= tx;
+    analysis_body<T, 0>(a, lv, bx, loc % ty, loc / ty);
 }
 
 template <typename T>
@@ -1100,58 +1404,69 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
                                                    int n, Dyn<T> d)
 {
     const int img = locate(start, n, blockIdx.x);
-    CoarseArgs<T> a = tab[img];
+    const CoarseArgs<T> &a = tab[img];
+    Live<T> lv;
     if (a.ops & COARSE_PROX) {
-        apply_dyn<T>(a.p, d);
-        a.beta_next = d.beta_next;
+        lv = live_dyn<T>(a.p, d);
     } else if (!(a.ops & COARSE_ANA)) {  // synthesis only: y from the state
-        if (d.parity) {
-            const T *t = a.p.zc;
-            a.p.zc = a.p.zp;
-            a.p.zp = t;
-        }
-        a.p.beta = d.beta;
+        lv = live_dyn<T>(a.p, d);
+        lv.slots = nullptr;
+    } else {
+        lv = live_of<T>(a.p, T(0));
     }
-    coarse_body<T>(a, blockIdx.x - start[img]);
+    coarse_body<T, 1>(a, lv, blockIdx.x - start[img]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_blur_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
                                                 int n, int ring)
 {
-    const int img = locate(start, n, blockIdx.x);
+    const int g = xcd_tile(start[n]);
+    if (g < 0) return;
+    const int img = locate(start, n, g);
     BlurArgs<T> a = tab[img];
     if (a.slots) a.slots += (size_t)ring * 3 * PD_NSLOT;
-    int loc = blockIdx.x - start[img];
+    int loc = g - start[img];
     const int bx = loc % a.tx;
     loc /= a.tx;
-    blur_body<T>(a, bx, loc % a.ty, loc / a.ty);
+    blur_tile<T>(a, bx, loc % a.ty, loc / a.ty);
 }
 
 // ------------------------------------------------------------ launchers ---
 template <typename T>
 hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s)
 {
-    dim3 grid((a.M1c + SP - 1) / SP, (a.M2c + SP - 1) / SP, C);
-    hipLaunchKernelGGL(k_synth<T>, grid, dim3(NT), 0, s, a);
+    SynthArgs<T> b = a;
+    tiles_synth(a.M1c, a.M2c, &b.tx, &b.ty);
+    hipLaunchKernelGGL(k_synth<T>, dim3(xcd_grid(b.tx * b.ty), C), dim3(NT), 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s)
 {
-    dim3 grid((a.M1c + TC - 1) / TC, (a.M2c + TC - 1) / TC, a.p.joint ? 1 : a.p.C);
-    if (a.p.joint)
-        hipLaunchKernelGGL((k_analysis<T, true>), grid, dim3(NT), 0, s, a);
+    AnalysisArgs<T> b = a;
+    tiles_analysis(a.M1c, a.M2c, &b.tx, &b.ty);
+    const int groups = a.p.joint ? 1 : a.p.C;
+    dim3 grid(xcd_grid(b.tx * b.ty), groups);
+    if (!a.p.joint)
+        hipLaunchKernelGGL((k_analysis<T, 0>), grid, dim3(NT), 0, s, b);
+    else if (a.p.C == 1)
+        hipLaunchKernelGGL((k_analysis<T, 1>), grid, dim3(NT), 0, s, b);
+    else if (a.p.C == 2)
+        hipLaunchKernelGGL((k_analysis<T, 2>), grid, dim3(NT), 0, s, b);
+    else if (a.p.C == 3)
+        hipLaunchKernelGGL((k_analysis<T, 3>), grid, dim3(NT), 0, s, b);
     else
-        hipLaunchKernelGGL((k_analysis<T, false>), grid, dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_analysis<T, 4>), grid, dim3(NT), 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
 size_t coarse_lds_bytes(int m1, int m2, int chans)
 {
-    return sizeof(T) * (size_t)(chans + 1) * m2 * (m1 + 1);
+    if (m1 > CGeom<T>::CM || m2 > CGeom<T>::CM) return SIZE_MAX;
+    return sizeof(T) * (size_t)CLayout<T>(m1, m2, chans).total;
 }
 
 template <typename T>
@@ -1159,7 +1474,16 @@ hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s)
 {
     const int chans = a.p.joint ? a.p.C : 1;
     size_t lds = coarse_lds_bytes<T>(a.m1, a.m2, chans);
-    hipLaunchKernelGGL(k_coarse<T>, dim3(groups), dim3(NTC), lds, s, a);
+    if (!a.p.joint)
+        hipLaunchKernelGGL(k_coarse<T>, dim3(groups), dim3(NTC), lds, s, a);
+    else if (chans == 1)
+        hipLaunchKernelGGL((k_coarse_joint<T, 1>), dim3(groups), dim3(NTC), lds, s, a);
+    else if (chans == 2)
+        hipLaunchKernelGGL((k_coarse_joint<T, 2>), dim3(groups), dim3(NTC), lds, s, a);
+    else if (chans == 3)
+        hipLaunchKernelGGL((k_coarse_joint<T, 3>), dim3(groups), dim3(NTC), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_coarse_joint<T, 4>), dim3(groups), dim3(NTC), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1172,8 +1496,9 @@ hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s)
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(k_identity<T>, dim3(blocks), dim3(NT), 0, s, a);
     } else {
-        dim3 grid((a.n1 + BT1 - 1) / BT1, (a.n2 + BT2 - 1) / BT2, a.C);
-        hipLaunchKernelGGL(k_blur<T>, grid, dim3(NT), 0, s, a);
+        BlurArgs<T> b = a;
+        tiles_blur(a.n1, a.n2, &b.tx, &b.ty);
+        hipLaunchKernelGGL(k_blur<T>, dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NT), 0, s, b);
     }
     return hipGetLastError();
 }
@@ -1201,7 +1526,7 @@ hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t s)
 template <typename T>
 hipError_t launch_synth_b(const SynthArgs<T> *tab, const int *start, int n, int tiles, Dyn<T> d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_synth_b<T>, dim3(tiles), dim3(NT), 0, s, tab, start, n, d);
+    hipLaunchKernelGGL(k_synth_b<T>, dim3(xcd_grid(tiles)), dim3(NT), 0, s, tab, start, n, d);
     return hipGetLastError();
 }
 
@@ -1209,10 +1534,8 @@ template <typename T>
 hipError_t launch_analysis_b(const AnalysisArgs<T> *tab, const int *start, int n, int tiles, bool joint, Dyn<T> d,
                              hipStream_t s)
 {
-    if (joint)
-        hipLaunchKernelGGL((k_analysis_b<T, true>), dim3(tiles), dim3(NT), 0, s, tab, start, n, d);
-    else
-        hipLaunchKernelGGL((k_analysis_b<T, false>), dim3(tiles), dim3(NT), 0, s, tab, start, n, d);
+    if (joint) return hipErrorInvalidValue;  // lock-step batches use per-channel weights only
+    hipLaunchKernelGGL(k_analysis_b<T>, dim3(xcd_grid(tiles)), dim3(NT), 0, s, tab, start, n, d);
     return hipGetLastError();
 }
 
@@ -1227,7 +1550,7 @@ hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, in
 template <typename T>
 hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_blur_b<T>, dim3(tiles), dim3(NT), 0, s, tab, start, n, ring);
+    hipLaunchKernelGGL(k_blur_b<T>, dim3(xcd_grid(tiles)), dim3(NT), 0, s, tab, start, n, ring);
     return hipGetLastError();
 }
 
