@@ -236,6 +236,16 @@ int pd_timing_enable(int32_t enable);
 int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *launches,
                    double *total_ms, int32_t *rows);
 
+/* Graph replay of the iteration loop (default on).  pd_solve runs the
+ * iterations between its first and last in chunks of 64 whose launches are
+ * captured once into a HIP graph (on a library-owned stream, not the
+ * caller's) and replayed on the caller's stream; the kernels then read the
+ * iteration number from the workspace.  Results are bitwise the same with
+ * and without it.  Executable graphs are cached per argument set (up to 8;
+ * evicting one synchronises the device).  Off while timing is enabled and
+ * in pd_backward's recomputation.  Process-wide; not thread-safe. */
+int pd_graphs_enable(int32_t enable);
+
 /* Short description of a pd_status code. */
 const char *pd_strerror(int32_t status);
 

@@ -13,6 +13,7 @@ from .solver import (  # noqa: F401
     lipschitz,
     pd_apply_op,
     pd_fwt,
+    pd_graphs_enable,
     pd_op1_taps,
     pd_solve,
     pd_solve_batched,

@@ -55,7 +55,7 @@ class pd_image_desc(ctypes.Structure):
 EXPORTS = [
     "pd_workspace_size", "pd_solve", "pd_batched_workspace_size", "pd_solve_batched",
     "pd_backward_workspace_size", "pd_backward", "pd_fwt", "pd_apply_op", "pd_symmlet",
-    "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read",
+    "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
 ]
 
 PD_K_BLUR, PD_K_SYNTH, PD_K_ANALYSIS, PD_K_COARSE, PD_K_OTHER = 1, 2, 3, 4, 5
@@ -105,6 +105,8 @@ def load() -> ctypes.CDLL:
     L.pd_op1_taps.restype = ctypes.c_int
     L.pd_timing_enable.argtypes = [i32]
     L.pd_timing_enable.restype = ctypes.c_int
+    L.pd_graphs_enable.argtypes = [i32]
+    L.pd_graphs_enable.restype = ctypes.c_int
     L.pd_timing_read.argtypes = [i32, P(i32), P(i32), P(ctypes.c_int64), dp, P(i32)]
     L.pd_timing_read.restype = ctypes.c_int
     L.pd_strerror.argtypes = [i32]

@@ -10,6 +10,7 @@
 #include <type_traits>
 #include <utility>
 #include <vector>
+#include <mutex>
 
 #include "pd.h"
 #include "pd_kernels.h"
@@ -88,7 +89,7 @@ Filt<T> make_filt(const pd_wavelet *w)
 // Workspace: approximation pyramid (levels 1..L-1), x, s, flag.
 struct Layout {
     size_t apx[PD_MAXL + 1];
-    size_t x, s, flag, slots, tail, total;
+    size_t x, s, flag, slots, tail, it, total;
 };
 
 Layout layout(const pd_shape *s, size_t es)
@@ -112,6 +113,8 @@ Layout layout(const pd_shape *s, size_t es)
     off = align_up(off + (size_t)PD_RING * 3 * PD_NSLOT * sizeof(double));
     l.tail = off;
     off = align_up(off + 2 * PD_TAIL_MAX * PD_TAIL_MAX * es);
+    l.it = off;  // device iteration number of replayed graphs
+    off = align_up(off + 256);
     l.total = off;
     return l;
 }
@@ -191,6 +194,7 @@ struct Ctx {
     int *flag() const { return (int *)(ws + lay.flag); }
     double *ring() const { return (double *)(ws + lay.slots); }
     double *slots(int it) const { return ring() + (size_t)(it % PD_RING) * 3 * PD_NSLOT; }
+    int *it_dev() const { return (int *)(ws + lay.it); }
 };
 
 // First level lc such that the level lc-1 approximation fits the coarse
@@ -296,6 +300,7 @@ ProxArgs<T> prox_args(const Ctx<T> &c, const T *zc, const T *zp, T *zn, T beta, 
     p.C = c.sh->channels;
     p.slots = slots;
     p.flag = c.flag();
+    p.di = DevIter{nullptr, 0};
     return p;
 }
 
@@ -332,7 +337,7 @@ int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T>
 // Fine synthesis levels lc-1 .. 1 (their approximation input comes from the
 // coarse kernel's output, or from the state when there is no coarse kernel).
 template <typename T>
-int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
+int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIter di = DevIter{nullptr, 0})
 {
     const int L = c.sh->levels, n1 = c.sh->n1, n2 = c.sh->n2;
     for (int lev = c.lc - 1; lev >= 1; --lev) {
@@ -341,6 +346,7 @@ int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
         a.zc = zc;
         a.zp = zp;
         a.beta = beta;
+        a.di = di;
         a.plane = c.N();
         a.pitch = n1;
         a.apx = lev == L ? nullptr : c.apx(lev);
@@ -451,6 +457,149 @@ Ctx<T> make_ctx(const pd_shape *sh, const pd_wavelet *wav, void *workspace, hipS
 // Momentum of y(i) = z(i-1) + b (z(i-1) - z(i-2)):  b_{i-1} = (i-2)/(i+1), 0 for i = 1.
 inline double beta_y(int i) { return i >= 2 ? (double)(i - 2) / (double)(i + 1) : 0.0; }
 
+// One iteration (local index it, global i = i_first + it) of the recursion
+// from (zc, zp) = (z(i-1), z(i-2)); z(i) is written in place of z(i-2).
+// With di.it_dev set the launches take i from device memory (*it_dev +
+// di.it_off == i), so that a captured graph of them replays for any i.
+template <typename T>
+int one_iteration(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, const T *zc,
+                  T *zp, int it, int i, int count, double *stats, int i_first, DevIter di)
+{
+    const pd_shape *sh = c.sh;
+    const hipStream_t st = c.st;
+    const bool coarse = c.lc <= sh->levels;
+    const T beta = (T)beta_y(i);
+    const bool last = it == count - 1;
+    double *sti = stats ? c.slots(it) : nullptr;
+    int rc;
+    // x = Psi y(i); the coarse part was produced by the previous iteration's coarse kernel
+    if (it == 0) {
+        if ((rc = synth_chain<T>(c, zc, zp, beta, c.x())) != PD_OK) return rc;
+    } else if ((rc = synth_fine<T>(c, zc, zp, beta, c.x(), di)) != PD_OK) {
+        return rc;
+    }
+    if ((rc = blur_step<T>(c, op, c.x(), f0, c.s(), sti)) != PD_OK) return rc;
+    // z(i) overwrites z(i-2) in place (each coefficient is read, then written, by one thread)
+    ProxArgs<T> p = prox_args<T>(c, zc, zp, zp, beta, tau, w, sti);
+    p.di = di;
+    if ((rc = analysis_fine<T>(c, c.s(), MODE_PROX, p)) != PD_OK) return rc;
+    if (coarse) {
+        const int ops = COARSE_ANA | COARSE_PROX | (last ? 0 : COARSE_SYN);
+        if ((rc = coarse_step<T>(c, ops, c.s(), c.x(), p, (T)beta_y(i + 1))) != PD_OK) return rc;
+    }
+    if (stats && ((it + 1) % PD_RING == 0 || last)) {  // fold the ring into stats
+        const int cnt = (it % PD_RING) + 1, it0 = it + 1 - cnt;
+        if (di.it_dev) {  // it0 = (*it_dev + it_off - i_first) + 1 - cnt
+            const int sub = i_first - di.it_off - 1 + cnt;
+            PD_TRY_HIP(launch_stats_finalize_dev(c.ring(), stats, di.it_dev, sub, cnt, st));
+        } else {
+            PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_stats_finalize(c.ring(), stats, it0, cnt, st); }));
+        }
+    }
+    return PD_OK;
+}
+
+// ---------------------------------------------------- graph replay ---
+// The middle iterations (neither the first nor the last) run in chunks of
+// PD_RING starting at local index 1 mod PD_RING: the launches of a chunk are
+// captured once into a HIP graph whose kernels read the iteration number
+// from device memory, and that executable graph is replayed for every chunk
+// of this and of later solves with the same arguments (a small cache keyed
+// by everything the launches bake in).  Each replay is preceded by a one-
+// thread kernel that stores the chunk's first iteration number.
+bool g_graphs = true;
+struct CachedGraph {
+    std::vector<char> key;
+    hipGraphExec_t exec;
+};
+std::vector<CachedGraph> g_graph_cache;  // least recently used first
+std::mutex g_graph_mu;
+constexpr size_t GRAPH_CACHE = 8;
+
+template <typename V>
+void key_put(std::vector<char> &k, const V &v)
+{
+    const char *p = (const char *)&v;
+    k.insert(k.end(), p, p + sizeof(V));
+}
+
+hipStream_t capture_stream(int dev)
+{
+    static std::map<int, hipStream_t> streams;  // guarded by g_graph_mu
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = s;
+    return s;
+}
+
+template <typename T>
+hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc,
+                           T *zp, int it_a, int count, double *stats, int i_first)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::vector<char> key;
+    key_put(key, (int)sizeof(T));
+    key_put(key, dev);
+    key_put(key, *c.sh);
+    key_put(key, c.ws);
+    key_put(key, c.lc);
+    key_put(key, c.tail);
+    key_put(key, c.f);
+    key_put(key, op->kind);
+    key_put(key, op->radius);
+    key_put(key, op->taps);
+    key_put(key, w->coeff_w);
+    key_put(key, w->joint);
+    for (int k = 0; k <= c.sh->levels; ++k) key_put(key, w->level_w ? w->level_w[k] : 0.0);
+    key_put(key, tau);
+    key_put(key, f0);
+    key_put(key, zc);
+    key_put(key, zp);
+    key_put(key, stats);
+    key_put(key, i_first);
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (size_t k = 0; k < g_graph_cache.size(); ++k)
+        if (g_graph_cache[k].key == key) {
+            CachedGraph e = g_graph_cache[k];
+            g_graph_cache.erase(g_graph_cache.begin() + k);
+            g_graph_cache.push_back(e);
+            return e.exec;
+        }
+    hipStream_t cs = capture_stream(dev);
+    if (!cs) return nullptr;
+    Ctx<T> cc = c;
+    cc.st = cs;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    int rc = PD_OK;
+    T *a = zc, *b = zp;
+    for (int j = 0; j < PD_RING && rc == PD_OK; ++j) {
+        rc = one_iteration<T>(cc, op, w, tau, f0, a, b, it_a + j, i_first + it_a + j, count, stats, i_first,
+                              DevIter{c.it_dev(), j});
+        std::swap(a, b);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    hipGraphExec_t ex = nullptr;
+    if (rc == PD_OK && e == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
+        ex = nullptr;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (!ex) return nullptr;
+    if (g_graph_cache.size() >= GRAPH_CACHE) {  // the evicted graph may still be queued somewhere
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(g_graph_cache.front().exec);
+        g_graph_cache.erase(g_graph_cache.begin());
+    }
+    g_graph_cache.push_back(CachedGraph{key, ex});
+    return ex;
+}
+
 // Iterations i = i_first .. i_first+count-1 of the recursion from the state
 // (zc, zp) = (z(i_first-1), z(i_first-2)); on return the pointers hold
 // (z(last), z(last-1)).  z(i) is written in place of z(i-2).  stats (nullable)
@@ -460,39 +609,29 @@ template <typename T>
 int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *&zc, T *&zp,
             int i_first, int count, double *stats, T *seg)
 {
-    const pd_shape *sh = c.sh;
     const hipStream_t st = c.st;
-    const bool coarse = c.lc <= sh->levels;
-    const int64_t NC = c.N() * sh->channels;
+    const int64_t NC = c.N() * c.sh->channels;
+    const bool graphs = g_graphs && !g_timing && !seg;
     int rc;
     if (stats && count > 0) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
-    for (int it = 0; it < count; ++it) {
-        const int i = i_first + it;  // global iteration number
-        const T beta = (T)beta_y(i);
-        const bool last = it == count - 1;
-        double *sti = stats ? c.slots(it) : nullptr;
-        // x = Psi y(i); the coarse part was produced by the previous iteration's coarse kernel
-        if (it == 0) {
-            if ((rc = synth_chain<T>(c, zc, zp, beta, c.x())) != PD_OK) return rc;
-        } else if ((rc = synth_fine<T>(c, zc, zp, beta, c.x())) != PD_OK) {
+    for (int it = 0; it < count;) {
+        if (graphs && it % PD_RING == 1 && it + PD_RING < count) {
+            hipGraphExec_t ex = chunk_graph<T>(c, op, w, tau, f0, zc, zp, it, count, stats, i_first);
+            if (ex) {
+                PD_TRY_HIP(launch_set_int(c.it_dev(), i_first + it, st));
+                PD_TRY_HIP(hipGraphLaunch(ex, st));
+                it += PD_RING;  // an even number of swaps: (zc, zp) unchanged
+                continue;
+            }
+        }
+        if ((rc = one_iteration<T>(c, op, w, tau, f0, zc, zp, it, i_first + it, count, stats, i_first,
+                                   DevIter{nullptr, 0})) != PD_OK)
             return rc;
-        }
-        if ((rc = blur_step<T>(c, op, c.x(), f0, c.s(), sti)) != PD_OK) return rc;
-        // z(i) overwrites z(i-2) in place (each coefficient is read, then written, by one thread)
-        ProxArgs<T> p = prox_args<T>(c, zc, zp, zp, beta, tau, w, sti);
-        if ((rc = analysis_fine<T>(c, c.s(), MODE_PROX, p)) != PD_OK) return rc;
-        if (coarse) {
-            const int ops = COARSE_ANA | COARSE_PROX | (last ? 0 : COARSE_SYN);
-            if ((rc = coarse_step<T>(c, ops, c.s(), c.x(), p, (T)beta_y(i + 1))) != PD_OK) return rc;
-        }
-        if (stats && ((it + 1) % PD_RING == 0 || last)) {  // fold the ring into stats
-            const int cnt = (it % PD_RING) + 1, it0 = it + 1 - cnt;
-            PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_stats_finalize(c.ring(), stats, it0, cnt, st); }));
-        }
         if (seg) PD_TRY_HIP(launch_copy<T>(zp, seg + (int64_t)it * NC, NC, st));
         T *t = zc;
         zc = zp;
         zp = t;
+        ++it;
     }
     return PD_OK;
 }
@@ -695,6 +834,7 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
             t_init_ana[lev].add(a, tiles);
 
             SynthArgs<T> sa;
+            sa.di = DevIter{nullptr, 0};
             sa.f = f;
             sa.zc = zAb;
             sa.zp = zBb;
@@ -928,6 +1068,12 @@ extern "C" int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32
                                       (double *)f_out_packed, stats, workspace, ws_bytes, st);
 }
 
+
+extern "C" int pd_graphs_enable(int32_t enable)
+{
+    g_graphs = enable != 0;
+    return PD_OK;
+}
 
 extern "C" int pd_timing_enable(int32_t enable)
 {

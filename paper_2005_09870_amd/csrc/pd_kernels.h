@@ -27,11 +27,19 @@ struct Filt {
 // `plane`); the approximation band comes from `apx` (dense M2c x M1c per
 // channel, stride apx_plane) or, if apx == nullptr, from the coefficient
 // state at [0,M2c) x [0,M1c).
+// Iteration number read from device memory when a launch sits in a replayed
+// graph: i = *it_dev + it_off (it_dev == nullptr: the by-value momenta apply).
+struct DevIter {
+    const int *it_dev;
+    int it_off;
+};
+
 template <typename T>
 struct SynthArgs {
     Filt<T> f;
     const T *zc, *zp;
     T beta;
+    DevIter di;
     int64_t plane;
     int pitch;
     const T *apx;
@@ -59,6 +67,7 @@ struct ProxArgs {
     double *slots;          // this iteration's [3][PD_NSLOT] partial sums (nullptr: no
                             // statistics): 1/2||r||^2, sum w|y|, sum (z-y)^2
     int *flag;              // set to 1 if a prox argument is not finite
+    DevIter di;             // beta (and the coarse kernel's beta_next) from the device iteration
 };
 
 // One analysis level: fine input 2*M1c x 2*M2c -> four coarse M1c x M2c
@@ -163,6 +172,9 @@ void tiles_synth(int M1c, int M2c, int *tx, int *ty);
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty);
 void tiles_blur(int n1, int n2, int *tx, int *ty);
 hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s);
+// same with it0 = *it_dev - sub (graph replay)
+hipError_t launch_stats_finalize_dev(double *ring, double *stats, const int *it_dev, int sub, int count, hipStream_t s);
+hipError_t launch_set_int(int *dst, int v, hipStream_t s);
 template <typename T> hipError_t launch_fill(T *dst, T v, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, int64_t n, hipStream_t s);

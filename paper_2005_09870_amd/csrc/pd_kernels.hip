@@ -926,6 +926,17 @@ __global__ __launch_bounds__(256) void k_stats_finalize(double *ring, double *st
     finalize_entry(ring + (size_t)(it % PD_RING) * 3 * PD_NSLOT, stats + 3 * (size_t)it);
 }
 
+__global__ __launch_bounds__(256) void k_stats_finalize_dev(double *ring, double *stats, const int *it_dev, int sub)
+{
+    const int it = *it_dev - sub + blockIdx.x;
+    finalize_entry(ring + (size_t)(it % PD_RING) * 3 * PD_NSLOT, stats + 3 * (size_t)it);
+}
+
+__global__ void k_set_int(int *dst, int v)
+{
+    if (threadIdx.x == 0) dst[0] = v;
+}
+
 __global__ __launch_bounds__(256) void k_stats_finalize_b(double *const *__restrict__ ring,
                                                            double *const *__restrict__ stats, int it0)
 {
@@ -969,15 +980,13 @@ constexpr int RB_PER_WAVE = (BR2 / RVH + NT / 64 - 1) / (NT / 64);  // r-pass ro
 
 template <typename T>
 struct BlurLds {
-    T sA[BX2 * XP];           // x, later r (BR2 x TP)
-    T sB[BX2 * TP];           // t, later u (BT2 x TP)
-    T sK[BX2][2 * RM + 2];    // profiles of the rows of x / t
-    int rmax[NT / 64];        // per wave: largest |d| with a non-zero profile entry
+    alignas(16) T sA[BX2 * XP];         // x, later r (BR2 x TP)
+    alignas(16) T sB[BX2 * TP];         // t, later u (BT2 x TP)
+    alignas(16) T sK[BX2][2 * RM + 2];  // profiles of the rows of x / t
 };
 
-// RT: compile-time bound on the half-width of every profile this tile reads
-// (taps beyond it are zero), so only |d| <= RT is visited.
-template <typename T, int RT>
+// The four passes on a staged tile (profiles zero-padded to RM).
+template <typename T>
 __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, int bz, BlurLds<T> &lds,
                                           const T (&f0pre)[RB_PER_WAVE][RVH])
 {
@@ -997,10 +1006,10 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
         T xv[4 + 2 * RM];
 #pragma unroll
         for (int j = 0; j < 4 + 2 * RM; ++j)
-            xv[j] = (j >= RM - RT && j < RM + RT + 4) ? sA[r * XP + 4 * blk + j] : T(0);
+            xv[j] = sA[r * XP + 4 * blk + j];
         T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int m = RM - RT; m <= RM + RT; ++m) {
+        for (int m = 0; m <= 2 * RM; ++m) {
             T k = sK[r][2 * RM - m];  // d = RM - m
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = fma(k, xv[q + m], acc[q]);
@@ -1022,13 +1031,13 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 #pragma unroll
         for (int k = 0; k < RVH; ++k) acc[k] = T(0);
 #pragma unroll
-        for (int m = RM - RT; m < RVH + RM + RT; ++m) {
+        for (int m = 0; m < RVH + 2 * RM; ++m) {
             const T tv = sB[(r0 + m) * TP + lane];
             const T *kr = &sK[r0 + m][RM];  // profile of source row r0+m (broadcast reads)
 #pragma unroll
             for (int k = 0; k < RVH; ++k) {
                 const int d = k + RM - m;  // displacement x2 - y2
-                if (d >= -RT && d <= RT) acc[k] = fma(kr[d], tv, acc[k]);
+                if (d >= -RM && d <= RM) acc[k] = fma(kr[d], tv, acc[k]);
             }
         }
 #pragma unroll
@@ -1055,13 +1064,13 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
         T rv[UVH + 2 * RM];
 #pragma unroll
         for (int j = 0; j < UVH + 2 * RM; ++j)
-            rv[j] = (j >= RM - RT && j < UVH + RM + RT) ? sA[(q0 + j) * TP + lane] : T(0);
+            rv[j] = sA[(q0 + j) * TP + lane];
 #pragma unroll
         for (int k = 0; k < UVH; ++k) {
             const T *kr = &sK[q0 + k + 2 * RM][RM];  // profile of output row o2+q0+k
             T acc = T(0);
 #pragma unroll
-            for (int d = -RT; d <= RT; ++d) acc = fma(kr[d], rv[k + RM + d], acc);
+            for (int d = -RM; d <= RM; ++d) acc = fma(kr[d], rv[k + RM + d], acc);
             sB[(q0 + k) * TP + lane] = acc;
         }
     }
@@ -1075,11 +1084,11 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 #pragma unroll
         for (int j = 0; j < 4 + 2 * RM; ++j) {
             int c = 4 * blk + j;
-            uv[j] = (c < BW && j >= RM - RT && j < RM + RT + 4) ? sB[q * TP + c] : T(0);
+            uv[j] = c < BW ? sB[q * TP + c] : T(0);
         }
         T acc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int m = RM - RT; m <= RM + RT; ++m) {
+        for (int m = 0; m <= 2 * RM; ++m) {
             T k = sK[q + 2 * RM][m];  // d = m - RM
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[j] = fma(k, uv[j + m], acc[j]);
@@ -1094,8 +1103,8 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
     if (a.slots) block_slot_add<1, NT>(st, a.slots);
 }
 
-// Stages the x tile and the row profiles in LDS, then runs the passes with
-// the taps bounded by the widest profile the tile reads.
+// Stages the x tile and the row profiles in LDS (with f0 prefetched for the
+// r pass), then runs the passes.
 template <typename T>
 __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, int bz)
 {
@@ -1109,7 +1118,6 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    int rad = 0;
     T f0pre[RB_PER_WAVE][RVH];
     {
         // load: lane = column (two chunks: 64 + 18), wave = rows (17 each)
@@ -1151,11 +1159,7 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
             const int e = tid + i * NT;
             const int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
             if (e < KE) sK[r][d + RM] = kv[i];
-            if (kv[i] != T(0)) rad = max(rad, abs(d));
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) rad = max(rad, __shfl_xor(rad, off));
-        if (lane == 0) lds.rmax[wv] = rad;
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int r = wv + i * (NT / 64);
@@ -1164,14 +1168,7 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
         }
     }
     __syncthreads();
-    int rt = lds.rmax[0];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) rt = max(rt, lds.rmax[w]);
-    rt = __builtin_amdgcn_readfirstlane(rt);
-    if (rt <= 4)
-        blur_body<T, 4>(a, bx, by, bz, lds, f0pre);
-    else
-        blur_body<T, RM>(a, bx, by, bz, lds, f0pre);
+    blur_body<T>(a, bx, by, bz, lds, f0pre);
 }
 
 // H = Id: s = r = x - f0.
@@ -1309,10 +1306,19 @@ __device__ __forceinline__ int xcd_tile(int total)
 }
 __host__ __device__ inline int xcd_grid(int total) { return NXCD * ((total + NXCD - 1) / NXCD); }
 
+// Momentum of y(i) = z(i-1) + b (z(i-1) - z(i-2)): b = (i-2)/(i+1), 0 for i = 1
+// (Appendix A.1), in double then rounded to T exactly as on the host.
+template <typename T>
+__device__ __forceinline__ T beta_at(int i)
+{
+    return i >= 2 ? (T)((double)(i - 2) / (double)(i + 1)) : T(0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_synth(SynthArgs<T> a)
 {
-    const Live<T> lv{a.zc, a.zp, nullptr, a.beta, T(0), nullptr};
+    const T beta = a.di.it_dev ? beta_at<T>(*a.di.it_dev + a.di.it_off) : a.beta;
+    const Live<T> lv{a.zc, a.zp, nullptr, beta, T(0), nullptr};
     const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
     if (t < 0) return;
     synth_body<T>(a, lv, t % a.tx, t / a.tx, blockIdx.y);
@@ -1321,6 +1327,10 @@ __global__ __launch_bounds__(NT) void k_synth(SynthArgs<T> a)
 template <typename T>
 __device__ __forceinline__ Live<T> live_of(const ProxArgs<T> &p, T beta_next)
 {
+    if (p.di.it_dev) {
+        const int i = *p.di.it_dev + p.di.it_off;
+        return Live<T>{p.zc, p.zp, p.zn, beta_at<T>(i), beta_at<T>(i + 1), p.slots};
+    }
     return Live<T>{p.zc, p.zp, p.zn, p.beta, beta_next, p.slots};
 }
 
@@ -1621,6 +1631,18 @@ void tiles_blur(int n1, int n2, int *tx, int *ty) { *tx = (n1 + BT1 - 1) / BT1; 
 hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stats_finalize, dim3(count), dim3(256), 0, s, ring, stats, it0);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_finalize_dev(double *ring, double *stats, const int *it_dev, int sub, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stats_finalize_dev, dim3(count), dim3(256), 0, s, ring, stats, it_dev, sub);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int *dst, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, dst, v);
     return hipGetLastError();
 }
 

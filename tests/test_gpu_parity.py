@@ -180,6 +180,33 @@ def test_resume_is_bitwise():
     assert torch.equal(full["z_prev"], b["z_prev"])
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_graph_replay_is_bitwise(dtype):
+    """The middle iterations replayed from a captured graph (chunks of 64 that
+    read the iteration number from the workspace) equal eager launches bit for
+    bit, for a fresh capture, a cache hit and a resumed solve (iter_offset)."""
+    pb, f0, case = _problem(96, 64, seed=9)
+    tau = O.step_size(pb)
+    runs = {}
+    try:
+        for on in (False, True):
+            P.pd_graphs_enable(on)
+            a = _gpu_solve(pb, f0, case, tau, 200, dtype, stats=True)
+            b = _gpu_solve(pb, f0, case, tau, 200, dtype, stats=True)  # second call: cached graph
+            c = _gpu_solve(pb, f0, case, tau, 150, dtype, z_cur=a["z_cur"].clone(),
+                           z_prev=a["z_prev"].clone(), init=False, iter_offset=200)
+            runs[on] = (a, b, c)
+    finally:
+        P.pd_graphs_enable(True)
+    for k in ("f", "z_cur", "z_prev"):
+        for r in range(3):
+            assert torch.equal(runs[False][r][k], runs[True][r][k]), (k, r)
+        assert torch.equal(runs[True][0][k], runs[True][1][k])
+    # statistics: FP64 partial sums added atomically (order-dependent rounding)
+    for r in range(2):
+        np.testing.assert_allclose(_np(runs[True][r]["stats"]), _np(runs[False][r]["stats"]), rtol=1e-12)
+
+
 def test_nonfinite_is_reported():
     pb, f0, case = _problem(64, 64, seed=8)
     f0 = f0.copy()
