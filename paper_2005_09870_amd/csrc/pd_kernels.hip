@@ -80,6 +80,21 @@ __device__ __forceinline__ double wave_sum(double x)
     return (lane_d(x, 0) + lane_d(x, 16)) + (lane_d(x, 32) + lane_d(x, 48));
 }
 
+// x as a wave-uniform (scalar register) value; used so that selects between
+// argument-block entries do not become per-lane loads from the argument block.
+template <typename T>
+__device__ __forceinline__ T uniform(T x)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+    } else {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+        const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+}
+
 // Block-wide sums of NV doubles; thread q adds sum q to row q of the
 // [NV][PD_NSLOT] slot array at a slot chosen by the block index, so that
 // concurrent workgroups rarely hit the same address.  Contains a barrier.
@@ -386,9 +401,11 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
             for (int cc = 0; cc < NC; ++cc) lv.zn[(int64_t)(ch0 + cc) * p.plane + idx] = res[cc][2 * q + hx2];
             continue;
         }
-        const int band = (b == 0) ? 0 : a.band_detail;
+        // band weight: a select between two uniform table entries (a per-lane
+        // index into the argument block would be a vector load per lane)
+        const T wband = b == 0 ? uniform(p.wlev[0]) : uniform(p.wlev[a.band_detail]);
         if (!JOINT) {
-            T w = p.wmap ? wr[o] : p.wlev[band];
+            T w = p.wmap ? wr[o] : wband;
             T y = zcr[0][o] + lv.beta * (zcr[0][o] - zpr[0][o]);
             lv.zn[(int64_t)ch0 * p.plane + idx] = prox1(y, res[0][2 * q + hx2], p.tau, w, st, bad);
         } else {
@@ -402,7 +419,7 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
                 nv = fma(vv[cc], vv[cc], nv);
                 ny += (double)yv[cc] * (double)yv[cc];
             }
-            T w = p.wlev[band];
+            T w = wband;
             T nrm = sqrt(nv);
             T sc = nrm > T(0) ? T(1) - p.tau * w / nrm : T(0);
             sc = sc > T(0) ? sc : T(0);
@@ -794,6 +811,8 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     const bool use_w = prox && p.wmap;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) wr[k] = ld(p.wmap, use_w, (int64_t)ch0 * p.plane + gi[k]);
+    __shared__ T wtab[PD_MAXL + 1];  // band weights, read per coefficient by the prox
+    if (tid <= PD_MAXL) wtab[tid] = p.wlev[tid];
     constexpr int MPT = 2 * PD_TAIL_MAX * PD_TAIL_MAX / NTC;
     T mv[MPT];
     const int nm = a.tail ? 2 * tn * tn : 0;
@@ -836,17 +855,18 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         for (int k = 0; k < CPT; ++k) {
             if (tid + k * NTC >= cnt) continue;
             const int r = rr[k], c = cr[k];
-            // band index: finest level of the block whose detail region holds (r, c)
+            // band weight: finest level of the block whose detail region holds (r, c)
             int band = 0;
             for (int lev = 0; lev < a.nlev; ++lev)
                 if (r >= (m2 >> (lev + 1)) || c >= (m1 >> (lev + 1))) {
                     band = a.band_top - lev;
                     break;
                 }
+            const T wband = wtab[band];
             const int li = r * G::PA + c;
             if (NCH == 1 && !p.joint) {
                 T *A = home(0);
-                T w = p.wmap ? wr[k] : p.wlev[band];
+                T w = p.wmap ? wr[k] : wband;
                 T y = zcr[0][k] + lv.beta * (zcr[0][k] - zpr[0][k]);
                 T z = prox1(y, A[li], p.tau, w, st, bad);
                 lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
@@ -862,7 +882,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                     nv = fma(vv[cc], vv[cc], nv);
                     ny += (double)yv[cc] * (double)yv[cc];
                 }
-                T w = p.wlev[band];
+                T w = wband;
                 T nrm = sqrt(nv);
                 T sc = nrm > T(0) ? T(1) - p.tau * w / nrm : T(0);
                 sc = sc > T(0) ? sc : T(0);
