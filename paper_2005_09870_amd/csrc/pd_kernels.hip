@@ -109,11 +109,12 @@ __device__ void block_slot_add(double (&v)[NV], double *slots)
         if (lane == 0) red[q][wv] = a;
     }
     __syncthreads();
-    if (threadIdx.x < NV) {
-        double a = 0.0;
-        for (int k = 0; k < NTH / 64; ++k) a += red[threadIdx.x][k];
+    static_assert(NV <= 4 && NTH / 64 <= 16, "one DPP row per sum");
+    if (wv == 0) {  // lane = 16 q + k: row q sums the NTH/64 wave partials of sum q
+        const int q = lane >> 4, k = lane & 15;
+        const double a = dpp_row_sum((q < NV && k < NTH / 64) ? red[q < NV ? q : 0][k] : 0.0);
         const unsigned blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        atomicAdd(slots + threadIdx.x * PD_NSLOT + (blk % PD_NSLOT), a);
+        if (q < NV && k == 0) atomicAdd(slots + q * PD_NSLOT + (blk % PD_NSLOT), a);
     }
 }
 
@@ -670,7 +671,7 @@ __device__ __forceinline__ void syn_level(const T *D, T *E, T *Dn, int M2n, T *A
 // The tail: out = Mat in over the tM2 x tM1 approximation at the top-left of A
 // (tn <= PD_TAIL_MAX values), 16 threads per output, fixed summation order.
 template <typename T>
-__device__ void tail_apply(T *A, int tM1, int tM2, const T *Mat)
+__device__ void tail_apply(T *A, int tM1, int tM2, const T *Mat, T *Dout = nullptr, int DM2 = 0)
 {
     using G = CGeom<T>;
     const int tn = tM1 * tM2;
@@ -689,7 +690,10 @@ __device__ void tail_apply(T *A, int tM1, int tM2, const T *Mat)
     if (i < tn && q == 0) {
         int r, c;
         split(i, tM1, r, c);
-        A[r * G::PA + c] = acc;
+        if (Dout)  // approximation band of the coarsest pass-by-pass synthesis level
+            put_d<T>(Dout, DM2, r, c, acc);
+        else
+            A[r * G::PA + c] = acc;
     }
     __syncthreads();
 }
@@ -697,10 +701,10 @@ __device__ void tail_apply(T *A, int tM1, int tM2, const T *Mat)
 // Analysis of the block in A: kw levels pass by pass, then the tail as one matrix.
 template <typename T>
 __device__ void coarse_analysis(T *A, T *B, T *C, int m1, int m2, int nlev, const Filt<T> &f, int kw, int tM1,
-                                int tM2, const T *Mat)
+                                int tM2, const T *Mat, bool in_c)
 {
     using G = CGeom<T>;
-    if (kw > 0) {
+    if (kw > 0 && !in_c) {  // (in_c: the input was staged in C at load time)
         for (int e = threadIdx.x; e < m1 * m2; e += NTC) {
             int r, c;
             split(e, m1, r, c);
@@ -717,11 +721,15 @@ __device__ void coarse_analysis(T *A, T *B, T *C, int m1, int m2, int nlev, cons
 // coarse to fine; the result replaces the block in A.
 template <typename T>
 __device__ void coarse_synthesis(T *A, T *D, T *E, int m1, int m2, int nlev, const Filt<T> &f, int kw, int tM1,
-                                 int tM2, const T *MatT)
+                                 int tM2, const T *MatT, bool routed)
 {
+    using G = CGeom<T>;
+    if (routed) {  // the details are already in D: only the tail remains, straight into D
+        if (kw < nlev) tail_apply<T>(A, tM1, tM2, MatT, D + drow_base<T>(m2, kw - 1) * G::PB, m2 >> (kw - 1));
+        goto levels;
+    }
     if (kw < nlev) tail_apply<T>(A, tM1, tM2, MatT);
     if (kw == 0) return;
-    using G = CGeom<T>;
     // every coefficient of the block goes to the input of the level that reads it
     for (int e = threadIdx.x; e < m1 * m2; e += NTC) {
         int r, c;
@@ -735,6 +743,7 @@ __device__ void coarse_synthesis(T *A, T *D, T *E, int m1, int m2, int nlev, con
         put_d<T>(D + drow_base<T>(m2, lev) * G::PB, m2 >> lev, r, c, A[r * G::PA + c]);
     }
     __syncthreads();
+levels:
     for (int lev = kw - 1; lev >= 0; --lev) {
         const T *Dl = D + drow_base<T>(m2, lev) * G::PB;
         T *Dn = lev > 0 ? D + drow_base<T>(m2, lev - 1) * G::PB : nullptr;
@@ -779,6 +788,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     const int tid = threadIdx.x;
     const bool ana = (a.ops & COARSE_ANA) != 0, prox = (a.ops & COARSE_PROX) != 0;
     const bool need_z = !ana || prox;
+    const bool routed = NCH == 1 && ana && prox && (a.ops & COARSE_SYN) && a.kw > 0;
     auto home = [&](int cc) { return lds + L.a + cc * m2 * G::PA; };
 
     // 1. every global load at once (clamped indices, no data-dependent branch):
@@ -826,19 +836,28 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         const int e = tid + k * NTC;
         if (e < nm) Mat[e] = mv[k];
     }
+    // one channel with pass-by-pass levels: the analysis input goes straight
+    // into C with its wrapped columns
+    const bool in_c = NCH == 1 && ana && a.kw > 0;
 #pragma unroll
     for (int cc = 0; cc < NCH; ++cc)
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
-            if (tid + k * NTC < cnt)
-                home(cc)[rr[k] * G::PA + cr[k]] =
-                    ana ? v[cc][k] : zcr[cc][k] + lv.beta * (zcr[cc][k] - zpr[cc][k]);
+            if (tid + k * NTC < cnt) {
+                if (in_c) {
+                    const T x = v[cc][k];
+                    copies(cr[k] + G::HA, m1, 0, m1 + 2 * G::HA + 2, [&](int q) { Cb[rr[k] * G::PC + q] = x; });
+                } else {
+                    home(cc)[rr[k] * G::PA + cr[k]] =
+                        ana ? v[cc][k] : zcr[cc][k] + lv.beta * (zcr[cc][k] - zpr[cc][k]);
+                }
+            }
     __syncthreads();
 
     if (ana) {
 #pragma unroll
         for (int cc = 0; cc < NCH; ++cc)
-            coarse_analysis<T>(home(cc), B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat);
+            coarse_analysis<T>(home(cc), B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat, in_c);
         if (!prox) {  // plain forward transform
 #pragma unroll
             for (int cc = 0; cc < NCH; ++cc)
@@ -848,7 +867,9 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                         lv.zn[(int64_t)(ch0 + cc) * p.plane + gi[k]] = home(cc)[rr[k] * G::PA + cr[k]];
             return;
         }
-        // 2. gradient step + prox + momentum on the coarse block
+        // 2. gradient step + prox + momentum on the coarse block; with one
+        //    channel and a synthesis to follow, y(i+1) is routed to where the
+        //    synthesis reads it
         double st[2] = {0.0, 0.0};
         bool bad = false;
 #pragma unroll
@@ -870,7 +891,18 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 T y = zcr[0][k] + lv.beta * (zcr[0][k] - zpr[0][k]);
                 T z = prox1(y, A[li], p.tau, w, st, bad);
                 lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
-                A[li] = z + lv.beta_next * (z - zcr[0][k]);
+                const T yn = z + lv.beta_next * (z - zcr[0][k]);
+                if (!routed || (a.kw < a.nlev && r < a.tM2 && c < a.tM1)) {
+                    A[li] = yn;  // the tail's input (or the whole block)
+                } else {  // straight into the synthesis input of the level that reads it
+                    int lev = a.kw - 1;
+                    for (int j = 0; j < a.kw - 1; ++j)
+                        if (r >= (m2 >> (j + 1)) || c >= (m1 >> (j + 1))) {
+                            lev = j;
+                            break;
+                        }
+                    put_d<T>(B + drow_base<T>(m2, lev) * G::PB, m2 >> lev, r, c, yn);
+                }
             } else {
                 T yv[NCH], vv[NCH];
                 T nv = T(0);
@@ -906,7 +938,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
 #pragma unroll
     for (int cc = 0; cc < NCH; ++cc) {
         T *A = home(cc);
-        coarse_synthesis<T>(A, B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat + tn * tn);
+        coarse_synthesis<T>(A, B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat + tn * tn, routed);
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int e = tid + k * NTC;
