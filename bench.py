@@ -61,6 +61,27 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
     return 0.0
 
 
+def profiled_traffic(key: str):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of kernel `key` (e.g.
+    'coarse/4') from the committed rocprofv3 summary, or None when the kernel
+    sources changed since those counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", "fista512_traffic.md")).read()
+        line = next(l for l in text.splitlines() if l.startswith("traffic-json: "))
+        rec = json.loads(line[len("traffic-json: "):])
+        h = hashlib.sha256()
+        for f in ("pd_kernels.hip", "pd_kernels.h"):
+            with open(os.path.join(root, "paper_2005_09870_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("sources_sha256") != h.hexdigest():
+        return None
+    return rec.get("bytes_per_launch", {}).get(key)
+
+
 def make_problem(torch, P, SI, n=512, seed=2):
     case = SI.case_512(seed)
     dev = "cuda"
@@ -310,8 +331,9 @@ def main():
         rw["alg_bytes_per_launch"] = alg_bytes(rw["kernel"], rw["level"], n, n, 1, 4, False)
     dom = max(rows, key=lambda rw: rw["total_ms"])
     achieved = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
+    traffic = profiled_traffic(f"{dom['kernel']}/{dom['level']}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"{dom['kernel']}" + (f" level {dom['level']}" if dom["level"] else ""),
                 "avg_us": round(dom["avg_us"], 3), "launches_per_step": dom["launches"],
                 "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
