@@ -195,10 +195,13 @@ def batched_vs_per_image(torch, P, SI, h, iters, count):
             "speedup": round(res["batched"] / res["per_image"], 3), "bitwise_equal": same}
 
 
-def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20):
+def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20, streams=4):
     """16 x 256^2, per-coefficient weights softplus(theta), 200 unrolled
     iterations, L = 1/2 ||f - clean||^2: forward solve + pd_backward per image
-    (checkpoint every 20 iterations).  Mpixel-iter/s = count n^2 iters / time."""
+    (checkpoint every 20 iterations).  Mpixel-iter/s = count n^2 iters / time.
+    Reported twice: images one after another on one stream, and the batch
+    spread round-robin over `streams` torch streams (each image's solves and
+    its autograd backward run on its stream; the images are independent)."""
     cases = SI.case_grad(count, n=n)
     dev = "cuda"
     op = P.Operator.op1(n, dtype=torch.float32, device=dev)
@@ -210,25 +213,46 @@ def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20):
         th = torch.as_tensor(c.theta, dtype=torch.float32, device=dev)
         items.append((f0, th, clean, c.levels))
 
-    def run():
+    def one(f0, th, clean, L):
+        f0r = f0.clone().requires_grad_(True)
+        thr = th.clone().requires_grad_(True)
+        f = P.solve_autograd(f0r, thr, op, h, L, tau, iters, checkpoint_every=ce)
+        loss = 0.5 * ((f - clean) ** 2).sum()
+        loss.backward()
+        return f0r.grad, thr.grad
+
+    def run_seq():
+        return [one(*it) for it in items]
+
+    pool = [torch.cuda.Stream() for _ in range(streams)]
+
+    def run_streams():
+        main = torch.cuda.current_stream()
         gs = []
-        for f0, th, clean, L in items:
-            f0r = f0.clone().requires_grad_(True)
-            thr = th.clone().requires_grad_(True)
-            f = P.solve_autograd(f0r, thr, op, h, L, tau, iters, checkpoint_every=ce)
-            loss = 0.5 * ((f - clean) ** 2).sum()
-            loss.backward()
-            gs.append((f0r.grad, thr.grad))
+        for k, it in enumerate(items):
+            s = pool[k % streams]
+            s.wait_stream(main)
+            with torch.cuda.stream(s):
+                gs.append(one(*it))
+        for s in pool:
+            main.wait_stream(s)
         return gs
 
-    run()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    run()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
+    res = {}
+    for name, fn in (("seq", run_seq), ("streams", run_streams)):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        gs = fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t, gs)
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+               for a, b in zip(res["seq"][1], res["streams"][1]))
+    rate = lambda dt: round(count * n * n * iters / dt / 1e6, 1)
     return {"workload": f"{count} x {n}^2 FP32, softplus weights, {iters} iterations, checkpoint {ce}",
-            "fwd_bwd_mpx_it_s": round(count * n * n * iters / dt / 1e6, 1), "ms": round(1e3 * dt, 2)}
+            "fwd_bwd_mpx_it_s": rate(res["streams"][0]), "ms": round(1e3 * res["streams"][0], 2),
+            "streams": streams, "sequential_mpx_it_s": rate(res["seq"][0]),
+            "sequential_ms": round(1e3 * res["seq"][0], 2), "bitwise_equal": same}
 
 
 def colour_case(torch, P, SI, h, iters, n=2048):

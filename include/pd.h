@@ -241,9 +241,11 @@ int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *l
  * captured once into a HIP graph (on a library-owned stream, not the
  * caller's) and replayed on the caller's stream; the kernels then read the
  * iteration number from the workspace.  Results are bitwise the same with
- * and without it.  Executable graphs are cached per argument set (up to 8;
- * evicting one synchronises the device).  Off while timing is enabled and
- * in pd_backward's recomputation.  Process-wide; not thread-safe. */
+ * and without it.  A chunk is captured when the call replays it at least 4
+ * times (>= 258 iterations) and reused by later calls with the same
+ * arguments (up to 32 cached; an evicted graph is destroyed once its last
+ * launch has completed).  Off while timing is enabled and in pd_backward's
+ * recomputation.  Process-wide; not thread-safe. */
 int pd_graphs_enable(int32_t enable);
 
 /* Short description of a pd_status code. */

@@ -511,10 +511,26 @@ bool g_graphs = true;
 struct CachedGraph {
     std::vector<char> key;
     hipGraphExec_t exec;
+    hipEvent_t done;  // recorded after every launch of exec
 };
 std::vector<CachedGraph> g_graph_cache;  // least recently used first
+std::vector<CachedGraph> g_graph_retired;  // evicted, destroyed once their last launch completed
+
+void sweep_retired()
+{
+    for (size_t k = 0; k < g_graph_retired.size();) {
+        if (hipEventQuery(g_graph_retired[k].done) == hipSuccess) {
+            (void)hipGraphExecDestroy(g_graph_retired[k].exec);
+            (void)hipEventDestroy(g_graph_retired[k].done);
+            g_graph_retired.erase(g_graph_retired.begin() + k);
+        } else {
+            ++k;
+        }
+    }
+    (void)hipGetLastError();
+}
 std::mutex g_graph_mu;
-constexpr size_t GRAPH_CACHE = 8;
+constexpr size_t GRAPH_CACHE = 32;
 
 template <typename V>
 void key_put(std::vector<char> &k, const V &v)
@@ -534,9 +550,12 @@ hipStream_t capture_stream(int dev)
     return s;
 }
 
+// Returns the executable graph for the chunk starting at local index it_a
+// (and the event to record after launching it), capturing it if allowed.
 template <typename T>
 hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc,
-                           T *zp, int it_a, int count, double *stats, int i_first)
+                           T *zp, int it_a, int count, double *stats, int i_first, bool may_capture,
+                           hipEvent_t *done)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
@@ -561,13 +580,16 @@ hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weig
     key_put(key, stats);
     key_put(key, i_first);
     std::lock_guard<std::mutex> lock(g_graph_mu);
+    sweep_retired();
     for (size_t k = 0; k < g_graph_cache.size(); ++k)
         if (g_graph_cache[k].key == key) {
             CachedGraph e = g_graph_cache[k];
             g_graph_cache.erase(g_graph_cache.begin() + k);
             g_graph_cache.push_back(e);
+            *done = e.done;
             return e.exec;
         }
+    if (!may_capture) return nullptr;
     hipStream_t cs = capture_stream(dev);
     if (!cs) return nullptr;
     Ctx<T> cc = c;
@@ -591,12 +613,18 @@ hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weig
     if (g) (void)hipGraphDestroy(g);
     (void)hipGetLastError();
     if (!ex) return nullptr;
-    if (g_graph_cache.size() >= GRAPH_CACHE) {  // the evicted graph may still be queued somewhere
-        (void)hipDeviceSynchronize();
-        (void)hipGraphExecDestroy(g_graph_cache.front().exec);
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (g_graph_cache.size() >= GRAPH_CACHE) {  // it may still be queued: retire, destroy later
+        g_graph_retired.push_back(g_graph_cache.front());
         g_graph_cache.erase(g_graph_cache.begin());
     }
-    g_graph_cache.push_back(CachedGraph{key, ex});
+    g_graph_cache.push_back(CachedGraph{key, ex, ev});
+    *done = ev;
     return ex;
 }
 
@@ -614,12 +642,19 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
     const bool graphs = g_graphs && !g_timing && !seg;
     int rc;
     if (stats && count > 0) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
+    // capturing pays off only when the graph is replayed several times
+    int chunks = 0;
+    for (int it = 1; it + PD_RING < count; it += PD_RING) ++chunks;
+    const bool may_capture = chunks >= 4;
     for (int it = 0; it < count;) {
         if (graphs && it % PD_RING == 1 && it + PD_RING < count) {
-            hipGraphExec_t ex = chunk_graph<T>(c, op, w, tau, f0, zc, zp, it, count, stats, i_first);
+            hipEvent_t done = nullptr;
+            hipGraphExec_t ex =
+                chunk_graph<T>(c, op, w, tau, f0, zc, zp, it, count, stats, i_first, may_capture, &done);
             if (ex) {
                 PD_TRY_HIP(launch_set_int(c.it_dev(), i_first + it, st));
                 PD_TRY_HIP(hipGraphLaunch(ex, st));
+                PD_TRY_HIP(hipEventRecord(done, st));
                 it += PD_RING;  // an even number of swaps: (zc, zp) unchanged
                 continue;
             }

@@ -1025,10 +1025,11 @@ constexpr int BX2 = BT2 + 4 * RM;      // 68 x / t rows
 constexpr int BR2 = BT2 + 2 * RM;      // 50 r rows
 constexpr int XP = 84;                 // LDS pitch of x (multiple of 4)
 constexpr int TP = 68;                 // LDS pitch of t, r, u (multiple of 4)
-static_assert(BX2 % (NT / 64) == 0 && BX1 <= 128 && BX1 > 64, "blur load rows/columns");
+constexpr int NTB = 512;               // blur workgroup: 8 waves (two per SIMD hide LDS latency)
+static_assert(BX1 <= 128 && BX1 > 64, "blur load columns");
 constexpr int RVH = 5;                 // rows per column task in the r pass (50 = 10 x 5)
 constexpr int UVH = 4;                 // rows per column task in the u pass (32 = 8 x 4)
-constexpr int RB_PER_WAVE = (BR2 / RVH + NT / 64 - 1) / (NT / 64);  // r-pass row blocks per wave
+constexpr int RB_PER_WAVE = (BR2 / RVH + NTB / 64 - 1) / (NTB / 64);  // r-pass row blocks per wave
 
 template <typename T>
 struct BlurLds {
@@ -1053,7 +1054,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     // t: rows [0, BX2) (pixel row o2-2RM+r), columns [0, BW) (pixel col o1-RM+c)
-    for (int t = tid; t < BX2 * (BW / 4); t += NT) {
+    for (int t = tid; t < BX2 * (BW / 4); t += NTB) {
         int r = t / (BW / 4), blk = t - r * (BW / 4);
         T xv[4 + 2 * RM];
 #pragma unroll
@@ -1076,7 +1077,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
     double st[1] = {0.0};
 #pragma unroll
     for (int j = 0; j < RB_PER_WAVE; ++j) {
-        const int blk = wv + j * (NT / 64);
+        const int blk = wv + j * (NTB / 64);
         if (blk >= BR2 / RVH) break;
         const int r0 = blk * RVH;
         T acc[RVH];
@@ -1111,7 +1112,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
     __syncthreads();
 
     // u: rows [0, BT2) (pixel row o2+q), lane = column; output-row profile
-    for (int blk = wv; blk < BT2 / UVH; blk += NT / 64) {
+    for (int blk = wv; blk < BT2 / UVH; blk += NTB / 64) {
         const int q0 = blk * UVH;
         T rv[UVH + 2 * RM];
 #pragma unroll
@@ -1130,7 +1131,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 
     // s: rows [0, BT2), output columns [0, BT1) (pixel col o1+c)
     T *s = a.s + ch * a.plane;
-    for (int t = tid; t < BT2 * ((BT1 + 3) / 4); t += NT) {
+    for (int t = tid; t < BT2 * ((BT1 + 3) / 4); t += NTB) {
         int q = t / ((BT1 + 3) / 4), blk = t - q * ((BT1 + 3) / 4);
         T uv[4 + 2 * RM];
 #pragma unroll
@@ -1152,7 +1153,7 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
             if (c < BT1 && gy < n2 && gx < n1) s[(int64_t)gy * n1 + gx] = acc[j];
         }
     }
-    if (a.slots) block_slot_add<1, NT>(st, a.slots);
+    if (a.slots) block_slot_add<1, NTB>(st, a.slots);
 }
 
 // Stages the x tile and the row profiles in LDS (with f0 prefetched for the
@@ -1172,24 +1173,24 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     T f0pre[RB_PER_WAVE][RVH];
     {
-        // load: lane = column (two chunks: 64 + 18), wave = rows (17 each)
-        constexpr int RPW = BX2 / (NT / 64);
+        // load: lane = column (two chunks: 64 + 18), wave = rows (every 8th)
+        constexpr int RPW = (BX2 + NTB / 64 - 1) / (NTB / 64);
         const int qa = wrap(o1 - 2 * RM + lane, n1);
         const bool okb = 64 + lane < BX1;
         const int qb = okb ? wrap(o1 - 2 * RM + 64 + lane, n1) : 0;
         T va[RPW], vb[RPW];
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
-            const int r = wv + i * (NT / 64);
-            const T *rowp = x + (int64_t)wrap(o2 - 2 * RM + r, n2) * n1;
+            const int r = wv + i * (NTB / 64);  // rows past BX2 read row o2-2RM, unused
+            const T *rowp = x + (int64_t)wrap(o2 - 2 * RM + (r < BX2 ? r : 0), n2) * n1;
             va[i] = rowp[qa];
             vb[i] = okb ? rowp[qb] : T(0);
         }
-        constexpr int KE = BX2 * (2 * RM + 1), KPT = (KE + NT - 1) / NT;
+        constexpr int KE = BX2 * (2 * RM + 1), KPT = (KE + NTB - 1) / NTB;
         T kv[KPT];
 #pragma unroll
         for (int i = 0; i < KPT; ++i) {  // all profile loads in flight together
-            const int e = tid + i * NT;
+            const int e = tid + i * NTB;
             const int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
             const bool ok = e < KE && d >= -R && d <= R;
             const T k = taps[ok ? (int64_t)wrap(o2 - 2 * RM + r, n2) * W + d + R : 0];
@@ -1202,21 +1203,23 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
         for (int j = 0; j < RB_PER_WAVE; ++j)
 #pragma unroll
             for (int k = 0; k < RVH; ++k) {
-                const int rr = (wv + j * (NT / 64)) * RVH + k;
+                const int rr = (wv + j * (NTB / 64)) * RVH + k;
                 const T f = f0s[rr < BR2 ? (int64_t)wrap(o2 - RM + rr, n2) * n1 + fq1 : 0];
                 f0pre[j][k] = a.f0 ? f : T(0);
             }
 #pragma unroll
         for (int i = 0; i < KPT; ++i) {
-            const int e = tid + i * NT;
+            const int e = tid + i * NTB;
             const int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
             if (e < KE) sK[r][d + RM] = kv[i];
         }
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
-            const int r = wv + i * (NT / 64);
-            sA[r * XP + lane] = va[i];
-            if (okb) sA[r * XP + 64 + lane] = vb[i];
+            const int r = wv + i * (NTB / 64);
+            if (r < BX2) {
+                sA[r * XP + lane] = va[i];
+                if (okb) sA[r * XP + 64 + lane] = vb[i];
+            }
         }
     }
     __syncthreads();
@@ -1401,7 +1404,7 @@ template <typename T, int NCH>
 __global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a) { coarse_body<T, NCH>(a, live_of<T>(a.p, a.beta_next), 0); }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_blur(BlurArgs<T> a)
+__global__ __launch_bounds__(NTB) void k_blur(BlurArgs<T> a)
 {
     const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
     if (t < 0) return;
@@ -1480,7 +1483,7 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_blur_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
+__global__ __launch_bounds__(NTB) void k_blur_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
                                                 int n, int ring)
 {
     const int g = xcd_tile(start[n]);
@@ -1560,7 +1563,7 @@ hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s)
     } else {
         BlurArgs<T> b = a;
         tiles_blur(a.n1, a.n2, &b.tx, &b.ty);
-        hipLaunchKernelGGL(k_blur<T>, dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NT), 0, s, b);
+        hipLaunchKernelGGL(k_blur<T>, dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
     }
     return hipGetLastError();
 }
@@ -1612,7 +1615,7 @@ hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, in
 template <typename T>
 hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_blur_b<T>, dim3(xcd_grid(tiles)), dim3(NT), 0, s, tab, start, n, ring);
+    hipLaunchKernelGGL(k_blur_b<T>, dim3(xcd_grid(tiles)), dim3(NTB), 0, s, tab, start, n, ring);
     return hipGetLastError();
 }
 

@@ -191,10 +191,11 @@ def test_graph_replay_is_bitwise(dtype):
     try:
         for on in (False, True):
             P.pd_graphs_enable(on)
-            a = _gpu_solve(pb, f0, case, tau, 200, dtype, stats=True)
-            b = _gpu_solve(pb, f0, case, tau, 200, dtype, stats=True)  # second call: cached graph
-            c = _gpu_solve(pb, f0, case, tau, 150, dtype, z_cur=a["z_cur"].clone(),
-                           z_prev=a["z_prev"].clone(), init=False, iter_offset=200)
+            # 300 iterations: chunks at 1, 65, 129, 193 (captured: replayed 4 times)
+            a = _gpu_solve(pb, f0, case, tau, 300, dtype, stats=True)
+            b = _gpu_solve(pb, f0, case, tau, 300, dtype, stats=True)  # second call: cached graph
+            c = _gpu_solve(pb, f0, case, tau, 290, dtype, z_cur=a["z_cur"].clone(),
+                           z_prev=a["z_prev"].clone(), init=False, iter_offset=300)
             runs[on] = (a, b, c)
     finally:
         P.pd_graphs_enable(True)
