@@ -172,8 +172,8 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, const Live<T> 
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool lok = lane < 2 * SR;
     const bool hi1 = lane >= SR;
-    const int lc_ = hi1 ? lane - SR : lane;
-    const int q1 = lok ? wrap(p01 - 5 + lc_, M1c) : 0;
+    const int lc_ = min(hi1 ? lane - SR : lane, SR - 1);  // lanes >= 2 SR read a neighbour, unused
+    const int q1 = wrap(p01 - 5 + lc_, M1c);
     const int col = q1 + (hi1 ? M1c : 0);
     constexpr int RPW = (2 * SR) / (NT / 64);  // 13 wave-rows per wave
     // Every load is issued unconditionally (no data-dependent branch between
@@ -186,9 +186,8 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, const Live<T> 
         const int r = bottom ? R - SR : R;
         const int q2 = wrap(p02 - 5 + r, M2c);
         const bool from_apx = !bottom && !hi1 && apx;
-        const int64_t idx = !lok ? 0
-                            : from_apx ? (int64_t)q2 * M1c + q1
-                                       : (int64_t)(q2 + (bottom ? M2c : 0)) * a.pitch + col;
+        const int64_t idx = from_apx ? (int64_t)q2 * M1c + q1
+                                     : (int64_t)(q2 + (bottom ? M2c : 0)) * a.pitch + col;
         va[i] = (from_apx ? apx : zc)[idx];
         vb[i] = (from_apx ? apx : zp)[idx];
     }
@@ -312,17 +311,22 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
         toapx[o] = b == 0 && !a.last;
         idxs[o] = (int64_t)(g2 + (hx2 ? M2c : 0)) * p.pitch + g1 + (src ? M1c : 0);
         const bool use = valid[o] && !toapx[o] && prox;
+        // unused loads read an in-range neighbour (spread addresses), of the
+        // state in prox mode, else of the input row this lane loads anyway
+        const int64_t near = prox ? (int64_t)((g2 < M2c ? g2 : M2c - 1) + (hx2 ? M2c : 0)) * p.pitch +
+                                        (g1 < M1c ? g1 : M1c - 1) + (src ? M1c : 0)
+                                  : (int64_t)wrap(2 * c02, M2) * a.in_pitch + qc;
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
-            const int64_t ci = use ? (int64_t)(ch0 + cc) * p.plane + idxs[o] : 0;
-            const T u = (use ? lv.zc : a.in)[ci];
-            const T v = (use ? lv.zp : a.in)[ci];
+            const int64_t ci = prox ? (int64_t)(ch0 + cc) * p.plane + near : near;
+            const T u = (prox ? lv.zc : a.in)[ci];
+            const T v = (prox ? lv.zp : a.in)[ci];
             zcr[cc][o] = use ? u : T(0);
             zpr[cc][o] = use ? v : T(0);
         }
-        const bool usew = use && p.wmap;
-        const T wv_ = (usew ? p.wmap : a.in)[usew ? (int64_t)ch0 * p.plane + idxs[o] : 0];
-        wr[o] = usew ? wv_ : T(0);
+        const bool usew = prox && p.wmap;
+        const T wv_ = (usew ? p.wmap : a.in)[usew ? (int64_t)ch0 * p.plane + near : near];
+        wr[o] = use && usew ? wv_ : T(0);
     }
 
 #pragma unroll
@@ -1193,7 +1197,8 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
             const int e = tid + i * NTB;
             const int r = e / (2 * RM + 1), d = e - r * (2 * RM + 1) - RM;
             const bool ok = e < KE && d >= -R && d <= R;
-            const T k = taps[ok ? (int64_t)wrap(o2 - 2 * RM + r, n2) * W + d + R : 0];
+            const int rr = r < BX2 ? r : BX2 - 1, dd = d < -R ? -R : (d > R ? R : d);  // in-range neighbour
+            const T k = taps[(int64_t)wrap(o2 - 2 * RM + rr, n2) * W + dd + R];
             kv[i] = ok ? k : T(0);
         }
         // f0 for the r pass (rows of the wave's row blocks, lane = column)
@@ -1204,7 +1209,7 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
 #pragma unroll
             for (int k = 0; k < RVH; ++k) {
                 const int rr = (wv + j * (NTB / 64)) * RVH + k;
-                const T f = f0s[rr < BR2 ? (int64_t)wrap(o2 - RM + rr, n2) * n1 + fq1 : 0];
+                const T f = f0s[(int64_t)wrap(o2 - RM + (rr < BR2 ? rr : BR2 - 1), n2) * n1 + fq1];
                 f0pre[j][k] = a.f0 ? f : T(0);
             }
 #pragma unroll
