@@ -255,6 +255,47 @@ def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20, streams=4):
             "sequential_ms": round(1e3 * res["seq"][0], 2), "bitwise_equal": same}
 
 
+def fwd_bwd_512(torch, P, SI, h, iters=200, ce=20):
+    """The headline image (512^2 FP32, Operator 1) through solve_autograd:
+    per-coefficient weights softplus(theta), theta ~ N(-2, 0.1), 200 unrolled
+    iterations, checkpoint every 20, L = 1/2 ||f - clean||^2; forward + backward
+    Mpixel-iter/s and the ratio to the forward solve alone."""
+    import numpy as np
+    case = SI.case_512()
+    n = 512
+    dev = "cuda"
+    op = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    tau = P.step_size(op, n, n, device=dev)
+    clean = torch.as_tensor(case.clean, dtype=torch.float32, device=dev)
+    f0 = (P.pd_apply_op(clean, op) + torch.as_tensor(case.noise, dtype=torch.float32, device=dev)).contiguous()
+    rng = np.random.default_rng(5)
+    th = torch.as_tensor(rng.normal(-2.0, 0.1, (1, n, n)), dtype=torch.float32, device=dev)
+
+    def fwd():
+        return P.solve_autograd(f0, th, op, h, case.levels, tau, iters, checkpoint_every=ce)
+
+    def both():
+        f0r = f0.clone().requires_grad_(True)
+        thr = th.clone().requires_grad_(True)
+        f = P.solve_autograd(f0r, thr, op, h, case.levels, tau, iters, checkpoint_every=ce)
+        (0.5 * ((f - clean) ** 2).sum()).backward()
+        return f0r.grad, thr.grad
+
+    res = {}
+    for name, fn in (("fwd", fwd), ("fwd_bwd", both)):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t) / 3
+    rate = lambda dt: round(n * n * iters / dt / 1e6, 1)
+    return {"workload": f"512^2 FP32, softplus weights, {iters} iterations, checkpoint {ce}",
+            "fwd_bwd_mpx_it_s": rate(res["fwd_bwd"]), "fwd_mpx_it_s": rate(res["fwd"]),
+            "ms_fwd_bwd": round(1e3 * res["fwd_bwd"], 2), "ms_fwd": round(1e3 * res["fwd"], 2)}
+
+
 def colour_case(torch, P, SI, h, iters, n=2048):
     """2048 x 2048 x 3, joint (group) shrinkage across channels, noise 0.1 + 5%
     salt-and-pepper, lambda 0.1: forward solve Mpixel-iter/s (pixels x
@@ -378,6 +419,8 @@ def main():
     if not args.no_grad:
         log("[bench] fwd+bwd: 16 x 256^2, 200 iterations")
         line["fwd_bwd"] = fwd_bwd(torch, P, SI, h)
+        log("[bench] fwd+bwd: 512^2, 200 iterations")
+        line["fwd_bwd_512"] = fwd_bwd_512(torch, P, SI, h)
     if not args.no_colour:
         log(f"[bench] colour 2048^2 x 3, {args.colour_iters} iterations")
         line["colour_2048x3"] = colour_case(torch, P, SI, h, args.colour_iters)
