@@ -363,14 +363,15 @@ int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIte
 
 // x = Psi y, y = zc + beta (zc - zp): coarse kernel (synthesis only) + fine levels
 template <typename T>
-int synth_chain(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out)
+int synth_chain(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIter di = DevIter{nullptr, 0})
 {
     int rc;
     if (c.lc <= c.sh->levels) {
         ProxArgs<T> p = prox_args<T>(c, zc, zp, nullptr, beta, T(0), nullptr, nullptr);
+        p.di = di;
         if ((rc = coarse_step<T>(c, COARSE_SYN, nullptr, out, p, T(0))) != PD_OK) return rc;
     }
-    return synth_fine<T>(c, zc, zp, beta, out);
+    return synth_fine<T>(c, zc, zp, beta, out, di);
 }
 
 // Fine analysis levels 1 .. lc-1: plain coefficients (MODE_PLAIN) or the fused
@@ -474,7 +475,7 @@ int one_iteration(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T
     int rc;
     // x = Psi y(i); the coarse part was produced by the previous iteration's coarse kernel
     if (it == 0) {
-        if ((rc = synth_chain<T>(c, zc, zp, beta, c.x())) != PD_OK) return rc;
+        if ((rc = synth_chain<T>(c, zc, zp, beta, c.x(), di)) != PD_OK) return rc;
     } else if ((rc = synth_fine<T>(c, zc, zp, beta, c.x(), di)) != PD_OK) {
         return rc;
     }
@@ -667,6 +668,25 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
         zc = zp;
         zp = t;
         ++it;
+    }
+    return PD_OK;
+}
+
+// The recomputation of pd_backward: count iterations from (zc, zp) with a
+// copy of every z(i) in seg.  it_dev set: the launches read i = *it_dev +
+// local index from device memory (for a captured segment).
+template <typename T>
+int iterate_seg(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc, T *zp,
+                int i_first, int count, T *seg, const int *it_dev)
+{
+    const int64_t NC = c.N() * c.sh->channels;
+    int rc;
+    for (int it = 0; it < count; ++it) {
+        if ((rc = one_iteration<T>(c, op, w, tau, f0, zc, zp, it, i_first + it, count, nullptr, i_first,
+                                   DevIter{it_dev, it_dev ? it : 0})) != PD_OK)
+            return rc;
+        PD_TRY_HIP(launch_copy<T>(zp, seg + (int64_t)it * NC, NC, c.st));
+        std::swap(zc, zp);
     }
     return PD_OK;
 }
@@ -1308,18 +1328,77 @@ int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *w
     if (gf0) PD_TRY_HIP(launch_fill<T>(gf0, T(0), NC, st));
     if (gw) PD_TRY_HIP(launch_fill<T>(gw, T(0), NC, st));
 
-    for (int sidx = L.nseg - 1; sidx >= 0; --sidx) {
-        const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
-        T *zc = ck(sidx, 0), *zp = ck(sidx, 1);
-        if ((rc = iterate<T>(c, op, w, tau, f0, zc, zp, i0, cnt, nullptr, seg)) != PD_OK) return rc;
+    // One segment: recompute its iterates from (zc, zp), then run the adjoint
+    // back through them.  With di set, i comes from device memory (*it_dev is
+    // the segment's first iteration) so that a captured graph of a full
+    // segment replays for every full segment.
+    auto segment = [&](const Ctx<T> &cs, T *zc, T *zp, int i0, int cnt, bool dev) -> int {
+        const hipStream_t s = cs.st;
+        if ((rc = iterate_seg<T>(cs, op, w, tau, f0, zc, zp, i0, cnt, seg, dev ? cs.it_dev() : nullptr)) != PD_OK)
+            return rc;
         for (int j = cnt - 1; j >= 0; --j) {
             const int i = i0 + j;
-            PD_TRY_HIP(launch_rev_mask<T>(zbar, seg + (int64_t)j * NC, vbar, gw, tau, NC, st));
-            if ((rc = synth_chain<T>(c, vbar, vbar, T(0), c.x())) != PD_OK) return rc;         // Psi vbar
-            if ((rc = blur_step<T>(c, op, c.x(), nullptr, c.s(), nullptr, gf0, tau)) != PD_OK) return rc;
-            if ((rc = analysis_plain<T>(c, c.s(), gbar)) != PD_OK) return rc;                   // Psi^* H^T H Psi vbar
+            PD_TRY_HIP(launch_rev_mask<T>(zbar, seg + (int64_t)j * NC, vbar, gw, tau, NC, s));
+            if ((rc = synth_chain<T>(cs, vbar, vbar, T(0), cs.x())) != PD_OK) return rc;         // Psi vbar
+            if ((rc = blur_step<T>(cs, op, cs.x(), nullptr, cs.s(), nullptr, gf0, tau)) != PD_OK) return rc;
+            if ((rc = analysis_plain<T>(cs, cs.s(), gbar)) != PD_OK) return rc;                   // Psi^* H^T H Psi vbar
             const T b = (T)beta_y(i);  // b_{i-1}
-            PD_TRY_HIP(launch_rev_combine<T>(vbar, gbar, zbar, zbarm, tau, b, i == 1 ? 1 : 0, NC, st));
+            PD_TRY_HIP(launch_rev_combine<T>(vbar, gbar, zbar, zbarm, tau, b, i == 1 ? 1 : 0, NC,
+                                             DevIter{dev ? cs.it_dev() : nullptr, j}, s));
+        }
+        return PD_OK;
+    };
+    // full segments other than the last: one captured graph, replayed from
+    // the working planes zA, zB (the checkpoint is copied there first)
+    hipGraphExec_t seg_graph = nullptr;
+    const int full = (L.nseg > 1 && g_graphs && !g_timing) ? L.nseg - 1 : 0;
+    {
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        sweep_retired();
+    }
+    if (full >= 2) {
+        int dev = 0;
+        hipStream_t cap = nullptr;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            std::lock_guard<std::mutex> lock(g_graph_mu);
+            cap = capture_stream(dev);
+        }
+        if (cap) {
+            Ctx<T> cs = c;
+            cs.st = cap;
+            if (hipStreamBeginCapture(cs.st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                const int crc = segment(cs, zA, zB, 1, C, true);
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(cs.st, &g);
+                if (crc == PD_OK && e == hipSuccess && g &&
+                    hipGraphInstantiate(&seg_graph, g, nullptr, nullptr, 0) != hipSuccess)
+                    seg_graph = nullptr;
+                if (g) (void)hipGraphDestroy(g);
+            }
+            (void)hipGetLastError();
+        }
+    }
+    for (int sidx = L.nseg - 1; sidx >= 0; --sidx) {
+        const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
+        if (seg_graph && sidx < L.nseg - 1) {
+            PD_TRY_HIP(launch_copy<T>(ck(sidx, 0), zA, NC, st));
+            PD_TRY_HIP(launch_copy<T>(ck(sidx, 1), zB, NC, st));
+            PD_TRY_HIP(launch_set_int(c.it_dev(), i0, st));
+            PD_TRY_HIP(hipGraphLaunch(seg_graph, st));
+            continue;
+        }
+        if ((rc = segment(c, ck(sidx, 0), ck(sidx, 1), i0, cnt, false)) != PD_OK) return rc;
+    }
+    if (seg_graph) {  // retired: destroyed once its last launch has run
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(ev, st) == hipSuccess) {
+            std::lock_guard<std::mutex> lock(g_graph_mu);
+            g_graph_retired.push_back(CachedGraph{{}, seg_graph, ev});
+        } else {
+            PD_TRY_HIP(hipStreamSynchronize(st));
+            (void)hipGraphExecDestroy(seg_graph);
+            if (ev) (void)hipEventDestroy(ev);
         }
     }
     // f0bar += Psi initbar (initbar = zbar after the i = 1 step, or Psi^* fbar when K = 0)

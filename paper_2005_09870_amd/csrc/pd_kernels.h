@@ -180,7 +180,7 @@ template <typename T>
 hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
-                              hipStream_t s);
+                              DevIter di, hipStream_t s);
 template <typename T> hipError_t launch_add(const T *x, T *y, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C, int levels, hipStream_t s);

@@ -1295,11 +1295,25 @@ __global__ void k_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, i
     }
 }
 
+// Momentum of y(i) = z(i-1) + b (z(i-1) - z(i-2)): b = (i-2)/(i+1), 0 for i = 1
+// (Appendix A.1), in double then rounded to T exactly as on the host.
+template <typename T>
+__device__ __forceinline__ T beta_at(int i)
+{
+    return i >= 2 ? (T)((double)(i - 2) / (double)(i + 1)) : T(0);
+}
+
 // ybar = vbar - tau gbar; with b = b_{i-1}:  zbar <- zbarm + (1+b) ybar,
 // zbarm <- -b ybar  (i >= 2); for i = 1 zbar <- ybar + zbarm (the init's adjoint).
 template <typename T>
-__global__ void k_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n)
+__global__ void k_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
+                              DevIter di)
 {
+    if (di.it_dev) {  // iteration i from device memory (graph replay): b = b_{i-1}, first = (i == 1)
+        const int i = *di.it_dev + di.it_off;
+        b = beta_at<T>(i);
+        first = i == 1;
+    }
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const T yb = vbar[e] - tau * gbar[e];
         if (first) {
@@ -1366,13 +1380,6 @@ __device__ __forceinline__ int xcd_tile(int total)
 }
 __host__ __device__ inline int xcd_grid(int total) { return NXCD * ((total + NXCD - 1) / NXCD); }
 
-// Momentum of y(i) = z(i-1) + b (z(i-1) - z(i-2)): b = (i-2)/(i+1), 0 for i = 1
-// (Appendix A.1), in double then rounded to T exactly as on the host.
-template <typename T>
-__device__ __forceinline__ T beta_at(int i)
-{
-    return i >= 2 ? (T)((double)(i - 2) / (double)(i + 1)) : T(0);
-}
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_synth(SynthArgs<T> a)
@@ -1657,9 +1664,10 @@ hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, i
 }
 template <typename T>
 hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
-                              hipStream_t s)
+                              DevIter di, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rev_combine<T>, dim3(ew_blocks(n)), dim3(256), 0, s, vbar, gbar, zbar, zbarm, tau, b, first, n);
+    hipLaunchKernelGGL(k_rev_combine<T>, dim3(ew_blocks(n)), dim3(256), 0, s, vbar, gbar, zbar, zbarm, tau, b, first, n,
+                       di);
     return hipGetLastError();
 }
 template <typename T>
@@ -1677,7 +1685,7 @@ hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C,
 }
 #define PD_INST_REV(T)                                                                                  \
     template hipError_t launch_rev_mask<T>(const T *, const T *, T *, T *, T, int64_t, hipStream_t);    \
-    template hipError_t launch_rev_combine<T>(const T *, const T *, T *, T *, T, T, int, int64_t,       \
+    template hipError_t launch_rev_combine<T>(const T *, const T *, T *, T *, T, T, int, int64_t, DevIter, \
                                               hipStream_t);                                             \
     template hipError_t launch_add<T>(const T *, T *, int64_t, hipStream_t);                            \
     template hipError_t launch_expand_weights<T>(T *, const T *, int, int, int, int, hipStream_t);
