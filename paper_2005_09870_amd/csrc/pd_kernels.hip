@@ -1040,6 +1040,7 @@ struct BlurLds {
     alignas(16) T sA[BX2 * XP];         // x, later r (BR2 x TP)
     alignas(16) T sB[BX2 * TP];         // t, later u (BT2 x TP)
     alignas(16) T sK[BX2][2 * RM + 2];  // profiles of the rows of x / t
+    alignas(16) T sKT[BR2][2 * RM + 2]; // by output row of H: sKT[q][RM+d] = profile of source row q+RM-d at d
 };
 
 // The four passes on a staged tile (profiles zero-padded to RM).
@@ -1074,28 +1075,33 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 #pragma unroll
         for (int q = 0; q < 4; ++q) sB[r * TP + 4 * blk + q] = acc[q];
     }
+    // the r pass's taps gathered by output row (contiguous in d, like the u pass)
+    for (int e = tid; e < BR2 * (2 * RM + 1); e += NTB) {
+        const int q = e / (2 * RM + 1), i = e - q * (2 * RM + 1);  // i = RM + d
+        lds.sKT[q][i] = sK[q + 2 * RM - i][i];
+    }
     __syncthreads();
 
-    // r: rows [0, BR2) (pixel row o2-RM+r), lane = column; the source t row of
-    // output row r0+k and offset m is r0+m with profile index k+2RM-m.
+    // r: rows [0, BR2) (pixel row o2-RM+r), lane = column.  Output row q =
+    // r0+k gathers t rows q+RM-d (tile index k+2RM-i with i = RM+d) with the
+    // taps sKT[q][i] of those source rows.
     double st[1] = {0.0};
 #pragma unroll
     for (int j = 0; j < RB_PER_WAVE; ++j) {
         const int blk = wv + j * (NTB / 64);
         if (blk >= BR2 / RVH) break;
         const int r0 = blk * RVH;
+        T tv[RVH + 2 * RM];
+#pragma unroll
+        for (int m = 0; m < RVH + 2 * RM; ++m) tv[m] = sB[(r0 + m) * TP + lane];
         T acc[RVH];
 #pragma unroll
-        for (int k = 0; k < RVH; ++k) acc[k] = T(0);
+        for (int k = 0; k < RVH; ++k) {
+            const T *kt = lds.sKT[r0 + k];
+            T s0 = T(0);
 #pragma unroll
-        for (int m = 0; m < RVH + 2 * RM; ++m) {
-            const T tv = sB[(r0 + m) * TP + lane];
-            const T *kr = &sK[r0 + m][RM];  // profile of source row r0+m (broadcast reads)
-#pragma unroll
-            for (int k = 0; k < RVH; ++k) {
-                const int d = k + RM - m;  // displacement x2 - y2
-                if (d >= -RM && d <= RM) acc[k] = fma(kr[d], tv, acc[k]);
-            }
+            for (int i = 0; i <= 2 * RM; ++i) s0 = fma(kt[i], tv[k + 2 * RM - i], s0);
+            acc[k] = s0;
         }
 #pragma unroll
         for (int k = 0; k < RVH; ++k) {
