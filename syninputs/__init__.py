@@ -27,8 +27,8 @@ def scene(n1: int, n2: int, n_rect: int, n_disk: int, background: str = "const",
     earlier ones.  Rectangles are drawn first, then disks."""
     if rng is None:
         rng = np.random.default_rng(seed)
-    i2, i1 = np.meshgrid(np.arange(n2), np.arange(n1), indexing="ij")
     if background == "ramp":
+        i2, i1 = np.meshgrid(np.arange(n2), np.arange(n1), indexing="ij")
         img = 0.1 + 0.3 * (i1 / n1 + i2 / n2) / 2.0
     else:
         img = np.full((n2, n1), 0.2)
@@ -43,7 +43,12 @@ def scene(n1: int, n2: int, n_rect: int, n_disk: int, background: str = "const",
         c1 = rng.uniform(0, n1)
         c2 = rng.uniform(0, n2)
         r = rng.uniform(m / 32, m / 8)
-        img[(i1 - c1) ** 2 + (i2 - c2) ** 2 <= r * r] = rng.uniform(0.0, 1.0)
+        # the test only on the disk's bounding box (one pixel of margin)
+        a1, b1 = max(0, int(np.floor(c1 - r)) - 1), min(n1, int(np.ceil(c1 + r)) + 2)
+        a2, b2 = max(0, int(np.floor(c2 - r)) - 1), min(n2, int(np.ceil(c2 + r)) + 2)
+        j2, j1 = np.meshgrid(np.arange(a2, b2), np.arange(a1, b1), indexing="ij")
+        box = img[a2:b2, a1:b1]
+        box[(j1 - c1) ** 2 + (j2 - c2) ** 2 <= r * r] = rng.uniform(0.0, 1.0)
     return img
 
 

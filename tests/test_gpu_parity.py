@@ -247,3 +247,66 @@ def test_batched_equals_per_image():
     outs, _ = P.pd_solve_batched(f0s, ops, lws, taus, _h(), levels, 40)
     for a, b in zip(outs, singles):
         assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------- edge cases ---
+@pytest.mark.parametrize("n1,n2,levels", [(2, 2, 1), (4, 4, 2), (8, 8, 3), (16, 8, 3), (32, 4, 2)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_tiny_shapes(n1, n2, levels, dtype, tol):
+    """Images smaller than every tile and than the blur support (the profiles
+    wrap around the period several times); the coarse block is the image."""
+    pb, f0, case = _problem(n1, n2, levels=levels, seed=40 + n1 + n2)
+    tau = O.step_size(pb)
+    ref = O.fista(pb, f0, tau, 30)
+    out = _gpu_solve(pb, f0, case, tau, 30, dtype)
+    assert np.abs(_np(out["f"]) - ref["f"]).max() < tol
+    assert np.abs(_np(out["z_cur"]) - ref["z"]).max() < tol
+
+
+def test_zero_weights_is_plain_gradient_descent():
+    """lambda = 0: no shrinkage, the iteration is accelerated gradient descent
+    on 1/2 ||H Psi z - f0||^2 (the oracle computes the same recursion)."""
+    pb, f0, case = _problem(96, 64, seed=50)
+    pb0 = O.Problem(pb.n1, pb.n2, 1, pb.levels, h=_h(), w=np.zeros_like(pb.w))
+    tau = O.step_size(pb0)
+    ref = O.fista(pb0, f0, tau, 50)
+    out = P.pd_solve(_t(f0, torch.float64), _op(pb0, torch.float64), _h(), pb0.levels, tau, 50,
+                     level_w=np.zeros(pb0.levels + 1))
+    assert np.abs(_np(out["f"]) - ref["f"]).max() < 1e-10
+
+
+def test_batched_edge_cases():
+    """A batch of one image, and a batch mixing an image whose coarse block is
+    the whole image (no fine level) with larger ones; equal to pd_solve."""
+    for shapes in ([(128, 96)], [(32, 32), (160, 96), (64, 128)]):
+        f0s, ops, lws, taus, levels, singles = [], [], [], [], [], []
+        for b, (n1, n2) in enumerate(shapes):
+            pb, f0, case = _problem(n1, n2, seed=60 + b)
+            tau = O.step_size(pb)
+            f0t = _t(f0, torch.float32)
+            op = _op(pb, torch.float32)
+            f0s.append(f0t)
+            ops.append(op)
+            lws.append(case.level_w)
+            taus.append(tau)
+            levels.append(pb.levels)
+            singles.append(P.pd_solve(f0t, op, _h(), pb.levels, tau, 70, level_w=case.level_w)["f"])
+        outs, _ = P.pd_solve_batched(f0s, ops, lws, taus, _h(), levels, 70)
+        for a, b in zip(outs, singles):
+            assert torch.equal(a, b)
+
+
+def test_colour_2048_full_size():
+    """The largest workload (2048 x 2048 x 3, joint shrinkage, salt-and-pepper
+    noise) at full size: 2 iterations against the oracle, every pixel."""
+    c = SI.case_colour()
+    n = 2048
+    pb = O.Problem(n, n, 3, c.levels, h=_h(), w=O.expand_level_weights(c.level_w, n, n, c.levels, 3),
+                   joint=True)
+    f0 = np.stack([O.apply_H(pb, c.clean[k]) for k in range(3)]) + c.noise
+    f0 = np.where(c.sp_mask[None], c.sp_val[None], f0)
+    tau = 0.89
+    ref = O.fista(pb, f0, tau, 2)
+    op = P.Operator.from_taps(pb.kt, pb.R, dtype=torch.float32)
+    out = P.pd_solve(_t(f0, torch.float32), op, _h(), c.levels, tau, 2, level_w=c.level_w, joint=True)
+    assert np.abs(_np(out["f"]) - ref["f"]).max() < 1e-5
