@@ -215,8 +215,88 @@ int pd_symmlet(int32_t moments, double *h_out);
 int pd_op1_taps(int32_t n2, double sigma_max, double mass, int32_t *radius,
                 double *taps_out);
 
+/* ---------------------------------------------------------------------------
+ * FISTA in the wavelet domain (Section 4.3, eq. 4.3, and Appendix A.1).
+ * Eq. 4.1 approximated as
+ *
+ *     argmin_z  1/2 ||Theta_L z - z0||^2 + ||z||_{1,w},   z0 = Psi^* f0,
+ *
+ * with Theta_L a sparse approximation of Theta = Psi^* H Psi given by the
+ * caller, solved by
+ *
+ *     z(i)   = Prox^Sigma_{tau ||.||_{1,w}}( y(i) - tau Sigma Theta_L^T (Theta_L y(i) - z0) )
+ *     y(i+1) = z(i) + (i-1)/(i+2) (z(i) - z(i-1))
+ *
+ * with Sigma = Id ("FISTA-W") or the Jacobi preconditioner ("FISTA-WP",
+ * sigma_l = 1 / (Theta_L^T Theta_L)[l,l], 1 for an empty column of Theta_L).
+ * Prox^Sigma is the prox in the metric of Sigma^{-1}: soft-thresholding of
+ * coefficient l at tau * sigma_l * w_l.  One iteration is two sparse
+ * products (with Theta_L and with its transpose, stored as its own CSR).
+ * ------------------------------------------------------------------------- */
+
+/* A square sparse matrix in CSR form, all arrays device memory:
+ *   row_ptr int64 [n+1], row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz;
+ *   col     int32 [nnz], the column indices of each row strictly increasing
+ *           and in [0, n);
+ *   val     [nnz] of the call's dtype.
+ * Rows and columns of Theta_L are indexed by Mallat position i2*n1 + i1.
+ * pd_csr_transpose checks these rules; the products do not, but they clamp
+ * row bounds to [0, nnz] and columns to [0, n), so a malformed matrix gives
+ * meaningless results without any access outside its arrays. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const void *val;
+} pd_csr;
+
+/* Bytes of device workspace pd_csr_transpose needs for an n x n matrix. */
+size_t pd_csr_transpose_workspace_size(int32_t n);
+
+/* The transpose of a (set-up, not the iteration): t_row_ptr device int64
+ * [n+1], t_col device int32 [nnz], t_val device [nnz], each row's columns
+ * sorted, so the result does not depend on the order of atomic updates.
+ * Checks a first and returns PD_ERR_ARG if it breaks the pd_csr rules; this
+ * check synchronises the stream.  Errors: PD_ERR_ARG, PD_ERR_WORKSPACE,
+ * PD_ERR_HIP. */
+int pd_csr_transpose(const pd_csr *a, int32_t dtype, int64_t *t_row_ptr, int32_t *t_col,
+                     void *t_val, void *workspace, size_t ws_bytes, void *stream);
+
+/* y = a x (device [n] vectors, non-overlapping).  Errors: PD_ERR_ARG, PD_ERR_HIP. */
+int pd_spmv(const pd_csr *a, int32_t dtype, const void *x, void *y, void *stream);
+
+/* sigma (device [n]) = the Jacobi preconditioner of FISTA-WP from the
+ * transpose theta_t = Theta_L^T: sigma_l = 1 / sum_k theta_t[l,k]^2, or 1
+ * where that sum is 0.  Errors: PD_ERR_ARG, PD_ERR_HIP. */
+int pd_wjacobi(const pd_csr *theta_t, int32_t dtype, void *sigma, void *stream);
+
+/* Bytes of device workspace pd_wsolve needs (shape: channels = 1). */
+size_t pd_wsolve_workspace_size(const pd_shape *shape, int32_t dtype);
+
+/* Run FISTA-W (precond == 0) or FISTA-WP (precond != 0) on the problem above.
+ *   shape   n1 x n2 Mallat plane, channels = 1, levels (for level_w bands).
+ *   theta, theta_t  Theta_L and its transpose (pd_csr_transpose), n = n1*n2.
+ *   w       level_w (host, bands as for pd_solve) or coeff_w (device [n]);
+ *           joint must be 0.
+ *   prm     tau > 0 (the step bound is 1/||Sigma^{1/2} Theta_L^T Theta_L
+ *           Sigma^{1/2}||), iters, iter_offset (resume), check_finite.
+ *   z0      device [n]: Psi^* f0 (pd_fwt).
+ *   z_cur, z_prev  device [n] state, in/out, as for pd_solve: z(k), z(k-1)
+ *           on entry (k = iter_offset), z(k+iters), z(k+iters-1) on exit; if
+ *           init_from_z0 != 0 both are first set to z0.  f = Psi z_cur by pd_fwt.
+ *   stats   device double [iters][3] or NULL: per iteration i,
+ *           1/2||Theta_L y(i) - z0||^2, ||y(i)||_{1,w}, ||z(i) - y(i)||^2,
+ *           accumulated in FP64; the caller zeroes it.
+ * Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_TAU, PD_ERR_WORKSPACE,
+ * PD_ERR_UNSUPPORTED, PD_ERR_HIP, PD_ERR_NONFINITE (check_finite only). */
+int pd_wsolve(const pd_shape *shape, int32_t dtype, const pd_csr *theta, const pd_csr *theta_t,
+              const pd_weights *w, const pd_params *prm, int32_t precond, const void *z0,
+              void *z_cur, void *z_prev, int32_t init_from_z0, double *stats, void *workspace,
+              size_t ws_bytes, void *stream);
+
 /* Diagnostics: per-launch kernel timing.  While enabled, every kernel launch
- * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt is bracketed by
+ * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt / pd_wsolve is bracketed by
  * two HIP events recorded on its launch stream, keyed by kernel class and
  * decomposition level.  Adds one event pair per launch; not thread-safe.   */
 typedef enum {
@@ -224,7 +304,9 @@ typedef enum {
     PD_K_SYNTH = 2,     /* one synthesis level (level = decomposition level)   */
     PD_K_ANALYSIS = 3,  /* one analysis level with the fused prox              */
     PD_K_COARSE = 4,    /* all coarse levels of an iteration in one workgroup  */
-    PD_K_OTHER = 5      /* copies and set-up                                   */
+    PD_K_OTHER = 5,     /* copies and set-up                                   */
+    PD_K_WRES = 6,      /* wavelet domain: u = Theta_L y - z0                  */
+    PD_K_WPROX = 7      /* wavelet domain: Theta_L^T u, prox and momentum      */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */

@@ -6,6 +6,7 @@ include/pd.h); this package only marshals torch device tensors into it.
 """
 from ._lib import PDError, load  # noqa: F401
 from .solver import (  # noqa: F401
+    Csr,
     FistaSolve,
     Operator,
     pd_backward,
@@ -19,5 +20,12 @@ from .solver import (  # noqa: F401
     pd_solve_batched,
     pd_symmlet,
     pd_workspace_size,
+    pd_csr_transpose,
+    pd_spmv,
+    pd_wjacobi,
+    pd_wsolve,
+    pd_wsolve_workspace_size,
     step_size,
+    wlipschitz,
+    wstep_size,
 )

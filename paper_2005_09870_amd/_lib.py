@@ -46,6 +46,11 @@ class pd_params(ctypes.Structure):
                 ("iter_offset", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
 
 
+class pd_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
 class pd_image_desc(ctypes.Structure):
     _fields_ = [("shape", pd_shape), ("offset", ctypes.c_int64), ("tau", ctypes.c_double),
                 ("op", pd_operator), ("level_w", ctypes.POINTER(ctypes.c_double))]
@@ -56,10 +61,14 @@ EXPORTS = [
     "pd_workspace_size", "pd_solve", "pd_batched_workspace_size", "pd_solve_batched",
     "pd_backward_workspace_size", "pd_backward", "pd_fwt", "pd_apply_op", "pd_symmlet",
     "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
+    "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
+    "pd_wsolve_workspace_size", "pd_wsolve",
 ]
 
 PD_K_BLUR, PD_K_SYNTH, PD_K_ANALYSIS, PD_K_COARSE, PD_K_OTHER = 1, 2, 3, 4, 5
-KCLASS_NAMES = {1: "blur", 2: "synthesis", 3: "analysis", 4: "coarse", 5: "other"}
+PD_K_WRES, PD_K_WPROX = 6, 7
+KCLASS_NAMES = {1: "blur", 2: "synthesis", 3: "analysis", 4: "coarse", 5: "other",
+                6: "wres", 7: "wprox"}
 
 _lib = None
 
@@ -109,6 +118,19 @@ def load() -> ctypes.CDLL:
     L.pd_graphs_enable.restype = ctypes.c_int
     L.pd_timing_read.argtypes = [i32, P(i32), P(i32), P(ctypes.c_int64), dp, P(i32)]
     L.pd_timing_read.restype = ctypes.c_int
+    L.pd_csr_transpose_workspace_size.argtypes = [i32]
+    L.pd_csr_transpose_workspace_size.restype = sz
+    L.pd_csr_transpose.argtypes = [P(pd_csr), i32, vp, vp, vp, vp, sz, vp]
+    L.pd_csr_transpose.restype = ctypes.c_int
+    L.pd_spmv.argtypes = [P(pd_csr), i32, vp, vp, vp]
+    L.pd_spmv.restype = ctypes.c_int
+    L.pd_wjacobi.argtypes = [P(pd_csr), i32, vp, vp]
+    L.pd_wjacobi.restype = ctypes.c_int
+    L.pd_wsolve_workspace_size.argtypes = [P(pd_shape), i32]
+    L.pd_wsolve_workspace_size.restype = sz
+    L.pd_wsolve.argtypes = [P(pd_shape), i32, P(pd_csr), P(pd_csr), P(pd_weights), P(pd_params), i32,
+                            vp, vp, vp, i32, vp, vp, sz, vp]
+    L.pd_wsolve.restype = ctypes.c_int
     L.pd_strerror.argtypes = [i32]
     L.pd_strerror.restype = ctypes.c_char_p
     _lib = L

@@ -13,13 +13,12 @@
 #include <mutex>
 
 #include "pd.h"
+#include "pd_internal.h"
 #include "pd_kernels.h"
 
 using namespace pd;
 
 namespace {
-
-inline size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool is_pow2_divisible(int n, int L) { return L >= 0 && L < 31 && (n % (1 << L)) == 0; }
 
@@ -119,43 +118,6 @@ Layout layout(const pd_shape *s, size_t es)
     return l;
 }
 
-// ------------------------------------------------ per-launch event timing --
-struct TimedLaunch {
-    int kclass, level;
-    hipEvent_t a, b;
-};
-bool g_timing = false;
-std::vector<TimedLaunch> g_launches;
-
-template <typename F>
-hipError_t timed(int kclass, int level, hipStream_t st, F &&launch)
-{
-    if (!g_timing) return launch();
-    TimedLaunch t{kclass, level, nullptr, nullptr};
-    hipError_t e;
-    if ((e = hipEventCreate(&t.a)) != hipSuccess) return e;
-    if ((e = hipEventCreate(&t.b)) != hipSuccess) return e;
-    if ((e = hipEventRecord(t.a, st)) != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(t.b, st)) != hipSuccess) return e;
-    g_launches.push_back(t);
-    return hipSuccess;
-}
-
-void clear_timing()
-{
-    for (auto &t : g_launches) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
-    }
-    g_launches.clear();
-}
-
-#define PD_TRY_HIP(expr)                      \
-    do {                                      \
-        if ((expr) != hipSuccess) return PD_ERR_HIP; \
-    } while (0)
 
 // Largest approximation (per side) the coarse kernel holds in LDS.
 constexpr int COARSE_MAX = 64;

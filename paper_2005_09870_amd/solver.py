@@ -317,3 +317,135 @@ def solve_autograd(f0: torch.Tensor, theta: torch.Tensor, op: Operator, h, level
     """Differentiable solve with weights w = softplus(theta) (per coefficient)."""
     w = torch.nn.functional.softplus(theta)
     return FistaSolve.apply(f0, w, op, h, levels, tau, iters, checkpoint_every)
+
+
+# --------------------------------------------- FISTA in the wavelet domain ---
+@dataclass
+class Csr:
+    """A square CSR matrix on the device (row_ptr int64 [n+1], col int32 [nnz],
+    val float32/float64 [nnz]); rows and columns are Mallat positions."""
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.row_ptr.numel() - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_arrays(row_ptr, col, val, dtype=torch.float32, device="cuda") -> "Csr":
+        return Csr(torch.as_tensor(np.asarray(row_ptr, dtype=np.int64), device=device),
+                   torch.as_tensor(np.asarray(col, dtype=np.int32), device=device),
+                   torch.as_tensor(np.asarray(val, dtype=np.float64), dtype=dtype, device=device))
+
+    def c(self) -> C.pd_csr:
+        _check_dev(self.row_ptr, self.col, self.val)
+        if self.row_ptr.dtype != torch.int64 or self.col.dtype != torch.int32:
+            raise TypeError("row_ptr must be int64 and col int32")
+        return C.pd_csr(self.n, self.nnz, self.row_ptr.data_ptr(),
+                        self.col.data_ptr() if self.nnz else None,
+                        self.val.data_ptr() if self.nnz else None)
+
+
+def pd_csr_transpose(a: Csr) -> Csr:
+    """The transpose of a (each row's columns sorted)."""
+    dev = a.row_ptr.device
+    t = Csr(torch.empty(a.n + 1, dtype=torch.int64, device=dev),
+            torch.empty(max(a.nnz, 1), dtype=torch.int32, device=dev)[:a.nnz],
+            torch.empty(max(a.nnz, 1), dtype=a.val.dtype, device=dev)[:a.nnz])
+    need = int(C.load().pd_csr_transpose_workspace_size(a.n))
+    ws = workspace(need, dev)
+    ac = a.c()
+    rc = C.load().pd_csr_transpose(ctypes.byref(ac), _dtype_code(a.val.dtype), _ptr(t.row_ptr),
+                                   _ptr(t.col), _ptr(t.val), _ptr(ws), ws.numel(), _stream(dev))
+    C.check(rc, "pd_csr_transpose")
+    return t
+
+
+def pd_spmv(a: Csr, x: torch.Tensor) -> torch.Tensor:
+    """a @ x for a device vector x of length n."""
+    _check_dev(x)
+    y = torch.empty_like(x)
+    ac = a.c()
+    rc = C.load().pd_spmv(ctypes.byref(ac), _dtype_code(x.dtype), _ptr(x), _ptr(y), _stream(x.device))
+    C.check(rc, "pd_spmv")
+    return y
+
+
+def pd_wjacobi(theta_t: Csr) -> torch.Tensor:
+    """Jacobi preconditioner of FISTA-WP from Theta_L^T."""
+    s = torch.empty(theta_t.n, dtype=theta_t.val.dtype, device=theta_t.val.device)
+    tc = theta_t.c()
+    rc = C.load().pd_wjacobi(ctypes.byref(tc), _dtype_code(s.dtype), _ptr(s), _stream(s.device))
+    C.check(rc, "pd_wjacobi")
+    return s
+
+
+def wlipschitz(theta: Csr, theta_t: Csr, sigma: torch.Tensor | None = None, iters: int = 200,
+               seed: int = 0) -> float:
+    """||Sigma^{1/2} Theta_L^T Theta_L Sigma^{1/2}||_2 by power iteration with
+    the library's sparse products (host-side normalisation)."""
+    dev = theta.val.device
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    x = torch.randn(theta.n, generator=g, dtype=torch.float64).to(device=dev, dtype=theta.val.dtype)
+    r = None if sigma is None else torch.sqrt(sigma)
+    x /= torch.linalg.vector_norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        v = x if r is None else r * x
+        y = pd_spmv(theta_t, pd_spmv(theta, v))
+        if r is not None:
+            y = r * y
+        lam = float(torch.linalg.vector_norm(y))
+        x = y / lam
+    return lam
+
+
+def wstep_size(theta: Csr, theta_t: Csr, sigma: torch.Tensor | None = None) -> float:
+    return 1.0 / (wlipschitz(theta, theta_t, sigma) * (1.0 + 1e-6))
+
+
+def pd_wsolve_workspace_size(n1: int, n2: int, levels: int, dtype: torch.dtype) -> int:
+    shape = C.pd_shape(n1, n2, 1, levels)
+    return int(C.load().pd_wsolve_workspace_size(ctypes.byref(shape), _dtype_code(dtype)))
+
+
+def pd_wsolve(z0: torch.Tensor, theta: Csr, theta_t: Csr, levels: int, tau: float, iters: int,
+              precond: bool = False, level_w=None, coeff_w: torch.Tensor | None = None,
+              z_cur: torch.Tensor | None = None, z_prev: torch.Tensor | None = None,
+              init: bool = True, iter_offset: int = 0, stats: bool = False,
+              check_finite: bool = False, ws: torch.Tensor | None = None):
+    """FISTA-W (precond False) or FISTA-WP on 1/2||Theta_L z - z0||^2 + ||z||_{1,w}.
+    z0: (n2, n1) or (1, n2, n1) Mallat coefficients Psi^* f0.  Returns a dict
+    with z_cur = z(K), z_prev = z(K-1) (shaped like z0) and stats ((iters, 3)
+    FP64: 1/2||Theta_L y(i) - z0||^2, ||y(i)||_{1,w}, ||z(i) - y(i)||^2)."""
+    _check_dev(z0, coeff_w, z_cur, z_prev)
+    n2, n1 = z0.shape[-2:]
+    shape = C.pd_shape(int(n1), int(n2), 1, int(levels))
+    lw = None
+    if level_w is not None:
+        lw = np.ascontiguousarray(np.asarray(level_w, dtype=np.float64))
+        if lw.shape != (levels + 1,):
+            raise ValueError("level_w needs levels+1 entries")
+    w = C.pd_weights(_dptr(lw) if lw is not None else None,
+                     None if coeff_w is None else coeff_w.data_ptr(), 0)
+    prm = C.pd_params(float(tau), int(iters), int(iter_offset), 1 if check_finite else 0)
+    if z_cur is None:
+        z_cur = torch.empty_like(z0)
+    if z_prev is None:
+        z_prev = torch.empty_like(z0)
+    st = torch.zeros((max(iters, 1), 3), dtype=torch.float64, device=z0.device) if stats else None
+    need = pd_wsolve_workspace_size(n1, n2, levels, z0.dtype)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, z0.device)
+    tc, ttc = theta.c(), theta_t.c()
+    rc = C.load().pd_wsolve(ctypes.byref(shape), _dtype_code(z0.dtype), ctypes.byref(tc), ctypes.byref(ttc),
+                            ctypes.byref(w), ctypes.byref(prm), 1 if precond else 0, _ptr(z0), _ptr(z_cur),
+                            _ptr(z_prev), 1 if init else 0, _ptr(st), _ptr(ws), ws.numel(),
+                            _stream(z0.device))
+    C.check(rc, "pd_wsolve")
+    return {"z_cur": z_cur, "z_prev": z_prev, "stats": None if st is None else st[:iters]}

@@ -100,3 +100,51 @@ def test_workspace_size_rejects_bad_shapes():
 def test_strerror_covers_codes():
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert C.strerror(code) != "unknown status"
+
+
+def _call_wsolve(shape, dtype=C.PD_F32, th=None, tht=None, w=None, prm=None, z0=1, zc=2, zp=3, ws=4,
+                 ws_bytes=None, lw_len=None):
+    L = C.load()
+    n = shape.n1 * shape.n2
+    csr = C.pd_csr(n, 10, _fake(5), _fake(6), _fake(7))
+    th = csr if th is None else th
+    tht = csr if tht is None else tht
+    lw = np.zeros(shape.levels + 1 if shape.levels > 0 else 1)
+    w = w or C.pd_weights(lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0)
+    prm = prm or C.pd_params(0.5, 10, 0, 0)
+    if ws_bytes is None:
+        ws_bytes = 1 << 40
+    return L.pd_wsolve(ctypes.byref(shape), dtype, ctypes.byref(th) if th else None,
+                       ctypes.byref(tht) if tht else None, ctypes.byref(w), ctypes.byref(prm), 1,
+                       _fake(z0) if z0 else None, _fake(zc) if zc else None, _fake(zp) if zp else None, 1, None,
+                       _fake(ws) if ws else None, ws_bytes, None)
+
+
+def test_wavelet_domain_argument_errors_without_gpu_work():
+    """pd_wsolve / pd_csr_transpose / pd_spmv reject bad arguments before any
+    device work (the pointers here are never dereferenced)."""
+    L = C.load()
+    ok = C.pd_shape(64, 64, 1, 6)
+    assert _call_wsolve(C.pd_shape(64, 64, 2, 6)) == C.PD_ERR_SHAPE      # one channel only
+    assert _call_wsolve(C.pd_shape(100, 64, 1, 3)) == C.PD_ERR_SHAPE
+    assert _call_wsolve(ok, dtype=5) == C.PD_ERR_ARG
+    assert _call_wsolve(ok, th=C.pd_csr(64 * 64 + 1, 10, _fake(5), _fake(6), _fake(7))) == C.PD_ERR_SHAPE
+    assert _call_wsolve(ok, th=C.pd_csr(4096, 10, None, _fake(6), _fake(7))) == C.PD_ERR_ARG
+    assert _call_wsolve(ok, th=C.pd_csr(4096, -1, _fake(5), _fake(6), _fake(7))) == C.PD_ERR_ARG
+    assert _call_wsolve(ok, prm=C.pd_params(-1.0, 10, 0, 0)) == C.PD_ERR_TAU
+    assert _call_wsolve(ok, prm=C.pd_params(0.5, -2, 0, 0)) == C.PD_ERR_ARG
+    assert _call_wsolve(ok, zc=3, zp=3) == C.PD_ERR_ARG
+    assert _call_wsolve(ok, z0=2) == C.PD_ERR_ARG
+    assert _call_wsolve(ok, w=C.pd_weights(None, None, 0)) == C.PD_ERR_ARG
+    need = L.pd_wsolve_workspace_size(ctypes.byref(ok), C.PD_F32)
+    assert need >= 3 * 4096 * 4
+    assert L.pd_wsolve_workspace_size(ctypes.byref(C.pd_shape(64, 64, 3, 6)), C.PD_F32) == 0
+    assert _call_wsolve(ok, ws_bytes=need - 1) == C.PD_ERR_WORKSPACE
+    bad = C.pd_csr(0, 0, _fake(5), None, None)
+    assert L.pd_csr_transpose(ctypes.byref(bad), C.PD_F32, _fake(1), _fake(2), _fake(3), _fake(4), 1 << 30,
+                              None) == C.PD_ERR_ARG
+    a = C.pd_csr(100, 10, _fake(5), _fake(6), _fake(7))
+    assert L.pd_csr_transpose(ctypes.byref(a), C.PD_F32, _fake(1), _fake(2), _fake(3), _fake(4), 8,
+                              None) == C.PD_ERR_WORKSPACE
+    assert L.pd_spmv(ctypes.byref(a), C.PD_F32, None, _fake(2), None) == C.PD_ERR_ARG
+    assert L.pd_wjacobi(ctypes.byref(a), C.PD_F32, None, None) == C.PD_ERR_ARG
