@@ -338,6 +338,75 @@ def colour_case(torch, P, SI, h, iters, n=2048):
             "kernels_us": {f"{rw['kernel']}/{rw['level']}": round(rw["avg_us"], 2) for rw in rows}}
 
 
+def wavelet_case(torch, P, SI, h, iters, n=1024, levels=10, eta=3e-3):
+    """FISTA in the wavelet domain (Section 4.3, Appendix A.1) at the paper's
+    image size: 1024 x 1024, Operator 1, 10 levels, Theta_L = every entry of
+    Psi^* H Psi of magnitude >= eta (built by probing with libpd's transforms,
+    FP64, then stored FP32).  FISTA-W and FISTA-WP, FP32 state, FP64
+    statistics: Mpixel-iter/s and the HBM roofline of the two sparse products."""
+    from paper_2005_09870_amd import theta as TH
+    dev = "cuda"
+    r, d = SI.scaled_counts(n, n)
+    c = SI.make_case(n, n, 1, r, d, "ramp", 0.05, 0.08, levels=levels, seed=13)
+    op64 = P.Operator.op1(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m64 = TH.theta_rowblur(op64, h, n, n, levels, eta, dtype=torch.float64)
+    a = P.Csr(m64.row_ptr, m64.col, m64.val.float())
+    at = P.pd_csr_transpose(a)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    del m64
+    op = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    clean = torch.as_tensor(c.clean, dtype=torch.float32, device=dev)
+    f0 = P.pd_apply_op(clean, op) + torch.as_tensor(c.noise, dtype=torch.float32, device=dev)
+    z0 = P.pd_fwt(f0, h, levels)[0].contiguous()
+    sigma = P.pd_wjacobi(at)
+    N, nnz = n * n, a.nnz
+    ws = P.solver.workspace(P.pd_wsolve_workspace_size(n, n, levels, torch.float32), dev)
+    out = {"workload": f"{n}x{n} FP32, Operator 1, {levels} levels, Theta_L = |Psi^* H Psi| >= {eta:g}, "
+                       f"{iters} iterations",
+           "nnz": nnz, "nnz_per_row": round(nnz / N, 2), "build_s": round(t_build, 2)}
+    for name, pre in (("fista_w", False), ("fista_wp", True)):
+        tau = P.wstep_size(a, at, sigma if pre else None)
+
+        def run(k):
+            return P.pd_wsolve(z0, a, at, levels, tau, k, precond=pre, level_w=c.level_w, ws=ws, stats=True)
+
+        run(5)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        res = run(iters)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_it = e0.elapsed_time(e1) / iters
+        P.solver.pd_timing_enable(True)
+        run(20)
+        torch.cuda.synchronize()
+        rows = P.solver.pd_timing_read()
+        P.solver.pd_timing_enable(False)
+        es = 4
+        alg = {"wres": nnz * 8 + (N + 1) * 8 + 3 * N * es,
+               "wprox": nnz * 8 + (N + 1) * 8 + (6 + (1 if pre else 0)) * N * es}
+        kern = {}
+        for rw in rows:
+            if rw["kernel"] in alg:
+                kern[rw["kernel"]] = rw["avg_us"]
+        dom = max(kern, key=kern.get)
+        ach = alg[dom] / (kern[dom] * 1e-6) / 1e9
+        e_last = res["stats"][-1].sum().item()
+        out[name] = {"tau": tau, "ms_per_iter": round(ms_it, 4), "mpx_it_s": round(N / (ms_it * 1e-3) / 1e6, 1),
+                     "ms_38_iterations": round(38 * ms_it, 3), "final_energy_terms": round(e_last, 6),
+                     "kernels_us": {k: round(v, 2) for k, v in kern.items()},
+                     "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom,
+                                  "avg_us": round(kern[dom], 3), "alg_bytes_per_launch": alg[dom]}}
+        log(f"[bench] {name}: {ms_it * 1e3:.1f} us/iter, kernels " +
+            ", ".join(f"{k} {v:.1f} us" for k, v in kern.items()))
+    return out
+
+
 def copy_calibration(torch, nbytes=256 << 20):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -361,6 +430,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-colour", action="store_true")
     ap.add_argument("--colour-iters", type=int, default=300)
+    ap.add_argument("--no-wavelet", action="store_true")
+    ap.add_argument("--wavelet-iters", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -424,6 +495,9 @@ def main():
     if not args.no_colour:
         log(f"[bench] colour 2048^2 x 3, {args.colour_iters} iterations")
         line["colour_2048x3"] = colour_case(torch, P, SI, h, args.colour_iters)
+    if not args.no_wavelet:
+        log(f"[bench] wavelet domain 1024^2 (FISTA-W / FISTA-WP), {args.wavelet_iters} iterations")
+        line["wavelet_1024"] = wavelet_case(torch, P, SI, h, args.wavelet_iters)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(SI)

@@ -184,3 +184,63 @@ def test_wstep_size_matches_oracle():
         ref = W.lipschitz(m, sig, iters=500)   # both converged to ~1e-13 by then
         got = P.wlipschitz(a, at, None if sig is None else _t(sig, torch.float64), iters=500)
         assert abs(got - ref) < 1e-9 * ref
+
+
+# ------------------------------------------------------ Theta_L by probing ---
+def test_theta_builder_on_gpu_matches_dense():
+    """The probed Theta_L (libpd transforms and blur, FP64) equals the oracle's
+    dense Theta thresholded at eta, entry for entry."""
+    from paper_2005_09870_amd import theta as TH
+    n, L, eta = 64, 6, 3e-3
+    pb = O.Problem(n, n, 1, L, h=H6)
+    T = W.theta_dense(pb)
+    op = P.Operator.from_taps(pb.kt, pb.R, dtype=torch.float64)
+    m = TH.theta_rowblur(op, H6, n, n, L, eta, dtype=torch.float64)
+    A = sp.csr_matrix((m.val.cpu().numpy(), m.col.cpu().numpy(), m.row_ptr.cpu().numpy()), shape=T.shape)
+    keep = np.abs(T) >= eta
+    # entries within rounding of the threshold may fall either way
+    near = np.abs(np.abs(T) - eta) < 1e-12
+    got = A.toarray() != 0
+    assert not np.any((got != keep) & ~near)
+    assert np.abs(np.where(got & keep, A.toarray() - T, 0.0)).max() < 1e-12
+
+
+def test_wavelet_solver_at_1024_full_size():
+    """The 1024 x 1024 workload (Operator 1, 10 levels, Theta_L = entries of
+    magnitude >= 3e-3): sampled columns of the probed Theta_L against the
+    oracle's Psi^* H Psi e, then 4 FISTA-WP iterations in FP32 against the
+    oracle on the same matrix (every coefficient)."""
+    from paper_2005_09870_amd import theta as TH
+    n, L, eta = 1024, 10, 3e-3
+    kt, R = O.op1_profiles(n)
+    op = P.Operator.from_taps(kt, R, dtype=torch.float64)
+    m64 = TH.theta_rowblur(op, H6, n, n, L, eta, dtype=torch.float64)
+    mt64 = P.pd_csr_transpose(m64)
+    rp, col, val = mt64.row_ptr.cpu().numpy(), mt64.col.cpu().numpy(), mt64.val.cpu().numpy()
+    pb = O.Problem(n, n, 1, L, h=H6)
+    for mu in (5 * n + 700, 300 * n + 40, 3 * n + 2, 0):   # level-1, level-2, coarse detail, approximation
+        e = np.zeros((n, n))
+        e.flat[mu] = 1.0
+        colref = O.fwt(O.apply_H(pb, O.ifwt(e, L, H6)), L, H6).ravel()
+        keep = np.nonzero(np.abs(colref) >= eta)[0]
+        lo, hi = rp[mu], rp[mu + 1]
+        near = np.abs(np.abs(colref) - eta) < 1e-12
+        assert set(col[lo:hi]) ^ set(keep) <= set(np.nonzero(near)[0])
+        np.testing.assert_allclose(val[lo:hi], colref[col[lo:hi]], rtol=0, atol=1e-12)
+    # FISTA-WP, FP32 on the GPU vs the oracle (FP64) on the FP32-rounded matrix
+    a = P.Csr(m64.row_ptr, m64.col, m64.val.float())
+    at = P.pd_csr_transpose(a)
+    c = SI.make_case(n, n, 1, 160, 100, "ramp", 0.05, 0.08, seed=13)
+    f0 = O.apply_H(pb, c.clean[0]) + c.noise[0]
+    z0 = O.fwt(f0, L, H6)
+    A = sp.csr_matrix((a.val.double().cpu().numpy(), a.col.cpu().numpy(), a.row_ptr.cpu().numpy()),
+                      shape=(n * n, n * n))
+    sig = W.jacobi_sigma(A)
+    tau = 0.9 / W.lipschitz(A, sig, iters=30)
+    w = O.expand_level_weights(c.level_w, n, n, L)[0]
+    ref = W.fista_w(A, z0, w, tau, 4, sigma=sig)
+    out = P.pd_wsolve(_t(z0, torch.float32), a, at, L, tau, 4, precond=True, level_w=c.level_w)
+    # compared on f = Psi z (pixel scale): the approximation coefficient is ~400 here
+    fg = O.ifwt(_np(out["z_cur"]).reshape(n, n), L, H6)
+    fr = O.ifwt(ref["z"].reshape(n, n), L, H6)
+    assert np.abs(fg - fr).max() < 1e-5
