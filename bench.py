@@ -61,18 +61,19 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
     return 0.0
 
 
-def profiled_traffic(key: str):
+def profiled_traffic(key: str, summary: str = "fista512_traffic.md",
+                     sources=("pd_kernels.hip", "pd_kernels.h")):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of kernel `key` (e.g.
     'coarse/4') from the committed rocprofv3 summary, or None when the kernel
     sources changed since those counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
-        text = open(os.path.join(root, "profiles", "fista512_traffic.md")).read()
+        text = open(os.path.join(root, "profiles", summary)).read()
         line = next(l for l in text.splitlines() if l.startswith("traffic-json: "))
         rec = json.loads(line[len("traffic-json: "):])
         h = hashlib.sha256()
-        for f in ("pd_kernels.hip", "pd_kernels.h"):
+        for f in sources:
             with open(os.path.join(root, "paper_2005_09870_amd", "csrc", f), "rb") as fh:
                 h.update(fh.read())
     except (OSError, StopIteration, ValueError):
@@ -400,7 +401,10 @@ def wavelet_case(torch, P, SI, h, iters, n=1024, levels=10, eta=3e-3):
                      "ms_38_iterations": round(38 * ms_it, 3), "final_energy_terms": round(e_last, 6),
                      "kernels_us": {k: round(v, 2) for k, v in kern.items()},
                      "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom,
+                                  "frac": round(ach / HBM_PEAK_GBS, 4),
+                                  "traffic": profiled_traffic(dom, "fista_w1024_traffic.md",
+                                                              ("pd_wkernels.hip", "pd_wkernels.h")),
+                                  "kernel": dom,
                                   "avg_us": round(kern[dom], 3), "alg_bytes_per_launch": alg[dom]}}
         log(f"[bench] {name}: {ms_it * 1e3:.1f} us/iter, kernels " +
             ", ".join(f"{k} {v:.1f} us" for k, v in kern.items()))

@@ -10,11 +10,12 @@
 // product while the gathered vectors stay in L2 / the Infinity Cache.
 //
 // Row groups: G lanes (a power of two, picked from the average row length)
-// share one row; lane j reads entries j, j+G, ... of the row, two per trip,
-// all loads of a trip issued before the first use; the G partial sums meet in
-// an xor tree.  Workgroups take consecutive row ranges in XCD-aware order, so
-// each XCD's L2 sees a contiguous band of rows and the nearby columns they
-// gather.
+// share a row; lane j reads entries j, j+G, ... of it, UR per trip, and each
+// group keeps NRG rows in flight together (their loads interleaved, all
+// issued before the first use), so a wave has enough bytes outstanding to
+// cover the HBM latency; the G partial sums meet in an xor tree.  Workgroups
+// take consecutive row ranges in XCD-aware order, so each XCD's L2 sees a
+// contiguous band of rows and the nearby columns they gather.
 #include <hip/hip_runtime.h>
 
 #include "pd_wkernels.h"
@@ -71,22 +72,52 @@ __device__ __forceinline__ void row_bounds(const Csr<T> &A, int r, int64_t &b0, 
 
 __device__ __forceinline__ int clamp_col(int c, int n) { return (unsigned)c < (unsigned)n ? c : (c < 0 ? 0 : n - 1); }
 
-// Partial sum of lane lg (0..G-1) over row [b0, b1): sum val[k] x[col[k]].
+constexpr int UR = 4;    // entries per lane per trip
+constexpr int NRG = 2;   // rows per lane group in flight together
+
+// Partial sums of lane lg (0..G-1) over NRG rows [b0[j], b1[j]):
+// sum val[k] x[col[k]]; the rows' loads are interleaved so that all of a
+// trip's loads of every row are in flight before the first use.
 template <typename T, int G>
-__device__ __forceinline__ T row_partial(const Csr<T> &A, int64_t b0, int64_t b1, const T *__restrict__ x, int lg)
+__device__ __forceinline__ void rows_partial(const Csr<T> &A, const int64_t (&b0)[NRG], const int64_t (&b1)[NRG],
+                                             const T *__restrict__ x, int lg, T (&acc)[NRG])
 {
-    T acc = T(0);
-    for (int64_t k0 = b0; k0 < b1; k0 += 2 * G) {
-        const int64_t ka = k0 + lg, kb = k0 + G + lg;
-        const bool oa = ka < b1, ob = kb < b1;
-        const int64_t ca = oa ? ka : b1 - 1, cb = ob ? kb : b1 - 1;  // in-range neighbours
-        const int ia = A.col[ca], ib = A.col[cb];
-        const T va = A.val[ca], vb = A.val[cb];
-        const T xa = x[clamp_col(ia, A.n)], xb = x[clamp_col(ib, A.n)];
-        acc = fma(oa ? va : T(0), xa, acc);
-        acc = fma(ob ? vb : T(0), xb, acc);
+    int64_t k0[NRG];
+#pragma unroll
+    for (int j = 0; j < NRG; ++j) {
+        acc[j] = T(0);
+        k0[j] = b0[j];
     }
-    return acc;
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int j = 0; j < NRG; ++j) more |= k0[j] < b1[j];
+        if (!more) break;
+        int ci[NRG][UR];
+        T cv[NRG][UR];
+        bool ok[NRG][UR];
+#pragma unroll
+        for (int j = 0; j < NRG; ++j)
+#pragma unroll
+            for (int q = 0; q < UR; ++q) {
+                const int64_t k = k0[j] + q * G + lg;
+                ok[j][q] = k < b1[j];
+                const int64_t kk = ok[j][q] ? k : (b1[j] > b0[j] ? b1[j] - 1 : 0);  // in-range neighbour
+                ci[j][q] = A.nnz > 0 ? A.col[kk] : 0;
+                cv[j][q] = A.nnz > 0 ? A.val[kk] : T(0);
+            }
+        T xv[NRG][UR];
+#pragma unroll
+        for (int j = 0; j < NRG; ++j)
+#pragma unroll
+            for (int q = 0; q < UR; ++q) xv[j][q] = x[clamp_col(ci[j][q], A.n)];
+#pragma unroll
+        for (int j = 0; j < NRG; ++j) {
+#pragma unroll
+            for (int q = 0; q < UR; ++q) acc[j] = fma(ok[j][q] ? cv[j][q] : T(0), xv[j][q], acc[j]);
+            k0[j] += UR * G;
+        }
+    }
 }
 
 // Sum over the G lanes of a group (aligned groups; every lane gets the sum).
@@ -116,26 +147,37 @@ __device__ __forceinline__ T soft_w(T v, T t)
     return a > T(0) ? copysign(a, v) : T(0);
 }
 
+// Rows of lane group gi of workgroup blk: (blk * NRG + j) * RPB + gi, j < NRG.
 template <typename T, int G>
 __global__ __launch_bounds__(NTW) void k_wres(WResArgs<T> a)
 {
     constexpr int RPB = NTW / G;
-    const int nb = (a.a.n + RPB - 1) / RPB;
+    const int nb = (a.a.n + RPB * NRG - 1) / (RPB * NRG);
     const int blk = xcd_block(nb);
     double st[1] = {0.0};
     if (blk >= 0) {
-        const int lg = threadIdx.x & (G - 1);
-        const int row = blk * RPB + threadIdx.x / G;
-        const bool rok = row < a.a.n;
-        const int r = rok ? row : a.a.n - 1;
-        const T bv = a.b ? a.b[r] : T(0);
-        int64_t b0, b1;
-        row_bounds(a.a, r, b0, b1);
-        const T s = group_sum<T, G>(row_partial<T, G>(a.a, b0, b1, a.x, lg));
-        const T u = s - bv;
-        if (rok && lg == 0) {
-            a.u[r] = u;
-            st[0] = 0.5 * (double)u * (double)u;
+        const int lg = threadIdx.x & (G - 1), gi = threadIdx.x / G;
+        int r[NRG];
+        bool rok[NRG];
+        T bv[NRG];
+        int64_t b0[NRG], b1[NRG];
+#pragma unroll
+        for (int j = 0; j < NRG; ++j) {
+            const int row = (blk * NRG + j) * RPB + gi;
+            rok[j] = row < a.a.n;
+            r[j] = rok[j] ? row : a.a.n - 1;
+            bv[j] = a.b ? a.b[r[j]] : T(0);
+            row_bounds(a.a, r[j], b0[j], b1[j]);
+        }
+        T acc[NRG];
+        rows_partial<T, G>(a.a, b0, b1, a.x, lg, acc);
+#pragma unroll
+        for (int j = 0; j < NRG; ++j) {
+            const T u = group_sum<T, G>(acc[j]) - bv[j];
+            if (rok[j] && lg == 0) {
+                a.u[r[j]] = u;
+                st[0] += 0.5 * (double)u * (double)u;
+            }
         }
     }
     if (a.slots) wblock_add<1>(st, a.slots);
@@ -146,38 +188,49 @@ __global__ __launch_bounds__(NTW) void k_wprox(WProxArgs<T> a)
 {
     constexpr int RPB = NTW / G;
     __shared__ T sw[PD_MAXL + 1];
-    const int nb = (a.at.n + RPB - 1) / RPB;
+    const int nb = (a.at.n + RPB * NRG - 1) / (RPB * NRG);
     const int blk = xcd_block(nb);
     if (!a.wmap && threadIdx.x <= a.levels) sw[threadIdx.x] = a.wlev[threadIdx.x];
     double st[2] = {0.0, 0.0};
     bool bad = false;
     if (blk >= 0) {
-        const int lg = threadIdx.x & (G - 1);
-        const int row = blk * RPB + threadIdx.x / G;
-        const bool rok = row < a.at.n;
-        const int r = rok ? row : a.at.n - 1;
-        // the row's own operands load while its entries stream
-        const T y = a.y[r], zc = a.zc[r];
-        const T sg = a.sigma ? a.sigma[r] : T(1);
-        const T wm = a.wmap ? a.wmap[r] : T(0);
-        int64_t b0, b1;
-        row_bounds(a.at, r, b0, b1);
-        const T g = group_sum<T, G>(row_partial<T, G>(a.at, b0, b1, a.u, lg));
-        __syncthreads();  // sw
-        T w = wm;
-        if (!a.wmap) {
-            const int i2 = r / a.n1, i1 = r - i2 * a.n1;
-            w = sw[band_index(i1, i2, a.n1, a.n2, a.levels)];
+        const int lg = threadIdx.x & (G - 1), gi = threadIdx.x / G;
+        int r[NRG];
+        bool rok[NRG];
+        T y[NRG], zc[NRG], sg[NRG], wm[NRG];
+        int64_t b0[NRG], b1[NRG];
+#pragma unroll
+        for (int j = 0; j < NRG; ++j) {  // the rows' own operands load while their entries stream
+            const int row = (blk * NRG + j) * RPB + gi;
+            rok[j] = row < a.at.n;
+            r[j] = rok[j] ? row : a.at.n - 1;
+            y[j] = a.y[r[j]];
+            zc[j] = a.zc[r[j]];
+            sg[j] = a.sigma ? a.sigma[r[j]] : T(1);
+            wm[j] = a.wmap ? a.wmap[r[j]] : T(0);
+            row_bounds(a.at, r[j], b0[j], b1[j]);
         }
-        const T ts = a.tau * sg;
-        const T v = y - ts * g;
-        const T z = soft_w(v, ts * w);
-        if (rok && lg == 0) {
-            bad = !isfinite(v);
-            st[0] = (double)w * fabs((double)y);
-            st[1] = ((double)z - (double)y) * ((double)z - (double)y);
-            a.zn[r] = z;
-            a.y[r] = z + a.beta_next * (z - zc);
+        T acc[NRG];
+        rows_partial<T, G>(a.at, b0, b1, a.u, lg, acc);
+        __syncthreads();  // sw
+#pragma unroll
+        for (int j = 0; j < NRG; ++j) {
+            const T g = group_sum<T, G>(acc[j]);
+            T w = wm[j];
+            if (!a.wmap) {
+                const int i2 = r[j] / a.n1, i1 = r[j] - i2 * a.n1;
+                w = sw[band_index(i1, i2, a.n1, a.n2, a.levels)];
+            }
+            const T ts = a.tau * sg[j];
+            const T v = y[j] - ts * g;
+            const T z = soft_w(v, ts * w);
+            if (rok[j] && lg == 0) {
+                bad |= !isfinite(v);
+                st[0] += (double)w * fabs((double)y[j]);
+                st[1] += ((double)z - (double)y[j]) * ((double)z - (double)y[j]);
+                a.zn[r[j]] = z;
+                a.y[r[j]] = z + a.beta_next * (z - zc[j]);
+            }
         }
     } else {
         __syncthreads();
@@ -337,7 +390,7 @@ template <typename T>
 hipError_t launch_wres(const WResArgs<T> &a, int group, hipStream_t s)
 {
     if (a.a.n <= 0) return hipSuccess;
-    const int nb = (a.a.n + NTW / group - 1) / (NTW / group);
+    const int rows = (NTW / group) * NRG, nb = (a.a.n + rows - 1) / rows;
     PD_WDISPATCH(group, k_wres, dim3(xcd_blocks(nb)), dim3(NTW), 0, s, a);
     return hipGetLastError();
 }
@@ -346,7 +399,7 @@ template <typename T>
 hipError_t launch_wprox(const WProxArgs<T> &a, int group, hipStream_t s)
 {
     if (a.at.n <= 0) return hipSuccess;
-    const int nb = (a.at.n + NTW / group - 1) / (NTW / group);
+    const int rows = (NTW / group) * NRG, nb = (a.at.n + rows - 1) / rows;
     PD_WDISPATCH(group, k_wprox, dim3(xcd_blocks(nb)), dim3(NTW), 0, s, a);
     return hipGetLastError();
 }
