@@ -329,23 +329,25 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
         wr[o] = use && usew ? wv_ : T(0);
     }
 
+    // load every channel's tile at once: lane = fine column (52 of 64 lanes), wave = fine rows
+    constexpr int RPW = AR / (NT / 64);  // 13
+    T v[NC][RPW];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
-        const int ch = ch0 + cc;
-        const T *in = a.in + (int64_t)ch * a.in_plane;
-        // load: lane = fine column (52 of 64 lanes), wave = fine rows
-        constexpr int RPW = AR / (NT / 64);  // 13
-        T v[RPW];
+        const T *in = a.in + (int64_t)(ch0 + cc) * a.in_plane;
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
             const int r = wv + i * (NT / 64);
             const T *rowp = in + (int64_t)wrap(2 * c02 - 10 + r, M2) * a.in_pitch;
-            v[i] = rowp[qc];
+            v[cc][i] = rowp[qc];
         }
+    }
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
         if (cc > 0) __syncthreads();  // previous channel's passes are done
 #pragma unroll
         for (int i = 0; i < RPW; ++i)
-            if (lok) sIn[wv + i * (NT / 64)][lane] = v[i];
+            if (lok) sIn[wv + i * (NT / 64)][lane] = v[cc][i];
         __syncthreads();
         // along x1: task = (fine row r, block of 4 coarse columns)
         for (int t = tid; t < AR * (TC / 4); t += NT) {
