@@ -150,8 +150,14 @@ def cpu_baseline(SI, seconds_target=15.0):
     t = time.perf_counter()
     O.fista(pb, f0, tau, iters)
     dt = time.perf_counter() - t
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(n * n * iters / dt / 1e6, 4), "unit": "Mpixel-iter/s",
-            "cores": O.threads(), "kind": "oracle",
+            "cores": O.threads(), "kind": "oracle", "cpu_model": model,
             "sample": f"512x512 FP64, {iters} FISTA iterations (of the 2000-iteration workload), "
                       f"{dt:.1f} s"}
 
@@ -333,6 +339,7 @@ def colour_case(torch, P, SI, h, iters, n=2048):
     ach = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
     return {"workload": f"{n}x{n}x3 FP32 joint shrinkage, {iters} iterations",
             "mpx_it_s": round(3 * n * n * iters / dt / 1e6, 1), "ms_per_iter": round(1e3 * dt / iters, 4),
+            "alg_frac_20B": round(3 * n * n * iters / dt * 20 / (HBM_PEAK_GBS * 1e9), 5),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom["kernel"] +
                          (f" level {dom['level']}" if dom["level"] else ""), "avg_us": round(dom["avg_us"], 3)},
@@ -487,7 +494,10 @@ def main():
             "config": {"workload": "512x512 FP32 deblurring (Operator 1, Symmlet-6, 9 levels), "
                                    "2000 FISTA iterations per step, FP64 energy reductions",
                        "iters": args.iters, "n1": n, "n2": n, "levels": case.levels},
-            "roofline": roofline}
+            "roofline": roofline,
+            # the method's compulsory traffic in (y, z_prev) form -- read y, z_prev and f0, write z
+            # and y+, 4 B each: 20 B per pixel-iteration -- at this rate, as a fraction of HBM peak
+            "alg_frac_20B": round(value * 1e6 * 20 / (HBM_PEAK_GBS * 1e9), 5)}
     if not args.no_batched:
         log(f"[bench] batched vs per-image: {args.batched_count} images, {args.batched_iters} iterations")
         line["batched"] = batched_vs_per_image(torch, P, SI, h, args.batched_iters, args.batched_count)
