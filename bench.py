@@ -346,7 +346,7 @@ def colour_case(torch, P, SI, h, iters, n=2048):
             "kernels_us": {f"{rw['kernel']}/{rw['level']}": round(rw["avg_us"], 2) for rw in rows}}
 
 
-def wavelet_case(torch, P, SI, h, iters, n=1024, levels=10, eta=3e-3):
+def wavelet_case(torch, P, SI, h, iters, n=1024, levels=10, eta=3e-3, long_iters=2000):
     """FISTA in the wavelet domain (Section 4.3, Appendix A.1) at the paper's
     image size: 1024 x 1024, Operator 1, 10 levels, Theta_L = every entry of
     Psi^* H Psi of magnitude >= eta (built by probing with libpd's transforms,
@@ -415,6 +415,17 @@ def wavelet_case(torch, P, SI, h, iters, n=1024, levels=10, eta=3e-3):
                                   "avg_us": round(kern[dom], 3), "alg_bytes_per_launch": alg[dom]}}
         log(f"[bench] {name}: {ms_it * 1e3:.1f} us/iter, kernels " +
             ", ".join(f"{k} {v:.1f} us" for k, v in kern.items()))
+        # energy of the wavelet-domain problem at y(i), i = 1..long_iters, for the stopping rule below
+        out[name]["_energy"] = run(long_iters)["stats"][:, :2].sum(dim=1).cpu()
+    # iterations to the paper's criterion (eq. 4.3, read as E(i) - E* <= 1e-3 E(0)), with E* the lowest
+    # energy either run reached; the paper's Table 2 counts 84 (FISTA-W) and 38 (FISTA-WP) on its image
+    e_star = min(float(out[k]["_energy"].min()) for k in ("fista_w", "fista_wp"))
+    for k in ("fista_w", "fista_wp"):
+        e = out[k].pop("_energy")
+        ok = torch.nonzero(e - e_star <= 1e-3 * float(e[0])).reshape(-1)
+        its = int(ok[0]) + 1 if ok.numel() else None
+        out[k]["iters_to_criterion"] = its
+        out[k]["ms_to_criterion"] = None if its is None else round(its * out[k]["ms_per_iter"], 3)
     return out
 
 
