@@ -64,10 +64,14 @@ typedef enum { PD_F32 = 0, PD_F64 = 1 } pd_dtype;
 
 typedef enum {
     PD_OP_IDENTITY = 0, /* H = Id: wavelet denoising, the closed-form special case      */
-    PD_OP_ROWBLUR = 1   /* H f(x) = sum_y k_{y2}(x1-y1) k_{y2}(x2-y2) f(y), periodic:     */
+    PD_OP_ROWBLUR = 1,  /* H f(x) = sum_y k_{y2}(x1-y1) k_{y2}(x2-y2) f(y), periodic:     */
                         /* the response of source row y2 is the outer product of one    */
                         /* 1-D profile k_{y2}[-R..R] with itself (Section 1, eq. 1.1;   */
                         /* Operator 1 of Section 4.1 when built by pd_op1_taps)         */
+    PD_OP_PC = 2        /* product-convolution expansion (Section 1, Section 3.1; the   */
+                        /* operator of FISTA-PC, Table 1):                              */
+                        /*   H f = sum_{k<m} u_k * (v_k . f),                           */
+                        /*   (u * g)(x) = sum_d u(d) g(x - d), d in [-R, R]^2, periodic */
 } pd_op_kind;
 
 /* Problem size: n1 x n2 pixels (n1 fastest), `channels` planar channels,
@@ -77,13 +81,22 @@ typedef struct {
     int32_t n1, n2, channels, levels;
 } pd_shape;
 
-/* Blur operator.  taps: device array [n2][2*radius+1] of the call's dtype,
- * row i2 holding the profile k_{i2}[d], d = -radius..radius, of SOURCE row
- * i2 (ignored for PD_OP_IDENTITY).  radius in [0, 9]. */
+/* Blur operator, radius in [0, 9].
+ *   PD_OP_ROWBLUR: taps = device array [n2][2*radius+1] of the call's dtype,
+ *     row i2 holding the profile k_{i2}[d], d = -radius..radius, of SOURCE
+ *     row i2; terms and mult unused.
+ *   PD_OP_PC: terms = m in [1, 64]; taps = device [m][2*radius+1][2*radius+1]
+ *     kernels u_k, row-major in (d2, d1) with d = -radius..radius; mult =
+ *     device [m][n2][n1] multipliers v_k, shared by the channels.  Supported
+ *     by pd_solve and pd_apply_op (not pd_solve_batched or pd_backward:
+ *     PD_ERR_UNSUPPORTED).
+ *   PD_OP_IDENTITY: all fields unused. */
 typedef struct {
     int32_t kind;
     int32_t radius;
     const void *taps;
+    int32_t terms;
+    const void *mult;
 } pd_operator;
 
 /* Low-pass filter h[0..len-1] of the orthogonal wavelet (Section 2.1; the

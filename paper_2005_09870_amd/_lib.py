@@ -21,6 +21,7 @@ PD_F32 = 0
 PD_F64 = 1
 PD_OP_IDENTITY = 0
 PD_OP_ROWBLUR = 1
+PD_OP_PC = 2
 
 
 class pd_shape(ctypes.Structure):
@@ -29,7 +30,8 @@ class pd_shape(ctypes.Structure):
 
 
 class pd_operator(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("radius", ctypes.c_int32), ("taps", ctypes.c_void_p)]
+    _fields_ = [("kind", ctypes.c_int32), ("radius", ctypes.c_int32), ("taps", ctypes.c_void_p),
+                ("terms", ctypes.c_int32), ("mult", ctypes.c_void_p)]
 
 
 class pd_wavelet(ctypes.Structure):

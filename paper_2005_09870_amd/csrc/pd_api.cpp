@@ -15,6 +15,7 @@
 #include "pd.h"
 #include "pd_internal.h"
 #include "pd_kernels.h"
+#include "pd_pckernels.h"
 
 using namespace pd;
 
@@ -47,9 +48,13 @@ int check_op(const pd_operator *op, const pd_shape *s)
 {
     if (!op) return PD_ERR_ARG;
     if (op->kind == PD_OP_IDENTITY) return PD_OK;
-    if (op->kind != PD_OP_ROWBLUR) return PD_ERR_ARG;
+    if (op->kind != PD_OP_ROWBLUR && op->kind != PD_OP_PC) return PD_ERR_ARG;
     if (!op->taps) return PD_ERR_ARG;
     if (op->radius < 0 || op->radius > PD_MAX_RADIUS) return PD_ERR_UNSUPPORTED;
+    if (op->kind == PD_OP_PC) {
+        if (!op->mult || op->terms < 1) return PD_ERR_ARG;
+        if (op->terms > PD_MAX_PC) return PD_ERR_UNSUPPORTED;
+    }
     (void)s;
     return PD_OK;
 }
@@ -389,6 +394,13 @@ int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T
     a.slots = slots;
     a.racc = racc;
     a.rscale = rscale;
+    if (op->kind == PD_OP_PC) {  // product-convolution expansion (no reverse-mode accumulation)
+        if (racc) return PD_ERR_UNSUPPORTED;
+        PcArgs<T> p{x, f0, s, (const T *)op->taps, (const T *)op->mult, c.sh->n1, c.sh->n2, c.sh->channels,
+                    op->radius, op->terms, c.N(), slots};
+        PD_TRY_HIP(timed(PD_K_BLUR, 0, c.st, [&] { return launch_pcblur<T>(p, c.st); }));
+        return PD_OK;
+    }
     PD_TRY_HIP(timed(PD_K_BLUR, 0, c.st, [&] { return launch_blur<T>(a, op->kind == PD_OP_IDENTITY, c.st); }));
     return PD_OK;
 }
@@ -533,6 +545,8 @@ hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weig
     key_put(key, op->kind);
     key_put(key, op->radius);
     key_put(key, op->taps);
+    key_put(key, op->terms);
+    key_put(key, op->mult);
     key_put(key, w->coeff_w);
     key_put(key, w->joint);
     for (int k = 0; k <= c.sh->levels; ++k) key_put(key, w->level_w ? w->level_w[k] : 0.0);
@@ -1186,6 +1200,12 @@ extern "C" int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operat
             PD_TRY_HIP(launch_copy<T>((const T *)in, (T *)out, NC, st));
             return PD_OK;
         }
+        if (op->kind == PD_OP_PC) {
+            PcArgs<T> p{(const T *)in, nullptr, (T *)out, (const T *)op->taps, (const T *)op->mult, shape->n1,
+                        shape->n2, shape->channels, op->radius, op->terms, (int64_t)shape->n1 * shape->n2, nullptr};
+            PD_TRY_HIP(launch_pc_single<T>(p, transpose, st));
+            return PD_OK;
+        }
         BlurArgs<T> a;
         a.x = (const T *)in;
         a.f0 = nullptr;
@@ -1390,7 +1410,7 @@ extern "C" int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operat
         (rc = check_wavelet(wav)) || (rc = check_weights(w, shape)) || (rc = check_params(prm)))
         return rc;
     if (!f0 || !grad_f || !workspace || checkpoint_every < 1) return PD_ERR_ARG;
-    if (w->joint || prm->iter_offset != 0) return PD_ERR_UNSUPPORTED;
+    if (w->joint || prm->iter_offset != 0 || op->kind == PD_OP_PC) return PD_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == PD_F32)
         return backward_impl<float>(shape, op, wav, w, prm, (const float *)f0, (const float *)grad_f,

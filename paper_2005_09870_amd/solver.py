@@ -63,10 +63,24 @@ def pd_op1_taps(n2: int, sigma_max: float = 3.0, mass: float = 0.99):
 
 @dataclass
 class Operator:
-    """Blur operator on the device: PD_OP_IDENTITY or a row-profile table."""
+    """Blur operator on the device: PD_OP_IDENTITY, a row-profile table
+    (PD_OP_ROWBLUR) or a product-convolution expansion (PD_OP_PC: kernels
+    `taps` (m, 2R+1, 2R+1) and multipliers `mult` (m, n2, n1))."""
     kind: int
     radius: int = 0
     taps: torch.Tensor | None = None
+    mult: torch.Tensor | None = None
+
+    @staticmethod
+    def pc(u, v, dtype=torch.float32, device="cuda") -> "Operator":
+        """H f = sum_k u_k * (v_k . f): u (m, 2R+1, 2R+1) kernels, v (m, n2, n1)
+        per-pixel multipliers."""
+        ut = torch.as_tensor(np.asarray(u), dtype=dtype, device=device).contiguous()
+        vt = torch.as_tensor(np.asarray(v), dtype=dtype, device=device).contiguous()
+        if ut.dim() != 3 or ut.shape[1] != ut.shape[2] or ut.shape[1] % 2 == 0 or vt.dim() != 3 \
+                or vt.shape[0] != ut.shape[0]:
+            raise ValueError("u must be (m, 2R+1, 2R+1) and v (m, n2, n1)")
+        return Operator(C.PD_OP_PC, int(ut.shape[1] // 2), ut, vt)
 
     @staticmethod
     def identity() -> "Operator":
@@ -83,7 +97,9 @@ class Operator:
         return Operator(C.PD_OP_ROWBLUR, int(radius), t)
 
     def c(self) -> C.pd_operator:
-        return C.pd_operator(self.kind, self.radius, None if self.taps is None else self.taps.data_ptr())
+        return C.pd_operator(self.kind, self.radius, None if self.taps is None else self.taps.data_ptr(),
+                             0 if self.mult is None else int(self.mult.shape[0]),
+                             None if self.mult is None else self.mult.data_ptr())
 
 
 def _shape(x: torch.Tensor, levels: int) -> C.pd_shape:
@@ -186,7 +202,8 @@ def lipschitz(op: Operator, n1: int, n2: int, iters: int = 200, seed: int = 0,
     x = torch.randn((1, n2, n1), generator=g, dtype=torch.float64).to(device=device, dtype=dtype)
     x /= torch.linalg.vector_norm(x)
     lam = 0.0
-    opd = op if op.taps is None or op.taps.dtype == dtype else Operator(op.kind, op.radius, op.taps.to(dtype))
+    opd = op if op.taps is None or op.taps.dtype == dtype else \
+        Operator(op.kind, op.radius, op.taps.to(dtype), None if op.mult is None else op.mult.to(dtype))
     for _ in range(iters):
         y = pd_apply_op(pd_apply_op(x, opd), opd, transpose=True)
         lam = float(torch.linalg.vector_norm(y))

@@ -79,6 +79,11 @@ def test_argument_errors_are_reported_without_gpu_work():
     assert _call_solve(ok, op=C.pd_operator(9, 0, None)) == C.PD_ERR_ARG
     assert _call_solve(ok, op=C.pd_operator(C.PD_OP_ROWBLUR, 9, None)) == C.PD_ERR_ARG
     assert _call_solve(ok, op=C.pd_operator(C.PD_OP_ROWBLUR, 12, _fake(9))) == C.PD_ERR_UNSUPPORTED
+    # product-convolution expansion: kernels, multipliers and 1..64 terms required
+    assert _call_solve(ok, op=C.pd_operator(C.PD_OP_PC, 3, _fake(9), 0, _fake(10))) == C.PD_ERR_ARG
+    assert _call_solve(ok, op=C.pd_operator(C.PD_OP_PC, 3, _fake(9), 5, None)) == C.PD_ERR_ARG
+    assert _call_solve(ok, op=C.pd_operator(C.PD_OP_PC, 3, _fake(9), 65, _fake(10))) == C.PD_ERR_UNSUPPORTED
+    assert _call_solve(ok, op=C.pd_operator(C.PD_OP_PC, 10, _fake(9), 5, _fake(10))) == C.PD_ERR_UNSUPPORTED
     h3 = np.zeros(3)
     assert _call_solve(ok, wav=C.pd_wavelet(3, h3.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))) \
         == C.PD_ERR_UNSUPPORTED
