@@ -26,6 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA without packed instructions (which this build does not emit): 256 CU x 4 SIMD x 16 lanes
+# x 2 FLOP x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
 
 
 def log(msg: str) -> None:
@@ -429,6 +432,56 @@ def wavelet_case(torch, P, SI, h, iters, n=1024, levels=10, eta=3e-3, long_iters
     return out
 
 
+def pc_case(torch, P, SI, h, iters, n=512, m=5):
+    """FISTA-PC (Table 1) on the 512 x 512 workload: the data come from
+    Operator 1, the solver uses its rank-m product-convolution expansion
+    (m = 5, the paper's order for its first blur).  FP32.  Mpixel-iter/s and
+    the ALU roofline of the fused operator kernel (2 m (2R+1)^2 FMA per pixel,
+    R = 9)."""
+    from paper_2005_09870_amd import pc as PCX
+    dev = "cuda"
+    case = SI.case_512()
+    taps, R = P.pd_op1_taps(n)
+    op = PCX.rowblur_pc_operator(taps, R, m, n, device=dev)
+    op1 = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    clean = torch.as_tensor(case.clean, dtype=torch.float32, device=dev)
+    f0 = (P.pd_apply_op(clean, op1) + torch.as_tensor(case.noise, dtype=torch.float32, device=dev)).contiguous()
+    tau = P.step_size(op, n, n, device=dev)
+    ws = P.solver.workspace(P.pd_workspace_size(P.solver._shape(f0, case.levels), f0.dtype), dev)
+
+    def run(k):
+        return P.pd_solve(f0, op, h, case.levels, tau, k, level_w=case.level_w, ws=ws, stats=True)
+
+    run(5)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run(iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_it = e0.elapsed_time(e1) / iters
+    P.solver.pd_timing_enable(True)
+    run(20)
+    torch.cuda.synchronize()
+    rows = P.solver.pd_timing_read()
+    P.solver.pd_timing_enable(False)
+    kern = {f"{r['kernel']}/{r['level']}": r["avg_us"] for r in rows}
+    W = 2 * 9 + 1
+    flop = 2 * m * W * W * 2 * n * n   # H and H^T, taps padded to R = 9 as the kernel computes them
+    us = kern.get("blur/0")
+    ach = flop / (us * 1e-6) / 1e12 if us else None
+    log(f"[bench] fista-pc 512^2 m={m}: {ms_it * 1e3:.1f} us/iter, operator kernel {us:.1f} us")
+    return {"workload": f"{n}x{n} FP32, Operator 1 data, rank-{m} product-convolution solver operator, "
+                        f"{iters} iterations",
+            "tau": tau, "ms_per_iter": round(ms_it, 4), "mpx_it_s": round(n * n / (ms_it * 1e-3) / 1e6, 1),
+            "kernels_us": {k: round(v, 2) for k, v in kern.items()},
+            "roofline": {"bound": "alu", "achieved": None if ach is None else round(ach, 2),
+                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": None if ach is None else round(ach / FP32_PEAK_TFLOPS, 4),
+                         "traffic": None, "kernel": "pc operator (fused H, H^T)",
+                         "avg_us": None if us is None else round(us, 3), "alg_flop_per_launch": flop}}
+
+
 def copy_calibration(torch, nbytes=256 << 20):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -453,6 +506,8 @@ def main():
     ap.add_argument("--no-colour", action="store_true")
     ap.add_argument("--colour-iters", type=int, default=300)
     ap.add_argument("--no-wavelet", action="store_true")
+    ap.add_argument("--no-pc", action="store_true")
+    ap.add_argument("--pc-iters", type=int, default=200)
     ap.add_argument("--wavelet-iters", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
@@ -523,6 +578,9 @@ def main():
     if not args.no_wavelet:
         log(f"[bench] wavelet domain 1024^2 (FISTA-W / FISTA-WP), {args.wavelet_iters} iterations")
         line["wavelet_1024"] = wavelet_case(torch, P, SI, h, args.wavelet_iters)
+    if not args.no_pc:
+        log(f"[bench] FISTA-PC 512^2, {args.pc_iters} iterations")
+        line["fista_pc_512"] = pc_case(torch, P, SI, h, args.pc_iters)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(SI)

@@ -29,10 +29,16 @@ constexpr int RG = PT + 2 * PR;     // 50: r region
 constexpr int XG = PT + 4 * PR;     // 68: x region
 constexpr int PXP = XG + 1;         // LDS pitches
 constexpr int PRP = RG + 1;
-constexpr int NTP = 256;
-constexpr int RSEG = 10;            // r rows per thread (50 = 5 x 10; 50 columns x 5 = 250 threads)
-constexpr int SSEG = 4;             // s rows per thread (32 = 8 x 4; 32 columns x 8 = 256 threads)
-static_assert(RG % RSEG == 0 && RG * (RG / RSEG) <= NTP && PT * (PT / SSEG) == NTP, "pc tile tasks");
+// Thread layouts (NTP threads; a thread owns RSEG rows of one r column and SSEG rows of one s column):
+// 256 threads (10 / 4 rows) when the image has many tiles, 512 (5 / 2) when few tiles must fill the chip.
+template <int NTP, int RSEG, int SSEG>
+struct PcLayout {
+    static constexpr int nt = NTP, rseg = RSEG, sseg = SSEG;
+    static constexpr int XPT = (XG * XG + NTP - 1) / NTP;  // x-region elements per thread
+    static_assert(RG % RSEG == 0 && RG * (RG / RSEG) <= NTP && PT * (PT / SSEG) == NTP, "pc tile tasks");
+};
+using PcSmall = PcLayout<256, 10, 4>;
+using PcLarge = PcLayout<512, 5, 2>;
 
 __device__ __forceinline__ int wrapp(int a, int n)
 {
@@ -42,7 +48,7 @@ __device__ __forceinline__ int wrapp(int a, int n)
 }
 
 // Taps of term k padded to PR (zero outside radius R) into sU.
-template <typename T>
+template <typename T, int NTP>
 __device__ __forceinline__ void load_taps(const PcArgs<T> &a, int k, T *sU)
 {
     const int W = 2 * a.R + 1;
@@ -54,7 +60,7 @@ __device__ __forceinline__ void load_taps(const PcArgs<T> &a, int k, T *sU)
     }
 }
 
-template <typename T>
+template <typename T, int NTP>
 __device__ void block_add1(double v, double *slots)
 {
     __shared__ double red[NTP / 64];
@@ -71,9 +77,10 @@ __device__ void block_add1(double v, double *slots)
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NTP) void k_pcblur(PcArgs<T> a)
+template <typename T, class LY>
+__global__ __launch_bounds__(LY::nt) void k_pcblur(PcArgs<T> a)
 {
+    constexpr int NTP = LY::nt, RSEG = LY::rseg, SSEG = LY::sseg, XPT = LY::XPT;
     __shared__ T sX[XG][PXP];
     __shared__ T sG[XG][PXP];
     __shared__ T sU[PW * PW];
@@ -101,15 +108,31 @@ __global__ __launch_bounds__(NTP) void k_pcblur(PcArgs<T> a)
 #pragma unroll
     for (int q = 0; q < RSEG; ++q) racc[q] = T(0);
 
+    // multipliers of the x region for term k, prefetched one term ahead
+    T vpre[XPT];
+    auto load_v = [&](int k) {
+        const T *v = a.v + (int64_t)k * n1 * n2;
+#pragma unroll
+        for (int t = 0; t < XPT; ++t) {
+            const int e0 = tid + t * NTP, e = e0 < XG * XG ? e0 : XG * XG - 1;
+            const int i = e / XG, j = e - i * XG;
+            vpre[t] = v[(int64_t)wrapp(o2 - 2 * PR + i, n2) * n1 + wrapp(o1 - 2 * PR + j, n1)];
+        }
+    };
+    load_v(0);
     for (int k = 0; k < a.m; ++k) {
         __syncthreads();  // previous term's sG / sU readers are done (and sX is staged)
-        load_taps(a, k, sU);
-        const T *v = a.v + (int64_t)k * n1 * n2;
-        for (int e = tid; e < XG * XG; e += NTP) {
-            const int i = e / XG, j = e - i * XG;
-            sG[i][j] = v[(int64_t)wrapp(o2 - 2 * PR + i, n2) * n1 + wrapp(o1 - 2 * PR + j, n1)] * sX[i][j];
+        load_taps<T, NTP>(a, k, sU);
+#pragma unroll
+        for (int t = 0; t < XPT; ++t) {
+            const int e = tid + t * NTP;
+            if (e < XG * XG) {
+                const int i = e / XG, j = e - i * XG;
+                sG[i][j] = vpre[t] * sX[i][j];
+            }
         }
         __syncthreads();
+        if (k + 1 < a.m) load_v(k + 1);  // in flight during this term's stencil
         if (rt) {
             // r(i, j) += sum_{a,b} u(a - PR, b - PR) g(i + 2PR - a, j + 2PR - b)  (region indices)
             for (int b = 0; b < PW; ++b) {
@@ -144,15 +167,20 @@ __global__ __launch_bounds__(NTP) void k_pcblur(PcArgs<T> a)
     T sacc[SSEG];
 #pragma unroll
     for (int q = 0; q < SSEG; ++q) sacc[q] = T(0);
+    T vv[SSEG], vn[SSEG];
+    auto load_vo = [&](int k, T (&dst)[SSEG]) {
+        const T *v = a.v + (int64_t)k * n1 * n2;
+#pragma unroll
+        for (int q = 0; q < SSEG; ++q) dst[q] = v[(int64_t)wrapp(o2 + si0 + q, n2) * n1 + wrapp(o1 + sj, n1)];
+    };
+    load_vo(0, vn);
     for (int k = 0; k < a.m; ++k) {
         __syncthreads();  // sR complete; previous term's sU readers done
-        load_taps(a, k, sU);
-        const T *v = a.v + (int64_t)k * n1 * n2;
-        T vv[SSEG];
+        load_taps<T, NTP>(a, k, sU);
 #pragma unroll
-        for (int q = 0; q < SSEG; ++q)
-            vv[q] = v[(int64_t)wrapp(o2 + si0 + q, n2) * n1 + wrapp(o1 + sj, n1)];
+        for (int q = 0; q < SSEG; ++q) vv[q] = vn[q];
         __syncthreads();
+        if (k + 1 < a.m) load_vo(k + 1, vn);
         T h[SSEG];
 #pragma unroll
         for (int q = 0; q < SSEG; ++q) h[q] = T(0);
@@ -177,14 +205,15 @@ __global__ __launch_bounds__(NTP) void k_pcblur(PcArgs<T> a)
         const int gy = o2 + si0 + q, gx = o1 + sj;
         if (gy < n2 && gx < n1) s[(int64_t)gy * n1 + gx] = sacc[q];
     }
-    if (a.slots) block_add1<T>(st, a.slots);
+    if (a.slots) block_add1<T, NTP>(st, a.slots);
 }
 
 // One pass, one thread per output pixel: H x or H^T x (set-up and tests).
+constexpr int NTS = 256;
 template <typename T>
-__global__ __launch_bounds__(NTP) void k_pc_single(PcArgs<T> a, int transpose)
+__global__ __launch_bounds__(NTS) void k_pc_single(PcArgs<T> a, int transpose)
 {
-    const int64_t p = (int64_t)blockIdx.x * NTP + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * NTS + threadIdx.x;
     const int n1 = a.n1, n2 = a.n2;
     if (p >= (int64_t)n1 * n2) return;
     const int i2 = (int)(p / n1), i1 = (int)(p - (int64_t)i2 * n1);
@@ -217,7 +246,11 @@ template <typename T>
 hipError_t launch_pcblur(const PcArgs<T> &a, hipStream_t s)
 {
     dim3 grid((a.n1 + PT - 1) / PT, (a.n2 + PT - 1) / PT, a.C);
-    hipLaunchKernelGGL(k_pcblur<T>, grid, dim3(NTP), 0, s, a);
+    // few tiles: twice the threads per tile so that every SIMD holds two waves
+    if ((int64_t)grid.x * grid.y * grid.z < 512)
+        hipLaunchKernelGGL((k_pcblur<T, PcLarge>), grid, dim3(PcLarge::nt), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pcblur<T, PcSmall>), grid, dim3(PcSmall::nt), 0, s, a);
     return hipGetLastError();
 }
 
@@ -225,8 +258,8 @@ template <typename T>
 hipError_t launch_pc_single(const PcArgs<T> &a, int transpose, hipStream_t s)
 {
     const int64_t N = (int64_t)a.n1 * a.n2;
-    dim3 grid((unsigned)((N + NTP - 1) / NTP), a.C);
-    hipLaunchKernelGGL(k_pc_single<T>, grid, dim3(NTP), 0, s, a, transpose);
+    dim3 grid((unsigned)((N + NTS - 1) / NTS), a.C);
+    hipLaunchKernelGGL(k_pc_single<T>, grid, dim3(NTS), 0, s, a, transpose);
     return hipGetLastError();
 }
 
