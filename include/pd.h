@@ -308,6 +308,55 @@ int pd_wsolve(const pd_shape *shape, int32_t dtype, const pd_csr *theta, const p
               void *z_cur, void *z_prev, int32_t init_from_z0, double *stats, void *workspace,
               size_t ws_bytes, void *stream);
 
+/* ---------------------------------------------------------------- ADMM-PC --
+ * ADMM on eq. 4.1 with a product-convolution operator H = sum_k u_k * (v_k . f)
+ * (Appendix A.2; Table 1).  With g = V f, z = Psi^* f and D = diag(gamma_k Id),
+ * one iteration is, in this order,
+ *   g  <- (U^T U + beta D)^-1 (U^T f0 - xi + beta D V f)
+ *   z  <- Prox_{||.||_{1,w}/beta}(Psi^* f - zeta / beta)
+ *   f  <- (beta sum_k gamma_k v_k^2 + beta)^-1 (V^T (xi + beta D g) + Psi (beta z + zeta))
+ *   xi <- xi + beta D (g - V f);   zeta <- zeta + beta (z - Psi^* f),
+ * started from f = f0, z = Psi^* f0, xi = zeta = 0.  The g system is solved
+ * by the Woodbury identity, whose middle matrix Id + sum_k U_k U_k^T / (beta
+ * gamma_k) is diagonal in the Fourier basis (periodic boundaries, 2-D FFTs);
+ * gamma_k = max |u_k^| normalised to sum 1 (1/m if every kernel is 0).     */
+
+/* Bytes of device workspace pd_admm_solve needs for m = terms. 0 on bad
+ * arguments. */
+size_t pd_admm_workspace_size(const pd_shape *shape, int32_t dtype, int32_t terms);
+
+/* Run `iters` ADMM-PC iterations on each channel (the same operator).
+ *   shape   n1 x n2 x channels, levels; n1 and n2 powers of two in [2, 4096]
+ *           (FP32) or [2, 2048] (FP64), else PD_ERR_UNSUPPORTED.
+ *   op      kind PD_OP_PC (taps [m][2R+1][2R+1], mult [m][n2][n1] device).
+ *   w       level_w (host) or coeff_w (device [n2][n1], every channel);
+ *           joint must be 0.
+ *   beta    beta1 = beta2 > 0 (finite).
+ *   f0      device [channels][n2][n1]; f_out, z_out device, same size,
+ *           written (f and z after the last iteration; iters = 0 gives f0
+ *           and Psi^* f0).  No two of f0, f_out, z_out may alias.
+ *   stats   device double [iters][3] or NULL: per iteration, summed over
+ *           channels, ||g - V f||^2_D, ||z - Psi^* f||^2 and ||z||_{1,w}
+ *           (the primal residuals after the multiplier step, and the
+ *           penalty), accumulated in FP64; zeroed by the call.
+ * Asynchronous on `stream` (no host synchronisation).
+ * Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_TAU (beta), PD_ERR_WORKSPACE,
+ * PD_ERR_UNSUPPORTED, PD_ERR_HIP. */
+int pd_admm_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                  const pd_weights *w, double beta, int32_t iters, const void *f0, void *f_out, void *z_out,
+                  double *stats, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of twiddle workspace pd_fft2 needs. 0 on bad arguments. */
+size_t pd_fft2_workspace_size(int32_t n1, int32_t n2, int32_t dtype);
+
+/* In-place 2-D DFT of `batch` complex planes (the transform ADMM-PC's g-update
+ * uses): data device [batch][n2][n1] interleaved (re, im) of the dtype;
+ * forward X(k) = sum_p x(p) exp(-2 pi i <k, p / n>), inverse with the opposite
+ * sign and a 1/(n1 n2) scale.  Sizes as for pd_admm_solve.
+ * Errors: PD_ERR_ARG, PD_ERR_WORKSPACE, PD_ERR_UNSUPPORTED, PD_ERR_HIP. */
+int pd_fft2(int32_t n1, int32_t n2, int32_t batch, int32_t dtype, int32_t inverse, void *data, void *workspace,
+            size_t ws_bytes, void *stream);
+
 /* Diagnostics: per-launch kernel timing.  While enabled, every kernel launch
  * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt / pd_wsolve is bracketed by
  * two HIP events recorded on its launch stream, keyed by kernel class and

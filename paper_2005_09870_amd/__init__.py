@@ -12,7 +12,10 @@ from .solver import (  # noqa: F401
     pd_backward,
     solve_autograd,
     lipschitz,
+    pd_admm_solve,
+    pd_admm_workspace_size,
     pd_apply_op,
+    pd_fft2,
     pd_fwt,
     pd_graphs_enable,
     pd_op1_taps,

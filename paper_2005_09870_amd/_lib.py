@@ -64,7 +64,8 @@ EXPORTS = [
     "pd_backward_workspace_size", "pd_backward", "pd_fwt", "pd_apply_op", "pd_symmlet",
     "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
-    "pd_wsolve_workspace_size", "pd_wsolve",
+    "pd_wsolve_workspace_size", "pd_wsolve", "pd_admm_workspace_size", "pd_admm_solve",
+    "pd_fft2_workspace_size", "pd_fft2",
 ]
 
 PD_K_BLUR, PD_K_SYNTH, PD_K_ANALYSIS, PD_K_COARSE, PD_K_OTHER = 1, 2, 3, 4, 5
@@ -133,6 +134,15 @@ def load() -> ctypes.CDLL:
     L.pd_wsolve.argtypes = [P(pd_shape), i32, P(pd_csr), P(pd_csr), P(pd_weights), P(pd_params), i32,
                             vp, vp, vp, i32, vp, vp, sz, vp]
     L.pd_wsolve.restype = ctypes.c_int
+    L.pd_admm_workspace_size.argtypes = [P(pd_shape), i32, i32]
+    L.pd_admm_workspace_size.restype = sz
+    L.pd_admm_solve.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights), d, i32,
+                                vp, vp, vp, vp, vp, sz, vp]
+    L.pd_admm_solve.restype = ctypes.c_int
+    L.pd_fft2_workspace_size.argtypes = [i32, i32, i32]
+    L.pd_fft2_workspace_size.restype = sz
+    L.pd_fft2.argtypes = [i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.pd_fft2.restype = ctypes.c_int
     L.pd_strerror.argtypes = [i32]
     L.pd_strerror.restype = ctypes.c_char_p
     _lib = L

@@ -16,6 +16,7 @@
 #include "pd_internal.h"
 #include "pd_kernels.h"
 #include "pd_pckernels.h"
+#include "pd_admm.h"
 
 using namespace pd;
 
@@ -1417,4 +1418,216 @@ extern "C" int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operat
                                     (float *)grad_f0, (float *)grad_w, checkpoint_every, workspace, ws_bytes, st);
     return backward_impl<double>(shape, op, wav, w, prm, (const double *)f0, (const double *)grad_f,
                                  (double *)grad_f0, (double *)grad_w, checkpoint_every, workspace, ws_bytes, st);
+}
+
+// ------------------------------------------------------------------ ADMM-PC --
+// ADMM on eq. 4.1 with a product-convolution operator H = U V (Appendix A.2):
+// g = (U^T U + beta1 D)^-1 (U^T f0 - xi + beta1 D V f) by the Woodbury
+// identity in the Fourier basis, z = Prox(Psi^* f - zeta / beta2), f by its
+// diagonal normal equations, then the multiplier updates; beta1 = beta2 =
+// beta, gamma_k = max|u_k^| normalised to sum 1, start f = f0, z = Psi^* f0,
+// xi = zeta = 0.  Channels are solved one after the other (same operator).
+namespace {
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+struct AdmmLayout {
+    size_t zeta, g, xi, utf0, den, mh, tz, tfz, tfs, uh, cb, th, tw1, tw2, gam, mx, total;
+};
+
+AdmmLayout admm_layout(const pd_shape *sh, size_t es, int m)
+{
+    pd_shape s1 = *sh;
+    s1.channels = 1;
+    const size_t N = (size_t)sh->n1 * sh->n2;
+    AdmmLayout l;
+    size_t off = align_up(layout(&s1, es).total);
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    l.zeta = take(N * es);
+    l.g = take((size_t)m * N * es);
+    l.xi = take((size_t)m * N * es);
+    l.utf0 = take((size_t)m * N * es);
+    l.den = take(N * es);
+    l.mh = take(N * es);
+    l.tz = take(N * es);
+    l.tfz = take(N * es);
+    l.tfs = take(N * es);
+    l.uh = take((size_t)m * N * 2 * es);
+    l.cb = take(N * 2 * es);
+    l.th = take(N * 2 * es);
+    l.tw1 = take((size_t)sh->n1 * es);   // n1/2 complex
+    l.tw2 = take((size_t)sh->n2 * es);
+    l.gam = take((size_t)m * es);
+    l.mx = take((size_t)m * es);
+    l.total = off;
+    return l;
+}
+
+template <typename T>
+int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w, double beta,
+              int iters, const T *f0, T *f_out, T *z_out, double *stats, void *workspace, size_t ws_bytes,
+              hipStream_t st)
+{
+    const int n1 = sh->n1, n2 = sh->n2, m = op->terms;
+    const int64_t N = (int64_t)n1 * n2;
+    const AdmmLayout L = admm_layout(sh, sizeof(T), m);
+    if (ws_bytes < L.total) return PD_ERR_WORKSPACE;
+    char *ws = (char *)workspace;
+    pd_shape s1 = *sh;
+    s1.channels = 1;
+    Ctx<T> c = make_ctx<T>(&s1, wav, workspace, st, 0);
+    if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
+    AdmmArgs<T> a{};
+    a.n1 = n1;
+    a.n2 = n2;
+    a.m = m;
+    a.levels = sh->levels;
+    a.N = N;
+    a.beta1 = a.beta2 = (T)beta;
+    a.gam = (const T *)(ws + L.gam);
+    a.v = (const T *)op->mult;
+    a.uh = (const Cx<T> *)(ws + L.uh);
+    a.mh = (const T *)(ws + L.mh);
+    a.den = (const T *)(ws + L.den);
+    a.utf0 = (const T *)(ws + L.utf0);
+    a.g = (T *)(ws + L.g);
+    a.xi = (T *)(ws + L.xi);
+    a.zeta = (T *)(ws + L.zeta);
+    a.tz = (T *)(ws + L.tz);
+    a.cb = (Cx<T> *)(ws + L.cb);
+    a.th = (Cx<T> *)(ws + L.th);
+    a.wmap = (const T *)w->coeff_w;
+    for (int k = 0; k <= PD_MAXL; ++k) a.wlev[k] = (w->level_w && k <= sh->levels) ? (T)w->level_w[k] : T(0);
+    T *tfz = (T *)(ws + L.tfz), *tfs = (T *)(ws + L.tfs);
+    Cx<T> *tw1 = (Cx<T> *)(ws + L.tw1), *tw2 = (Cx<T> *)(ws + L.tw2);
+    Cx<T> *uh = (Cx<T> *)(ws + L.uh);
+
+    // twiddles, kernel spectra, gamma_k = ||U_k|| normalised to sum 1, diagonal factors
+    PD_TRY_HIP(launch_admm_twiddle<T>(tw1, n1, st));
+    PD_TRY_HIP(launch_admm_twiddle<T>(tw2, n2, st));
+    PD_TRY_HIP(launch_admm_padk<T>((const T *)op->taps, op->radius, m, n1, n2, uh, st));
+    PD_TRY_HIP(launch_fft2<T>(uh, n1, n2, m, tw1, tw2, 0, st));
+    PD_TRY_HIP(launch_admm_absmax<T>(uh, m, N, (T *)(ws + L.mx), st));
+    PD_TRY_HIP(launch_admm_gamma<T>((const T *)(ws + L.mx), m, (T *)(ws + L.gam), st));
+    PD_TRY_HIP(launch_admm_diag<T>(a, st));
+
+    if (stats && iters > 0) PD_TRY_HIP(launch_fill<double>(stats, 0.0, (int64_t)iters * 3, st));
+    for (int ch = 0; ch < sh->channels; ++ch) {
+        const T *f0c = f0 + ch * N;
+        a.f = f_out + ch * N;
+        a.z = z_out + ch * N;
+        // U_k^T f0 through the spectra
+        PD_TRY_HIP(launch_admm_real<T>(f0c, a.cb, N, st));
+        PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, 1, tw1, tw2, 0, st));
+        for (int k = 0; k < m; ++k) {
+            PD_TRY_HIP(launch_admm_conjmul<T>(uh + k * N, a.cb, a.th, N, st));
+            PD_TRY_HIP(launch_fft2<T>(a.th, n1, n2, 1, tw1, tw2, 1, st));
+            PD_TRY_HIP(launch_admm_takere<T>(a.th, (T *)a.utf0 + k * N, N, st));
+        }
+        // start: f = f0, z = Psi^* f, xi = zeta = 0
+        PD_TRY_HIP(launch_copy<T>(f0c, a.f, N, st));
+        int rc;
+        if ((rc = analysis_plain<T>(c, a.f, a.tz)) != PD_OK) return rc;
+        PD_TRY_HIP(launch_copy<T>(a.tz, a.z, N, st));
+        PD_TRY_HIP(launch_fill<T>(a.zeta, T(0), N, st));
+        PD_TRY_HIP(launch_fill<T>(a.xi, T(0), (int64_t)m * N, st));
+        if (stats && iters > 0) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
+        for (int it = 0; it < iters; ++it) {
+            a.slots = stats ? c.slots(it) : nullptr;
+            // g: Woodbury with the Fourier-diagonal middle matrix
+            for (int k = 0; k < m; ++k) {
+                PD_TRY_HIP(launch_admm_a<T>(a, k, st));
+                PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, 1, tw1, tw2, 0, st));
+                PD_TRY_HIP(launch_admm_acc<T>(a, k, st));
+            }
+            for (int k = 0; k < m; ++k) {
+                PD_TRY_HIP(launch_admm_q<T>(a, k, st));
+                PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, 1, tw1, tw2, 1, st));
+                PD_TRY_HIP(launch_admm_g<T>(a, k, st));
+            }
+            // z (from Psi^* f of the previous step), then f, then the multipliers
+            a.tf = tfz;
+            PD_TRY_HIP(launch_admm_z<T>(a, st));
+            if ((rc = synth_chain<T>(c, tfz, tfz, T(0), tfs)) != PD_OK) return rc;
+            a.tf = tfs;
+            PD_TRY_HIP(launch_admm_f<T>(a, st));
+            if ((rc = analysis_plain<T>(c, a.f, a.tz)) != PD_OK) return rc;
+            PD_TRY_HIP(launch_admm_zeta<T>(a, st));
+            if (stats && ((it + 1) % PD_RING == 0 || it == iters - 1)) {
+                const int cnt = (it % PD_RING) + 1;
+                PD_TRY_HIP(launch_stats_finalize(c.ring(), stats, it + 1 - cnt, cnt, st));
+            }
+        }
+    }
+    return PD_OK;
+}
+
+}  // namespace
+
+extern "C" size_t pd_admm_workspace_size(const pd_shape *shape, int32_t dtype, int32_t terms)
+{
+    if (check_shape(shape) != PD_OK || check_dtype(dtype) != PD_OK || terms < 1 || terms > PD_MAX_PC) return 0;
+    return admm_layout(shape, dtype == PD_F64 ? 8 : 4, terms).total;
+}
+
+extern "C" int pd_admm_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                             const pd_weights *w, double beta, int32_t iters, const void *f0, void *f_out,
+                             void *z_out, double *stats, void *workspace, size_t ws_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_shape(shape)) || (rc = check_dtype(dtype)) || (rc = check_op(op, shape)) ||
+        (rc = check_wavelet(wav)) || (rc = check_weights(w, shape)))
+        return rc;
+    if (op->kind != PD_OP_PC || w->joint) return PD_ERR_UNSUPPORTED;
+    const int nmax = dtype == PD_F64 ? 2048 : 4096;  // one FFT line and its ping-pong copy within 64 KiB of LDS
+    if (!pow2_in(shape->n1, 2, nmax) || !pow2_in(shape->n2, 2, nmax)) return PD_ERR_UNSUPPORTED;
+    if (!std::isfinite(beta) || beta <= 0.0) return PD_ERR_TAU;
+    if (iters < 0 || !f0 || !f_out || !z_out || !workspace) return PD_ERR_ARG;
+    if (f0 == f_out || f0 == z_out || f_out == z_out) return PD_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == PD_F32)
+        return admm_impl<float>(shape, op, wav, w, beta, iters, (const float *)f0, (float *)f_out, (float *)z_out,
+                                stats, workspace, ws_bytes, st);
+    return admm_impl<double>(shape, op, wav, w, beta, iters, (const double *)f0, (double *)f_out, (double *)z_out,
+                             stats, workspace, ws_bytes, st);
+}
+
+extern "C" size_t pd_fft2_workspace_size(int32_t n1, int32_t n2, int32_t dtype)
+{
+    if (check_dtype(dtype) != PD_OK) return 0;
+    const int nmax = dtype == PD_F64 ? 2048 : 4096;
+    if (!pow2_in(n1, 2, nmax) || !pow2_in(n2, 2, nmax)) return 0;
+    const size_t es = dtype == PD_F64 ? 8 : 4;
+    return align_up((size_t)n1 * es) + align_up((size_t)n2 * es);
+}
+
+extern "C" int pd_fft2(int32_t n1, int32_t n2, int32_t batch, int32_t dtype, int32_t inverse, void *data,
+                       void *workspace, size_t ws_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_dtype(dtype))) return rc;
+    const int nmax = dtype == PD_F64 ? 2048 : 4096;
+    if (!pow2_in(n1, 2, nmax) || !pow2_in(n2, 2, nmax)) return PD_ERR_UNSUPPORTED;
+    if (batch < 0 || (batch > 0 && (!data || !workspace))) return PD_ERR_ARG;
+    if (batch == 0) return PD_OK;
+    if (ws_bytes < pd_fft2_workspace_size(n1, n2, dtype)) return PD_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = dtype == PD_F64 ? 8 : 4, o2 = align_up((size_t)n1 * es);
+    char *ws = (char *)workspace;
+    if (dtype == PD_F32) {
+        Cx<float> *t1 = (Cx<float> *)ws, *t2 = (Cx<float> *)(ws + o2);
+        PD_TRY_HIP(launch_admm_twiddle<float>(t1, n1, st));
+        PD_TRY_HIP(launch_admm_twiddle<float>(t2, n2, st));
+        PD_TRY_HIP(launch_fft2<float>((Cx<float> *)data, n1, n2, batch, t1, t2, inverse != 0, st));
+    } else {
+        Cx<double> *t1 = (Cx<double> *)ws, *t2 = (Cx<double> *)(ws + o2);
+        PD_TRY_HIP(launch_admm_twiddle<double>(t1, n1, st));
+        PD_TRY_HIP(launch_admm_twiddle<double>(t2, n2, st));
+        PD_TRY_HIP(launch_fft2<double>((Cx<double> *)data, n1, n2, batch, t1, t2, inverse != 0, st));
+    }
+    return PD_OK;
 }

@@ -466,3 +466,62 @@ def pd_wsolve(z0: torch.Tensor, theta: Csr, theta_t: Csr, levels: int, tau: floa
                             _stream(z0.device))
     C.check(rc, "pd_wsolve")
     return {"z_cur": z_cur, "z_prev": z_prev, "stats": None if st is None else st[:iters]}
+
+
+def pd_admm_workspace_size(n1: int, n2: int, channels: int, levels: int, terms: int, dtype: torch.dtype) -> int:
+    shape = C.pd_shape(n1, n2, channels, levels)
+    return int(C.load().pd_admm_workspace_size(ctypes.byref(shape), _dtype_code(dtype), int(terms)))
+
+
+def pd_admm_solve(f0: torch.Tensor, op: Operator, h, levels: int, beta: float, iters: int,
+                  level_w=None, coeff_w: torch.Tensor | None = None, stats: bool = False,
+                  ws: torch.Tensor | None = None):
+    """ADMM-PC (Appendix A.2) on 1/2||H Psi z - f0||^2 + ||z||_{1,w} with H the
+    product-convolution expansion `op` (Operator.pc).  f0: (n2, n1) or
+    (C, n2, n1).  Returns dict(f, z, stats) with stats (iters, 3) FP64:
+    ||g - V f||^2_D, ||z - Psi^* f||^2, ||z||_{1,w} per iteration."""
+    _check_dev(f0, coeff_w)
+    if op.kind != C.PD_OP_PC:
+        raise ValueError("pd_admm_solve needs a product-convolution operator")
+    shape = _shape(f0, levels)
+    wav, _hk = _wavelet(h)
+    lw = None
+    if level_w is not None:
+        lw = np.ascontiguousarray(np.asarray(level_w, dtype=np.float64))
+        if lw.shape != (levels + 1,):
+            raise ValueError("level_w needs levels+1 entries")
+    w = C.pd_weights(_dptr(lw) if lw is not None else None,
+                     None if coeff_w is None else coeff_w.data_ptr(), 0)
+    f = torch.empty_like(f0)
+    z = torch.empty_like(f0)
+    st = torch.empty((max(iters, 1), 3), dtype=torch.float64, device=f0.device) if stats else None
+    need = int(C.load().pd_admm_workspace_size(ctypes.byref(shape), _dtype_code(f0.dtype), int(op.mult.shape[0])))
+    if need == 0:
+        raise ValueError("pd_admm_solve: unsupported shape or terms")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, f0.device)
+    oc = op.c()
+    rc = C.load().pd_admm_solve(ctypes.byref(shape), _dtype_code(f0.dtype), ctypes.byref(oc), ctypes.byref(wav),
+                                ctypes.byref(w), float(beta), int(iters), _ptr(f0), _ptr(f), _ptr(z), _ptr(st),
+                                _ptr(ws), ws.numel(), _stream(f0.device))
+    C.check(rc, "pd_admm_solve")
+    return {"f": f, "z": z, "stats": None if st is None else st[:iters]}
+
+
+def pd_fft2(x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
+    """2-D DFT over the last two axes of a complex64/complex128 tensor (a copy)."""
+    _check_dev(x)
+    if x.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("pd_fft2 needs complex64 or complex128")
+    y = x.contiguous().clone()
+    n2, n1 = y.shape[-2:]
+    batch = y.numel() // (n1 * n2) if y.numel() else 0
+    dt = C.PD_F32 if y.dtype == torch.complex64 else C.PD_F64
+    need = int(C.load().pd_fft2_workspace_size(int(n1), int(n2), dt))
+    if need == 0:
+        raise ValueError("pd_fft2: sizes must be powers of two within the LDS limit")
+    ws = workspace(need, y.device)
+    rc = C.load().pd_fft2(int(n1), int(n2), int(batch), dt, 1 if inverse else 0, _ptr(y), _ptr(ws), ws.numel(),
+                          _stream(y.device))
+    C.check(rc, "pd_fft2")
+    return y

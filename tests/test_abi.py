@@ -153,3 +153,55 @@ def test_wavelet_domain_argument_errors_without_gpu_work():
                               None) == C.PD_ERR_WORKSPACE
     assert L.pd_spmv(ctypes.byref(a), C.PD_F32, None, _fake(2), None) == C.PD_ERR_ARG
     assert L.pd_wjacobi(ctypes.byref(a), C.PD_F32, None, None) == C.PD_ERR_ARG
+
+
+def _call_admm(shape, dtype=C.PD_F32, op=None, w=None, beta=1.0, iters=5, f0=1, fo=2, zo=3, ws=4,
+               ws_bytes=None):
+    L = C.load()
+    h = S.pd_symmlet(6)
+    wav = C.pd_wavelet(12, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    lw = np.zeros(shape.levels + 1 if shape.levels > 0 else 1)
+    w = w or C.pd_weights(lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0)
+    op = op or C.pd_operator(C.PD_OP_PC, 2, _fake(8), 3, _fake(9))
+    if ws_bytes is None:
+        ws_bytes = 1 << 40
+    return L.pd_admm_solve(ctypes.byref(shape), dtype, ctypes.byref(op), ctypes.byref(wav), ctypes.byref(w),
+                           beta, iters, _fake(f0) if f0 else None, _fake(fo) if fo else None,
+                           _fake(zo) if zo else None, None, _fake(ws) if ws else None, ws_bytes, None)
+
+
+def test_admm_argument_errors_without_gpu_work():
+    """pd_admm_solve / pd_fft2 reject bad arguments before any device work."""
+    L = C.load()
+    ok = C.pd_shape(64, 32, 2, 4)
+    assert _call_admm(C.pd_shape(96, 64, 1, 3)) == C.PD_ERR_UNSUPPORTED       # 96 is not a power of two
+    assert _call_admm(C.pd_shape(4096, 64, 1, 3), dtype=C.PD_F64) == C.PD_ERR_UNSUPPORTED  # FP64 LDS limit
+    assert _call_admm(C.pd_shape(64, 64, 0, 3)) == C.PD_ERR_SHAPE
+    assert _call_admm(ok, dtype=7) == C.PD_ERR_ARG
+    assert _call_admm(ok, op=C.pd_operator(C.PD_OP_ROWBLUR, 2, _fake(8), 0, None)) == C.PD_ERR_UNSUPPORTED
+    assert _call_admm(ok, op=C.pd_operator(C.PD_OP_PC, 2, _fake(8), 0, _fake(9))) == C.PD_ERR_ARG
+    assert _call_admm(ok, op=C.pd_operator(C.PD_OP_PC, 2, _fake(8), 65, _fake(9))) == C.PD_ERR_UNSUPPORTED
+    assert _call_admm(ok, beta=0.0) == C.PD_ERR_TAU
+    assert _call_admm(ok, beta=float("nan")) == C.PD_ERR_TAU
+    assert _call_admm(ok, iters=-1) == C.PD_ERR_ARG
+    assert _call_admm(ok, fo=1) == C.PD_ERR_ARG              # f_out aliases f0
+    assert _call_admm(ok, zo=2) == C.PD_ERR_ARG              # z_out aliases f_out
+    assert _call_admm(ok, f0=0) == C.PD_ERR_ARG
+    assert _call_admm(ok, w=C.pd_weights(None, None, 0)) == C.PD_ERR_ARG
+    lw = np.zeros(5)
+    joint = C.pd_weights(lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 1)
+    assert _call_admm(ok, w=joint) == C.PD_ERR_UNSUPPORTED
+    need = L.pd_admm_workspace_size(ctypes.byref(ok), C.PD_F32, 3)
+    assert need > (3 * 3 + 2 * 3 * 2) * 64 * 32 * 4
+    assert L.pd_admm_workspace_size(ctypes.byref(ok), C.PD_F32, 4) > need
+    assert L.pd_admm_workspace_size(ctypes.byref(ok), C.PD_F32, 0) == 0
+    assert _call_admm(ok, ws_bytes=need - 1) == C.PD_ERR_WORKSPACE
+    # FFT utility
+    assert L.pd_fft2_workspace_size(64, 32, C.PD_F32) > 0
+    assert L.pd_fft2_workspace_size(48, 32, C.PD_F32) == 0
+    assert L.pd_fft2_workspace_size(4096, 8, C.PD_F64) == 0
+    assert L.pd_fft2(48, 32, 1, C.PD_F32, 0, _fake(1), _fake(2), 1 << 20, None) == C.PD_ERR_UNSUPPORTED
+    assert L.pd_fft2(64, 32, -1, C.PD_F32, 0, _fake(1), _fake(2), 1 << 20, None) == C.PD_ERR_ARG
+    assert L.pd_fft2(64, 32, 1, C.PD_F32, 0, None, _fake(2), 1 << 20, None) == C.PD_ERR_ARG
+    assert L.pd_fft2(64, 32, 1, C.PD_F32, 0, _fake(1), _fake(2), 8, None) == C.PD_ERR_WORKSPACE
+    assert L.pd_fft2(64, 32, 0, C.PD_F32, 0, None, None, 0, None) == C.PD_OK

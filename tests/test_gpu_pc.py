@@ -111,3 +111,29 @@ def test_fista_pc_512_full_size_first_iterations():
     out = P.pd_solve(_t(f0[None], torch.float32), P.Operator.pc(u, v), H6, case.levels, tau, 3,
                      level_w=case.level_w)
     assert np.abs(_np(out["f"])[0] - ref["f"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("R,m", [(0, 1), (2, 3), (5, 2)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_pc_small_radius_random_terms(R, m, dtype, tol):
+    """Random kernels of radius < 9 (padded with zero taps in the kernel) and
+    random per-pixel multipliers: single pass and fused (through 12 FISTA-PC
+    iterations) against the oracle."""
+    n2, n1 = 48, 64
+    rng = np.random.default_rng(100 + R)
+    u = rng.standard_normal((m, 2 * R + 1, 2 * R + 1)) / (2 * R + 1)
+    v = rng.uniform(0.5, 1.5, (m, n2, n1))
+    op = P.Operator.pc(u, v, dtype=dtype)
+    x = rng.standard_normal((1, n2, n1))
+    for tr in (False, True):
+        got = _np(P.pd_apply_op(_t(x, dtype), op, transpose=tr))[0]
+        ref = PC.apply_pc(u, v, x[0], transpose=tr)
+        assert np.abs(got - ref).max() < tol * max(1.0, np.abs(ref).max())
+    c = SI.make_case(n1, n2, 1, 4, 3, "const", 0.1, 0.1, levels=4, seed=7)
+    f0 = PC.apply_pc(u, v, c.clean[0]) + c.noise[0]
+    tau = 1.0 / (PC.lipschitz_pc(u, v, (n2, n1), iters=100) * 1.01)
+    w = O.expand_level_weights(c.level_w, n1, n2, 4)[0]
+    ref = PC.fista_pc(u, v, H6, 4, f0, w, tau, 12)
+    out = P.pd_solve(_t(f0[None], dtype), op, H6, 4, tau, 12, level_w=c.level_w)
+    scale = max(1.0, np.abs(ref["f"]).max())
+    assert np.abs(_np(out["f"])[0] - ref["f"]).max() < tol * 10 * scale
