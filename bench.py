@@ -482,6 +482,62 @@ def pc_case(torch, P, SI, h, iters, n=512, m=5):
                          "avg_us": None if us is None else round(us, 3), "alg_flop_per_launch": flop}}
 
 
+def admm_case(torch, P, SI, h, iters, n=512, m=5, beta=1.0):
+    """ADMM-PC (Appendix A.2, Table 1) on the same 512 x 512 workload as
+    FISTA-PC: rank-m expansion of Operator 1, beta1 = beta2 = 1, FP32.
+    Mpixel-iter/s, the per-kernel breakdown, and the HBM roofline of the
+    kernel with the largest share of the iteration."""
+    from paper_2005_09870_amd import pc as PCX
+    dev = "cuda"
+    case = SI.case_512()
+    taps, R = P.pd_op1_taps(n)
+    op = PCX.rowblur_pc_operator(taps, R, m, n, device=dev)
+    op1 = P.Operator.op1(n, dtype=torch.float32, device=dev)
+    clean = torch.as_tensor(case.clean, dtype=torch.float32, device=dev)
+    f0 = (P.pd_apply_op(clean, op1) + torch.as_tensor(case.noise, dtype=torch.float32, device=dev)).contiguous()
+    ws = P.solver.workspace(P.pd_admm_workspace_size(n, n, 1, case.levels, m, torch.float32), dev)
+
+    def run(k):
+        return P.pd_admm_solve(f0, op, h, case.levels, beta, k, level_w=case.level_w, ws=ws, stats=True)
+
+    run(5)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run(iters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_it = e0.elapsed_time(e1) / iters
+    P.solver.pd_timing_enable(True)
+    k_t = 20
+    run(k_t)
+    torch.cuda.synchronize()
+    rows = P.solver.pd_timing_read()
+    P.solver.pd_timing_enable(False)
+    kern = {f"{r['kernel']}/{r['level']}": r["avg_us"] for r in rows}
+    # algorithmic bytes per launch (FP32): an FFT pass reads and writes the m complex planes;
+    # accq reads u^_k, cb_k, mh, writes cb_k; f reads g, cb, xi, v, utf0 per term and tfs, den,
+    # writes xi, g, cb per term and f; zeta reads z, tz, zeta, writes zeta, z, tf
+    N = n * n
+    alg = {"fft/0": 16 * m * N, "fft/1": 16 * m * N, "fft/2": 16 * m * N, "fft/3": 16 * m * N,
+           "admm/1": (24 * m + 4) * N, "admm/2": (40 * m + 12) * N, "admm/3": 24 * N}
+    per_it = {r["kernel"] + "/" + str(r["level"]): r["total_ms"] * 1e3 / k_t for r in rows}
+    dom = max((k for k in alg if k in per_it), key=lambda k: per_it[k], default=None)
+    us = kern.get(dom) if dom else None
+    ach = alg[dom] / (us * 1e-6) / 1e9 if us else None
+    log(f"[bench] admm-pc 512^2 m={m}: {ms_it * 1e3:.1f} us/iter, dominant {dom} {us:.1f} us")
+    return {"workload": f"{n}x{n} FP32, Operator 1 data, rank-{m} product-convolution ADMM (beta {beta}), "
+                        f"{iters} iterations",
+            "ms_per_iter": round(ms_it, 4), "mpx_it_s": round(N / (ms_it * 1e-3) / 1e6, 1),
+            "kernels_us": {k: round(v, 2) for k, v in kern.items()},
+            "kernel_us_per_iter": {k: round(v, 2) for k, v in per_it.items()},
+            "roofline": {"bound": "hbm", "achieved": None if ach is None else round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": dom, "avg_us": None if us is None else round(us, 3),
+                         "alg_bytes_per_launch": None if dom is None else alg[dom]}}
+
+
 def copy_calibration(torch, nbytes=256 << 20):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -509,6 +565,8 @@ def main():
     ap.add_argument("--no-pc", action="store_true")
     ap.add_argument("--pc-iters", type=int, default=200)
     ap.add_argument("--wavelet-iters", type=int, default=200)
+    ap.add_argument("--no-admm", action="store_true")
+    ap.add_argument("--admm-iters", type=int, default=200)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -581,6 +639,9 @@ def main():
     if not args.no_pc:
         log(f"[bench] FISTA-PC 512^2, {args.pc_iters} iterations")
         line["fista_pc_512"] = pc_case(torch, P, SI, h, args.pc_iters)
+    if not args.no_admm:
+        log(f"[bench] ADMM-PC 512^2, {args.admm_iters} iterations")
+        line["admm_pc_512"] = admm_case(torch, P, SI, h, args.admm_iters)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(SI)

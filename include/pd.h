@@ -358,7 +358,8 @@ int pd_fft2(int32_t n1, int32_t n2, int32_t batch, int32_t dtype, int32_t invers
             size_t ws_bytes, void *stream);
 
 /* Diagnostics: per-launch kernel timing.  While enabled, every kernel launch
- * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt / pd_wsolve is bracketed by
+ * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt / pd_wsolve /
+ * pd_admm_solve (its iteration loop) is bracketed by
  * two HIP events recorded on its launch stream, keyed by kernel class and
  * decomposition level.  Adds one event pair per launch; not thread-safe.   */
 typedef enum {
@@ -368,7 +369,11 @@ typedef enum {
     PD_K_COARSE = 4,    /* all coarse levels of an iteration in one workgroup  */
     PD_K_OTHER = 5,     /* copies and set-up                                   */
     PD_K_WRES = 6,      /* wavelet domain: u = Theta_L y - z0                  */
-    PD_K_WPROX = 7      /* wavelet domain: Theta_L^T u, prox and momentum      */
+    PD_K_WPROX = 7,     /* wavelet domain: Theta_L^T u, prox and momentum      */
+    PD_K_FFT = 8,       /* ADMM-PC: one 2-D FFT pass over the m planes (level 0/1
+                           forward rows/columns, 2/3 inverse rows/columns)     */
+    PD_K_ADMM = 9       /* ADMM-PC element-wise steps (level 1 spectral, 2 f and
+                           multipliers, 3 zeta and z)                          */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */

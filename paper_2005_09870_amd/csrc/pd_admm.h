@@ -24,6 +24,12 @@ template <typename T>
 hipError_t launch_fft2(Cx<T> *data, int n1, int n2, int batch, const Cx<T> *tw1, const Cx<T> *tw2, int inverse,
                        hipStream_t s);
 
+// One pass of launch_fft2: rows (cols == 0, table tw1) or columns (cols != 0, table tw2, with the
+// inverse's scale).
+template <typename T>
+hipError_t launch_fft_pass(Cx<T> *data, int n1, int n2, int batch, const Cx<T> *tw, int inverse, int cols,
+                           hipStream_t s);
+
 // Element-wise steps (N pixels, m terms, plane stride N).
 template <typename T>
 struct AdmmArgs {
@@ -36,31 +42,30 @@ struct AdmmArgs {
     const T *mh;            // [N]: 1 + sum_k |u_k^|^2 / (beta1 gamma_k)
     const T *den;           // [N]: beta1 sum_k gamma_k v_k^2 + beta2
     const T *utf0;          // [m][N]: U_k^T f0
-    T *g, *xi;              // [m][N]
+    T *g, *xi;              // [m][N]; g holds a_k between the a-step and the g-step
     T *f, *z, *zeta;        // [N]
     T *tz;                  // [N]: Psi^* f
-    T *tf;                  // [N]: beta2 z + zeta, then Psi of it
-    Cx<T> *cb;              // [N] complex scratch
-    Cx<T> *th;              // [N] complex accumulator
+    T *tf;                  // [N]: beta2 z + zeta (then Psi of it, in tfs)
+    const T *tfs;           // [N]: Psi (beta2 z + zeta)
+    Cx<T> *cb;              // [m][N] complex planes of the g-step
     const T *wmap;          // per-coefficient weights or nullptr (then wlev by band)
     T wlev[PD_MAXL + 1];
-    double *slots;          // [3][PD_NSLOT] (nullptr: off): ||g - V f||_D^2, ||z - Psi^* f||^2, ||z||_{1,w}
+    double *slots;          // this iteration's [3][PD_NSLOT] (nullptr: off): ||g - V f||_D^2,
+                            // ||z - Psi^* f||^2, ||z||_{1,w}
+    double *slots_next;     // the next iteration's (row 2, written with its z), or nullptr
 };
 
-// a_k = (U_k^T f0 - xi_k + beta1 gamma_k v_k f) / (beta1 gamma_k) into g_k and into cb (imaginary 0)
-template <typename T> hipError_t launch_admm_a(const AdmmArgs<T> &a, int k, hipStream_t s);
-// th (=, k == 0; else +=) u_k^ * cb
-template <typename T> hipError_t launch_admm_acc(const AdmmArgs<T> &a, int k, hipStream_t s);
-// cb = conj(u_k^) th / mh
-template <typename T> hipError_t launch_admm_q(const AdmmArgs<T> &a, int k, hipStream_t s);
-// g_k -= Re(cb) / (beta1 gamma_k)
-template <typename T> hipError_t launch_admm_g(const AdmmArgs<T> &a, int k, hipStream_t s);
+// a_k = (U_k^T f0 - xi_k) / (beta1 gamma_k) + v_k f into g_k and cb_k (imaginary 0), all k
+template <typename T> hipError_t launch_admm_a(const AdmmArgs<T> &a, hipStream_t s);
+// per frequency: q = sum_k u_k^ cb_k / mh; cb_k = conj(u_k^) q, all k
+template <typename T> hipError_t launch_admm_accq(const AdmmArgs<T> &a, hipStream_t s);
 // z = soft(tz - zeta/beta2, w/beta2); tf = beta2 z + zeta; slots row 2 += w |z|
 template <typename T> hipError_t launch_admm_z(const AdmmArgs<T> &a, hipStream_t s);
-// f = (sum_k v_k (xi_k + beta1 gamma_k g_k) + tf) / den; xi_k += beta1 gamma_k (g_k - v_k f); slots row 0
-template <typename T> hipError_t launch_admm_f(const AdmmArgs<T> &a, hipStream_t s);
-// zeta += beta2 (z - tz); slots row 1
-template <typename T> hipError_t launch_admm_zeta(const AdmmArgs<T> &a, hipStream_t s);
+// g_k = a_k - Re(cb_k) / (beta1 gamma_k); f = (sum_k v_k (xi_k + beta1 gamma_k g_k) + tfs) / den;
+// xi_k += beta1 gamma_k (g_k - v_k f) (slots row 0); with `next`, the next a_k into g_k and cb_k
+template <typename T> hipError_t launch_admm_f(const AdmmArgs<T> &a, int next, hipStream_t s);
+// zeta += beta2 (z - tz) (slots row 1); with `next`, the next z and tf as launch_admm_z (slots_next row 2)
+template <typename T> hipError_t launch_admm_zeta(const AdmmArgs<T> &a, int next, hipStream_t s);
 
 // Set-up: u_k placed at offsets (d mod n) into cb-like planes [m][N] (complex, imaginary 0)
 template <typename T>
@@ -73,10 +78,10 @@ template <typename T> hipError_t launch_admm_gamma(const T *mx, int m, T *gam, h
 template <typename T> hipError_t launch_admm_twiddle(Cx<T> *tw, int n, hipStream_t s);
 // mh, den from gamma (device), uh, v
 template <typename T> hipError_t launch_admm_diag(const AdmmArgs<T> &a, hipStream_t s);
-// cb = conj(u_k^) * fh  (for U_k^T f0), then after an inverse FFT: utf0_k = Re(cb)
-template <typename T> hipError_t launch_admm_conjmul(const Cx<T> *uh_k, const Cx<T> *fh, Cx<T> *out, int64_t N,
-                                                     hipStream_t s);
+// out_k = conj(u_k^) * fh for all k (for U_k^T f0), then after an inverse FFT: out = Re(x)
+template <typename T> hipError_t launch_admm_conjmul(const Cx<T> *uh, const Cx<T> *fh, Cx<T> *out, int m,
+                                                     int64_t N, hipStream_t s);
 template <typename T> hipError_t launch_admm_real(const T *x, Cx<T> *out, int64_t N, hipStream_t s);
-template <typename T> hipError_t launch_admm_takere(const Cx<T> *x, T *out, int64_t N, hipStream_t s);
+template <typename T> hipError_t launch_admm_takere(const Cx<T> *x, T *out, int64_t n, hipStream_t s);
 
 }  // namespace pd

@@ -15,6 +15,11 @@ namespace pd {
 namespace {
 
 constexpr int NTF = 256;
+// line FFT tiles: points per row tile, columns per column tile, threads per workgroup
+constexpr int FFT_ROW_POINTS = 1024;
+constexpr int FFT_COL_TILE = 4;
+constexpr int FFT_THREADS = 256;
+constexpr bool FFT_TW_LDS = true;  // twiddle table staged in LDS beside the tile
 
 template <typename T>
 __device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b)
@@ -84,6 +89,193 @@ __global__ __launch_bounds__(NTF) void k_fft_cols(Cx<T> *data, int n1, int n2, i
     }
 }
 
+// ---- mixed-radix line FFT (lines of n >= 8 points) -------------------------
+// Stockham autosort with one radix-2 or radix-4 stage first (when log2 n is not
+// a multiple of 3) and radix-8 stages after it.  A thread owns "groups" of 8
+// points: group g of a line holds positions g + t n/8 (t < 8), which are the
+// inputs of one radix-8 butterfly, two radix-4 or four radix-2 ones.  The first
+// stage reads the line from global memory and the last one writes it back
+// (both at positions g + t n/8, so a line's loads and stores are contiguous);
+// the stages in between exchange through one LDS tile, in place (all reads of
+// a stage, barrier, all writes, barrier).  The inverse conjugates on load and
+// store.
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cadd(Cx<T> a, Cx<T> b) { return Cx<T>{a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> csub(Cx<T> a, Cx<T> b) { return Cx<T>{a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) { return Cx<T>{a.im, -a.re}; }  // a * (-i)
+
+// X[q] = sum_r v[r] exp(-2 pi i r q / R), in place, natural order
+template <typename T>
+__device__ __forceinline__ void dft2(Cx<T> &a, Cx<T> &b)
+{
+    const Cx<T> t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(Cx<T> &v0, Cx<T> &v1, Cx<T> &v2, Cx<T> &v3)
+{
+    const Cx<T> t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_mi(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, t3);
+    v3 = csub(t1, t3);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(Cx<T> *v)
+{
+    Cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    Cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    const T c = T(0.70710678118654752440);
+    const Cx<T> w1{c * (o1.re + o1.im), c * (o1.im - o1.re)};    // o1 exp(-i pi/4)
+    const Cx<T> w2 = mul_mi(o2);                                  // o2 exp(-i pi/2)
+    const Cx<T> w3{c * (o3.im - o3.re), -c * (o3.re + o3.im)};   // o3 exp(-3 i pi/4)
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, w1);
+    v[5] = csub(e1, w1);
+    v[2] = cadd(e2, w2);
+    v[6] = csub(e2, w2);
+    v[3] = cadd(e3, w3);
+    v[7] = csub(e3, w3);
+}
+
+// exp(-2 pi i t / n) for t < n from the half table tw[t], t < n/2
+template <typename T>
+__device__ __forceinline__ Cx<T> twiddle(const Cx<T> *__restrict__ tw, int t, int half)
+{
+    if (t < half) return tw[t];
+    const Cx<T> w = tw[t - half];
+    return Cx<T>{-w.re, -w.im};
+}
+
+// One stage (radix R, Ns = product of the earlier radices) on the 8 points of
+// group g: butterflies j = g + q n/8 (q < 8/R) with inputs v[q + r 8/R].
+// Writes the outputs' positions into pos[] (same slots).
+template <typename T, int R>
+__device__ __forceinline__ void stage_group(Cx<T> *v, int *pos, int g, int n, int Ns,
+                                            const Cx<T> *__restrict__ tw)
+{
+    constexpr int Q = 8 / R;
+    const int n8 = n >> 3, stride = n / (Ns * R);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = g + q * n8;
+        const int k = j & (Ns - 1);
+        Cx<T> u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u[r] = v[q + r * Q];
+            if (Ns > 1 && r > 0) u[r] = cmul(u[r], twiddle(tw, r * k * stride, n >> 1));
+        }
+        if constexpr (R == 8) {
+            dft8(u);
+        } else if constexpr (R == 4) {
+            dft4(u[0], u[1], u[2], u[3]);
+        } else {
+            dft2(u[0], u[1]);
+        }
+        const int base = (j - k) * R + k;  // (j / Ns) Ns R + k
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[q + r * Q] = u[r];
+            pos[q + r * Q] = base + r * Ns;
+        }
+    }
+}
+
+// C lines of n points per workgroup, BG groups per thread; grid (lines / C, batch).
+// ROWS: line l is row (blockIdx.x C + l), points contiguous; else line l is
+// column (blockIdx.x C + l), points n1 apart.  first: radix of the first stage.
+template <typename T, bool ROWS, int BG>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(Cx<T> *data, int n, int n1, int64_t plane, int C,
+                                                  const Cx<T> *__restrict__ tw, int first, int nst,
+                                                  int inverse, T scale)
+{
+    extern __shared__ unsigned char lds_raw[];
+    Cx<T> *S = reinterpret_cast<Cx<T> *>(lds_raw);
+    const int n8 = n >> 3, nthr = blockDim.x;
+    Cx<T> *base = data + (int64_t)blockIdx.y * plane;
+    const Cx<T> *twp = tw;
+    if (FFT_TW_LDS && nst > 1) {  // read first in stage 1, after its barrier
+        Cx<T> *TW = S + C * n;
+        for (int i = threadIdx.x; i < (n >> 1); i += nthr) TW[i] = tw[i];
+        twp = TW;
+    }
+    const int line0 = blockIdx.x * C;
+    Cx<T> v[BG][8];
+    int pos[BG][8];
+    int gl[BG], gg[BG];
+    // load (positions g + t n/8)
+#pragma unroll
+    for (int b = 0; b < BG; ++b) {
+        const int grp = threadIdx.x + b * nthr;
+        gl[b] = ROWS ? grp / n8 : grp % C;
+        gg[b] = ROWS ? grp % n8 : grp / C;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = gg[b] + t * n8;
+            const int64_t off = ROWS ? (int64_t)(line0 + gl[b]) * n1 + e : (int64_t)e * n1 + line0 + gl[b];
+            Cx<T> x = base[off];
+            if (inverse) x.im = -x.im;
+            v[b][t] = x;
+        }
+    }
+    int Ns = 1;
+    for (int s = 0; s < nst; ++s) {
+        const int R = s == 0 ? first : 8;
+        if (s > 0) {
+            // gather this stage's inputs from the tile
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int e = gg[b] + t * n8;
+                    v[b][t] = S[ROWS ? gl[b] * n + e : e * C + gl[b]];
+                }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int b = 0; b < BG; ++b) {
+            if (R == 8)
+                stage_group<T, 8>(v[b], pos[b], gg[b], n, Ns, twp);
+            else if (R == 4)
+                stage_group<T, 4>(v[b], pos[b], gg[b], n, Ns, twp);
+            else
+                stage_group<T, 2>(v[b], pos[b], gg[b], n, Ns, twp);
+        }
+        Ns *= R;
+        if (s + 1 < nst) {
+#pragma unroll
+            for (int b = 0; b < BG; ++b)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int e = pos[b][t];
+                    S[ROWS ? gl[b] * n + e : e * C + gl[b]] = v[b][t];
+                }
+        }
+    }
+    // the last stage (radix 8) leaves point g + t n/8 in slot t: store
+#pragma unroll
+    for (int b = 0; b < BG; ++b)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = gg[b] + t * n8;
+            const int64_t off = ROWS ? (int64_t)(line0 + gl[b]) * n1 + e : (int64_t)e * n1 + line0 + gl[b];
+            Cx<T> x = v[b][t];
+            if (inverse) x.im = -x.im;
+            base[off] = Cx<T>{x.re * scale, x.im * scale};
+        }
+}
+
 inline int ilog2(int n)
 {
     int l = 0;
@@ -100,74 +292,84 @@ __device__ __forceinline__ int band_of(int i1, int i2, int n1, int n2, int L)
     return t == L ? 0 : L - t;
 }
 
-template <int NV>
-__device__ void slots_add(double (&v)[NV], double *slots)
+// two partial sums to two slot rows (either may be nullptr) with one LDS round
+__device__ void slots_add2(double v0, double *s0, double v1, double *s1)
 {
-    __shared__ double red[NV][NTF / 64];
+    __shared__ double red[2][NTF / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double a = v[q];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m);
-        if (lane == 0) red[q][wv] = a;
+    for (int m = 32; m >= 1; m >>= 1) {
+        v0 += __shfl_xor(v0, m);
+        v1 += __shfl_xor(v1, m);
+    }
+    if (lane == 0) {
+        red[0][wv] = v0;
+        red[1][wv] = v1;
     }
     __syncthreads();
-    if (threadIdx.x < NV) {
-        double a = 0.0;
+    if (threadIdx.x < 2) {
+        double *dst = threadIdx.x == 0 ? s0 : s1;
+        if (dst) {
+            double a = 0.0;
 #pragma unroll
-        for (int w = 0; w < NTF / 64; ++w) a += red[threadIdx.x][w];
-        atomicAdd(slots + threadIdx.x * PD_NSLOT + (blockIdx.x % PD_NSLOT), a);
+            for (int w = 0; w < NTF / 64; ++w) a += red[threadIdx.x][w];
+            atomicAdd(dst + (blockIdx.x % PD_NSLOT), a);
+        }
     }
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + NTF - 1) / NTF); }
 
 template <typename T>
-__global__ void k_admm_a(AdmmArgs<T> a, int k)
+__device__ __forceinline__ T pixel_weight(const AdmmArgs<T> &a, const T *sw, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
-    if (i >= a.N) return;
-    const T bg = a.beta1 * a.gam[k];
-    const int64_t o = (int64_t)k * a.N + i;
-    const T ak = (a.utf0[o] - a.xi[o] + bg * a.v[o] * a.f[i]) / bg;
-    a.g[o] = ak;
-    a.cb[i] = Cx<T>{ak, T(0)};
+    if (a.wmap) return a.wmap[i];
+    const int i2 = (int)(i / a.n1), i1 = (int)(i - (int64_t)i2 * a.n1);
+    return sw[band_of(i1, i2, a.n1, a.n2, a.levels)];
 }
 
 template <typename T>
-__global__ void k_admm_acc(AdmmArgs<T> a, int k)
+__device__ __forceinline__ T soft_thr(T v, T t)
+{
+    const T m = fabs(v) - t;
+    return m > T(0) ? copysign(m, v) : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTF) void k_admm_a(AdmmArgs<T> a)
 {
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
     if (i >= a.N) return;
-    const Cx<T> p = cmul(a.uh[(int64_t)k * a.N + i], a.cb[i]);
-    if (k == 0) {
-        a.th[i] = p;
-    } else {
-        const Cx<T> t = a.th[i];
-        a.th[i] = Cx<T>{t.re + p.re, t.im + p.im};
+    const T f = a.f[i];
+    for (int k = 0; k < a.m; ++k) {
+        const int64_t o = (int64_t)k * a.N + i;
+        const T ak = (a.utf0[o] - a.xi[o]) / (a.beta1 * a.gam[k]) + a.v[o] * f;
+        a.g[o] = ak;
+        a.cb[o] = Cx<T>{ak, T(0)};
     }
 }
 
 template <typename T>
-__global__ void k_admm_q(AdmmArgs<T> a, int k)
+__global__ __launch_bounds__(NTF) void k_admm_accq(AdmmArgs<T> a)
 {
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
     if (i >= a.N) return;
-    Cx<T> u = a.uh[(int64_t)k * a.N + i];
-    u.im = -u.im;
+    Cx<T> t{T(0), T(0)};
+    for (int k = 0; k < a.m; ++k) {
+        const int64_t o = (int64_t)k * a.N + i;
+        const Cx<T> p = cmul(a.uh[o], a.cb[o]);
+        t.re += p.re;
+        t.im += p.im;
+    }
     const T im = T(1) / a.mh[i];
-    const Cx<T> t = a.th[i];
-    a.cb[i] = cmul(u, Cx<T>{t.re * im, t.im * im});
-}
-
-template <typename T>
-__global__ void k_admm_g(AdmmArgs<T> a, int k)
-{
-    const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
-    if (i >= a.N) return;
-    const int64_t o = (int64_t)k * a.N + i;
-    a.g[o] -= a.cb[i].re / (a.beta1 * a.gam[k]);
+    t.re *= im;
+    t.im *= im;
+    for (int k = 0; k < a.m; ++k) {
+        const int64_t o = (int64_t)k * a.N + i;
+        Cx<T> u = a.uh[o];
+        u.im = -u.im;
+        a.cb[o] = cmul(u, t);
+    }
 }
 
 template <typename T>
@@ -177,60 +379,77 @@ __global__ __launch_bounds__(NTF) void k_admm_z(AdmmArgs<T> a)
     if (!a.wmap && threadIdx.x <= a.levels) sw[threadIdx.x] = a.wlev[threadIdx.x];
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
-    double st[1] = {0.0};
+    double st = 0.0;
     if (i < a.N) {
-        T w;
-        if (a.wmap) {
-            w = a.wmap[i];
-        } else {
-            const int i2 = (int)(i / a.n1), i1 = (int)(i - (int64_t)i2 * a.n1);
-            w = sw[band_of(i1, i2, a.n1, a.n2, a.levels)];
-        }
-        const T v = a.tz[i] - a.zeta[i] / a.beta2;
-        const T t = w / a.beta2;
-        const T m = fabs(v) - t;
-        const T z = m > T(0) ? copysign(m, v) : T(0);
+        const T w = pixel_weight(a, sw, i);
+        const T zt = a.zeta[i];
+        const T z = soft_thr(a.tz[i] - zt / a.beta2, w / a.beta2);
         a.z[i] = z;
-        a.tf[i] = a.beta2 * z + a.zeta[i];
-        st[0] = (double)w * fabs((double)z);
+        a.tf[i] = a.beta2 * z + zt;
+        st = (double)w * fabs((double)z);
     }
-    if (a.slots) slots_add<1>(st, a.slots + 2 * PD_NSLOT);
+    if (a.slots) slots_add2(st, a.slots + 2 * PD_NSLOT, 0.0, nullptr);
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTF) void k_admm_f(AdmmArgs<T> a)
+__global__ __launch_bounds__(NTF) void k_admm_f(AdmmArgs<T> a, int next)
 {
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
-    double st[1] = {0.0};
+    double st = 0.0;
     if (i < a.N) {
-        T acc = a.tf[i];
+        // g-step completion and f-step
+        T acc = a.tfs[i];
         for (int k = 0; k < a.m; ++k) {
             const int64_t o = (int64_t)k * a.N + i;
-            acc += a.v[o] * (a.xi[o] + a.beta1 * a.gam[k] * a.g[o]);
+            const T bg = a.beta1 * a.gam[k];
+            const T gk = a.g[o] - a.cb[o].re / bg;
+            acc += a.v[o] * (a.xi[o] + bg * gk);
         }
         const T f = acc / a.den[i];
         a.f[i] = f;
+        // multiplier step, then the next iteration's a_k
         for (int k = 0; k < a.m; ++k) {
             const int64_t o = (int64_t)k * a.N + i;
-            const T r = a.g[o] - a.v[o] * f;
-            a.xi[o] += a.beta1 * a.gam[k] * r;
-            st[0] += (double)a.gam[k] * (double)r * (double)r;
+            const T bg = a.beta1 * a.gam[k];
+            const T vk = a.v[o];
+            const T r = a.g[o] - a.cb[o].re / bg - vk * f;
+            const T xk = a.xi[o] + bg * r;
+            a.xi[o] = xk;
+            st += (double)a.gam[k] * (double)r * (double)r;
+            if (next) {
+                const T ak = (a.utf0[o] - xk) / bg + vk * f;
+                a.g[o] = ak;
+                a.cb[o] = Cx<T>{ak, T(0)};
+            }
         }
     }
-    if (a.slots) slots_add<1>(st, a.slots);
+    if (a.slots) slots_add2(st, a.slots, 0.0, nullptr);
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTF) void k_admm_zeta(AdmmArgs<T> a)
+__global__ __launch_bounds__(NTF) void k_admm_zeta(AdmmArgs<T> a, int next)
 {
+    __shared__ T sw[PD_MAXL + 1];
+    if (next && !a.wmap && threadIdx.x <= a.levels) sw[threadIdx.x] = a.wlev[threadIdx.x];
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
-    double st[1] = {0.0};
+    double st = 0.0, st2 = 0.0;
     if (i < a.N) {
-        const T r = a.z[i] - a.tz[i];
-        a.zeta[i] += a.beta2 * r;
-        st[0] = (double)r * (double)r;
+        const T tz = a.tz[i];
+        const T r = a.z[i] - tz;
+        const T zt = a.zeta[i] + a.beta2 * r;
+        a.zeta[i] = zt;
+        st = (double)r * (double)r;
+        if (next) {
+            const T w = pixel_weight(a, sw, i);
+            const T z = soft_thr(tz - zt / a.beta2, w / a.beta2);
+            a.z[i] = z;
+            a.tf[i] = a.beta2 * z + zt;
+            st2 = (double)w * fabs((double)z);
+        }
     }
-    if (a.slots) slots_add<1>(st, a.slots + PD_NSLOT);
+    if (a.slots)
+        slots_add2(st, a.slots + PD_NSLOT, st2, (next && a.slots_next) ? a.slots_next + 2 * PD_NSLOT : nullptr);
 }
 
 template <typename T>
@@ -311,13 +530,16 @@ __global__ void k_admm_diag(AdmmArgs<T> a)
 }
 
 template <typename T>
-__global__ void k_admm_conjmul(const Cx<T> *uh_k, const Cx<T> *fh, Cx<T> *out, int64_t N)
+__global__ void k_admm_conjmul(const Cx<T> *uh, const Cx<T> *fh, Cx<T> *out, int m, int64_t N)
 {
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
     if (i >= N) return;
-    Cx<T> u = uh_k[i];
-    u.im = -u.im;
-    out[i] = cmul(u, fh[i]);
+    const Cx<T> x = fh[i];
+    for (int k = 0; k < m; ++k) {
+        Cx<T> u = uh[(int64_t)k * N + i];
+        u.im = -u.im;
+        out[(int64_t)k * N + i] = cmul(u, x);
+    }
 }
 
 template <typename T>
@@ -336,47 +558,87 @@ __global__ void k_admm_takere(const Cx<T> *x, T *out, int64_t N)
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_fft2(Cx<T> *data, int n1, int n2, int batch, const Cx<T> *tw1, const Cx<T> *tw2, int inverse,
-                       hipStream_t s)
+template <typename T, bool ROWS>
+hipError_t launch_lines(Cx<T> *data, int n, int n1, int64_t plane, int lines, int C, int batch, const Cx<T> *tw,
+                        int inverse, T scale, hipStream_t s)
 {
-    const int l1 = ilog2(n1), l2 = ilog2(n2);
-    hipLaunchKernelGGL(k_fft_rows<T>, dim3(n2 * batch), dim3(NTF), 2 * n1 * sizeof(Cx<T>), s, data, n1, l1, tw1,
-                       inverse);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // columns per workgroup: both LDS buffers within 64 KiB
-    int cb = (int)(65536 / (2 * n2 * sizeof(Cx<T>)));
-    cb = cb < 1 ? 1 : (cb > n1 ? n1 : cb);
-    while (n1 % cb) --cb;
-    const T scale = inverse ? T(1) / ((T)n1 * (T)n2) : T(1);
-    hipLaunchKernelGGL(k_fft_cols<T>, dim3(n1 / cb, batch), dim3(NTF), 2 * cb * n2 * sizeof(Cx<T>), s, data, n1, n2,
-                       l2, cb, tw2, inverse, scale);
+    const int l = ilog2(n), rem = l % 3;
+    const int first = rem == 1 ? 2 : (rem == 2 ? 4 : 8);
+    const int nst = l / 3 + (rem ? 1 : 0);
+    const int groups = C * (n >> 3);
+    const int nthr = groups < FFT_THREADS ? groups : FFT_THREADS;
+    const int bg = groups / nthr;
+    // the kernel's indexing assumes C | lines, whole groups per thread and at most 4 of them
+    if (C < 1 || lines % C || groups % nthr || (bg != 1 && bg != 2 && bg != 4)) return hipErrorInvalidValue;
+    const size_t lds = nst > 1 ? ((size_t)C * n + (FFT_TW_LDS ? n / 2 : 0)) * sizeof(Cx<T>) : 0;
+    const dim3 grid(lines / C, batch);
+    if (bg == 1)
+        hipLaunchKernelGGL((k_fft_lines<T, ROWS, 1>), grid, dim3(nthr), lds, s, data, n, n1, plane, C, tw, first, nst,
+                           inverse, scale);
+    else if (bg == 2)
+        hipLaunchKernelGGL((k_fft_lines<T, ROWS, 2>), grid, dim3(nthr), lds, s, data, n, n1, plane, C, tw, first, nst,
+                           inverse, scale);
+    else
+        hipLaunchKernelGGL((k_fft_lines<T, ROWS, 4>), grid, dim3(nthr), lds, s, data, n, n1, plane, C, tw, first, nst,
+                           inverse, scale);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_admm_a(const AdmmArgs<T> &a, int k, hipStream_t s)
+hipError_t launch_fft_pass(Cx<T> *data, int n1, int n2, int batch, const Cx<T> *tw, int inverse, int cols,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_a<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, k);
+    const T scale = (cols && inverse) ? T(1) / ((T)n1 * (T)n2) : T(1);
+    const int64_t plane = (int64_t)n1 * n2;
+    const int n = cols ? n2 : n1;
+    const int lines = cols ? n1 : n2;
+    if (n >= 8) {
+        // tiles within 64 KiB of LDS and at most 4 groups of 8 points per thread; columns: at
+        // most FFT_COL_TILE per tile so that a wide image still gives many workgroups
+        const int cap = (int)(65536 / sizeof(Cx<T>)) - (FFT_TW_LDS ? n / 2 : 0);
+        int C = (cols ? 32 * FFT_THREADS : FFT_ROW_POINTS) / n;
+        if (C * n > cap) C = cap / n;
+        if (C * n > 32 * FFT_THREADS) C = 32 * FFT_THREADS / n;
+        if (cols && C > FFT_COL_TILE) C = FFT_COL_TILE;
+        if (C > lines) C = lines;
+        if (C < 1) C = 1;
+        while (C & (C - 1)) C &= C - 1;  // a power of two (the LDS cap need not be one)
+        if (cols) return launch_lines<T, false>(data, n, n1, plane, lines, C, batch, tw, inverse, scale, s);
+        return launch_lines<T, true>(data, n, n1, plane, lines, C, batch, tw, inverse, scale, s);
+    }
+    if (!cols) {
+        hipLaunchKernelGGL(k_fft_rows<T>, dim3(n2 * batch), dim3(NTF), 2 * n1 * sizeof(Cx<T>), s, data, n1,
+                           ilog2(n1), tw, inverse);
+        return hipGetLastError();
+    }
+    // short columns: cb columns per workgroup, both LDS buffers within 64 KiB
+    int cb = (int)(65536 / (2 * n2 * sizeof(Cx<T>)));
+    cb = cb < 1 ? 1 : (cb > n1 ? n1 : cb);
+    while (n1 % cb) --cb;
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3(n1 / cb, batch), dim3(NTF), 2 * cb * n2 * sizeof(Cx<T>), s, data, n1,
+                       n2, ilog2(n2), cb, tw, inverse, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft2(Cx<T> *data, int n1, int n2, int batch, const Cx<T> *tw1, const Cx<T> *tw2, int inverse,
+                       hipStream_t s)
+{
+    hipError_t e = launch_fft_pass<T>(data, n1, n2, batch, tw1, inverse, 0, s);
+    if (e != hipSuccess) return e;
+    return launch_fft_pass<T>(data, n1, n2, batch, tw2, inverse, 1, s);
+}
+
+template <typename T>
+hipError_t launch_admm_a(const AdmmArgs<T> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_admm_a<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_admm_acc(const AdmmArgs<T> &a, int k, hipStream_t s)
+hipError_t launch_admm_accq(const AdmmArgs<T> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_acc<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, k);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_admm_q(const AdmmArgs<T> &a, int k, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_admm_q<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, k);
-    return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_admm_g(const AdmmArgs<T> &a, int k, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_admm_g<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, k);
+    hipLaunchKernelGGL(k_admm_accq<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a);
     return hipGetLastError();
 }
 template <typename T>
@@ -386,15 +648,15 @@ hipError_t launch_admm_z(const AdmmArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_admm_f(const AdmmArgs<T> &a, hipStream_t s)
+hipError_t launch_admm_f(const AdmmArgs<T> &a, int next, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_f<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a);
+    hipLaunchKernelGGL(k_admm_f<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, next);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_admm_zeta(const AdmmArgs<T> &a, hipStream_t s)
+hipError_t launch_admm_zeta(const AdmmArgs<T> &a, int next, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_zeta<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a);
+    hipLaunchKernelGGL(k_admm_zeta<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, next);
     return hipGetLastError();
 }
 template <typename T>
@@ -428,9 +690,9 @@ hipError_t launch_admm_diag(const AdmmArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_admm_conjmul(const Cx<T> *uh_k, const Cx<T> *fh, Cx<T> *out, int64_t N, hipStream_t s)
+hipError_t launch_admm_conjmul(const Cx<T> *uh, const Cx<T> *fh, Cx<T> *out, int m, int64_t N, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_conjmul<T>, dim3(nblk(N)), dim3(NTF), 0, s, uh_k, fh, out, N);
+    hipLaunchKernelGGL(k_admm_conjmul<T>, dim3(nblk(N)), dim3(NTF), 0, s, uh, fh, out, m, N);
     return hipGetLastError();
 }
 template <typename T>
@@ -448,19 +710,18 @@ hipError_t launch_admm_takere(const Cx<T> *x, T *out, int64_t N, hipStream_t s)
 
 #define PD_ADMM_INST(T)                                                                                       \
     template hipError_t launch_fft2<T>(Cx<T> *, int, int, int, const Cx<T> *, const Cx<T> *, int, hipStream_t); \
-    template hipError_t launch_admm_a<T>(const AdmmArgs<T> &, int, hipStream_t);                              \
-    template hipError_t launch_admm_acc<T>(const AdmmArgs<T> &, int, hipStream_t);                            \
-    template hipError_t launch_admm_q<T>(const AdmmArgs<T> &, int, hipStream_t);                              \
-    template hipError_t launch_admm_g<T>(const AdmmArgs<T> &, int, hipStream_t);                              \
+    template hipError_t launch_fft_pass<T>(Cx<T> *, int, int, int, const Cx<T> *, int, int, hipStream_t);     \
+    template hipError_t launch_admm_a<T>(const AdmmArgs<T> &, hipStream_t);                                   \
+    template hipError_t launch_admm_accq<T>(const AdmmArgs<T> &, hipStream_t);                                \
     template hipError_t launch_admm_z<T>(const AdmmArgs<T> &, hipStream_t);                                   \
-    template hipError_t launch_admm_f<T>(const AdmmArgs<T> &, hipStream_t);                                   \
-    template hipError_t launch_admm_zeta<T>(const AdmmArgs<T> &, hipStream_t);                                \
+    template hipError_t launch_admm_f<T>(const AdmmArgs<T> &, int, hipStream_t);                              \
+    template hipError_t launch_admm_zeta<T>(const AdmmArgs<T> &, int, hipStream_t);                           \
     template hipError_t launch_admm_padk<T>(const T *, int, int, int, int, Cx<T> *, hipStream_t);             \
     template hipError_t launch_admm_absmax<T>(const Cx<T> *, int, int64_t, T *, hipStream_t);                 \
     template hipError_t launch_admm_gamma<T>(const T *, int, T *, hipStream_t);                               \
     template hipError_t launch_admm_twiddle<T>(Cx<T> *, int, hipStream_t);                                    \
     template hipError_t launch_admm_diag<T>(const AdmmArgs<T> &, hipStream_t);                                \
-    template hipError_t launch_admm_conjmul<T>(const Cx<T> *, const Cx<T> *, Cx<T> *, int64_t, hipStream_t);  \
+    template hipError_t launch_admm_conjmul<T>(const Cx<T> *, const Cx<T> *, Cx<T> *, int, int64_t, hipStream_t); \
     template hipError_t launch_admm_real<T>(const T *, Cx<T> *, int64_t, hipStream_t);                        \
     template hipError_t launch_admm_takere<T>(const Cx<T> *, T *, int64_t, hipStream_t);
 PD_ADMM_INST(float)

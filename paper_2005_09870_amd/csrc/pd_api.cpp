@@ -1457,7 +1457,7 @@ AdmmLayout admm_layout(const pd_shape *sh, size_t es, int m)
     l.tfz = take(N * es);
     l.tfs = take(N * es);
     l.uh = take((size_t)m * N * 2 * es);
-    l.cb = take(N * 2 * es);
+    l.cb = take((size_t)m * N * 2 * es);
     l.th = take(N * 2 * es);
     l.tw1 = take((size_t)sh->n1 * es);   // n1/2 complex
     l.tw2 = take((size_t)sh->n2 * es);
@@ -1499,10 +1499,12 @@ int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, 
     a.zeta = (T *)(ws + L.zeta);
     a.tz = (T *)(ws + L.tz);
     a.cb = (Cx<T> *)(ws + L.cb);
-    a.th = (Cx<T> *)(ws + L.th);
+    a.tf = (T *)(ws + L.tfz);
+    a.tfs = (const T *)(ws + L.tfs);
     a.wmap = (const T *)w->coeff_w;
     for (int k = 0; k <= PD_MAXL; ++k) a.wlev[k] = (w->level_w && k <= sh->levels) ? (T)w->level_w[k] : T(0);
     T *tfz = (T *)(ws + L.tfz), *tfs = (T *)(ws + L.tfs);
+    Cx<T> *th = (Cx<T> *)(ws + L.th);
     Cx<T> *tw1 = (Cx<T> *)(ws + L.tw1), *tw2 = (Cx<T> *)(ws + L.tw2);
     Cx<T> *uh = (Cx<T> *)(ws + L.uh);
 
@@ -1520,46 +1522,54 @@ int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, 
         const T *f0c = f0 + ch * N;
         a.f = f_out + ch * N;
         a.z = z_out + ch * N;
-        // U_k^T f0 through the spectra
-        PD_TRY_HIP(launch_admm_real<T>(f0c, a.cb, N, st));
-        PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, 1, tw1, tw2, 0, st));
-        for (int k = 0; k < m; ++k) {
-            PD_TRY_HIP(launch_admm_conjmul<T>(uh + k * N, a.cb, a.th, N, st));
-            PD_TRY_HIP(launch_fft2<T>(a.th, n1, n2, 1, tw1, tw2, 1, st));
-            PD_TRY_HIP(launch_admm_takere<T>(a.th, (T *)a.utf0 + k * N, N, st));
-        }
-        // start: f = f0, z = Psi^* f, xi = zeta = 0
+        // U_k^T f0 through the spectra (all k at once)
+        PD_TRY_HIP(launch_admm_real<T>(f0c, th, N, st));
+        PD_TRY_HIP(launch_fft2<T>(th, n1, n2, 1, tw1, tw2, 0, st));
+        PD_TRY_HIP(launch_admm_conjmul<T>(uh, th, a.cb, m, N, st));
+        PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, m, tw1, tw2, 1, st));
+        PD_TRY_HIP(launch_admm_takere<T>(a.cb, (T *)a.utf0, (int64_t)m * N, st));
+        // start: f = f0, z = Psi^* f, xi = zeta = 0; first a_k and z
         PD_TRY_HIP(launch_copy<T>(f0c, a.f, N, st));
         int rc;
         if ((rc = analysis_plain<T>(c, a.f, a.tz)) != PD_OK) return rc;
-        PD_TRY_HIP(launch_copy<T>(a.tz, a.z, N, st));
         PD_TRY_HIP(launch_fill<T>(a.zeta, T(0), N, st));
         PD_TRY_HIP(launch_fill<T>(a.xi, T(0), (int64_t)m * N, st));
-        if (stats && iters > 0) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
+        if (iters == 0) {
+            PD_TRY_HIP(launch_copy<T>(a.tz, a.z, N, st));
+            continue;
+        }
+        if (stats) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
+        a.slots = stats ? c.slots(0) : nullptr;
+        PD_TRY_HIP(launch_admm_a<T>(a, st));
+        PD_TRY_HIP(launch_admm_z<T>(a, st));
+        int b0 = 0;
+        // timed launches: FFT passes keyed 0/1 (forward rows/columns), 2/3 (inverse); element-wise
+        // steps 1 (spectral), 2 (f and multipliers), 3 (zeta and z)
+        auto fft = [&](int inverse) -> int {
+            for (int cols = 0; cols < 2; ++cols)
+                PD_TRY_HIP(timed(PD_K_FFT, 2 * inverse + cols, st, [&] {
+                    return launch_fft_pass<T>(a.cb, n1, n2, m, cols ? tw2 : tw1, inverse, cols, st);
+                }));
+            return PD_OK;
+        };
         for (int it = 0; it < iters; ++it) {
+            const int next = it + 1 < iters;
             a.slots = stats ? c.slots(it) : nullptr;
-            // g: Woodbury with the Fourier-diagonal middle matrix
-            for (int k = 0; k < m; ++k) {
-                PD_TRY_HIP(launch_admm_a<T>(a, k, st));
-                PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, 1, tw1, tw2, 0, st));
-                PD_TRY_HIP(launch_admm_acc<T>(a, k, st));
-            }
-            for (int k = 0; k < m; ++k) {
-                PD_TRY_HIP(launch_admm_q<T>(a, k, st));
-                PD_TRY_HIP(launch_fft2<T>(a.cb, n1, n2, 1, tw1, tw2, 1, st));
-                PD_TRY_HIP(launch_admm_g<T>(a, k, st));
-            }
-            // z (from Psi^* f of the previous step), then f, then the multipliers
-            a.tf = tfz;
-            PD_TRY_HIP(launch_admm_z<T>(a, st));
+            a.slots_next = (stats && next) ? c.slots(it + 1) : nullptr;
+            // g: Woodbury with the Fourier-diagonal middle matrix (a_k already in g and cb)
+            if ((rc = fft(0)) != PD_OK) return rc;
+            PD_TRY_HIP(timed(PD_K_ADMM, 1, st, [&] { return launch_admm_accq<T>(a, st); }));
+            if ((rc = fft(1)) != PD_OK) return rc;
+            // f (the z of this iteration was formed with the previous multiplier step), multipliers
             if ((rc = synth_chain<T>(c, tfz, tfz, T(0), tfs)) != PD_OK) return rc;
-            a.tf = tfs;
-            PD_TRY_HIP(launch_admm_f<T>(a, st));
+            PD_TRY_HIP(timed(PD_K_ADMM, 2, st, [&] { return launch_admm_f<T>(a, next, st); }));
             if ((rc = analysis_plain<T>(c, a.f, a.tz)) != PD_OK) return rc;
-            PD_TRY_HIP(launch_admm_zeta<T>(a, st));
-            if (stats && ((it + 1) % PD_RING == 0 || it == iters - 1)) {
-                const int cnt = (it % PD_RING) + 1;
-                PD_TRY_HIP(launch_stats_finalize(c.ring(), stats, it + 1 - cnt, cnt, st));
+            PD_TRY_HIP(timed(PD_K_ADMM, 3, st, [&] { return launch_admm_zeta<T>(a, next, st); }));
+            // batches of at most PD_RING - 1 entries, so that the entry of iteration it + 1 (whose
+            // penalty term is already in the ring) is never finalised with an older one
+            if (stats && (it + 1 - b0 == PD_RING - 1 || it == iters - 1)) {
+                PD_TRY_HIP(launch_stats_finalize(c.ring(), stats, b0, it + 1 - b0, st));
+                b0 = it + 1;
             }
         }
     }

@@ -45,8 +45,8 @@ def _pc(n1, n2, m):
     return u, PC.rows_to_pixels(v, n1)
 
 
-@pytest.mark.parametrize("n2,n1,batch", [(2, 2, 1), (8, 4, 3), (64, 32, 2), (128, 256, 1), (16, 4096, 1),
-                                         (4096, 16, 1)])
+@pytest.mark.parametrize("n2,n1,batch", [(2, 2, 1), (8, 4, 3), (4, 8, 2), (16, 8, 1), (64, 32, 2), (128, 256, 1),
+                                         (512, 512, 5), (2048, 1024, 1), (16, 4096, 1), (4096, 16, 1)])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 2e-6)])
 def test_fft2_matches_numpy(n2, n1, batch, dtype, tol):
     if dtype == torch.complex128 and max(n1, n2) > 2048:
@@ -115,6 +115,22 @@ def test_admm_coefficient_weights_and_zero_iterations():
     z0 = P.pd_admm_solve(_t(f0, torch.float64), op, H6, L, 0.7, 0, level_w=c.level_w)
     assert np.array_equal(_np(z0["f"]), f0)
     assert np.abs(_np(z0["z"])[0] - O.fwt(f0[0], L, H6)).max() < 1e-12
+
+
+def test_admm_long_run_statistics():
+    """150 iterations (past the statistics ring's batches) in FP64: every
+    statistics row and the final iterates match the oracle."""
+    n1, n2 = 16, 32
+    u, v, c, f0 = _case(n1, n2, 1, 3, 3, 81)
+    L = c.levels
+    w = O.expand_level_weights(c.level_w, n1, n2, L)[0]
+    op = P.Operator.pc(u, v, dtype=torch.float64)
+    K = 150
+    out = P.pd_admm_solve(_t(f0, torch.float64), op, H6, L, 0.5, K, level_w=c.level_w, stats=True)
+    ref = AD.admm_pc(u, v, H6, L, f0[0], w, 0.5, K, log=True)
+    assert np.abs(_np(out["f"])[0] - ref["f"]).max() < 1e-9
+    np.testing.assert_allclose(out["stats"].cpu().numpy(), ref["log"], rtol=1e-7,
+                               atol=1e-12 * np.abs(ref["log"]).max())
 
 
 def test_admm_kernel_wider_than_image():
