@@ -534,7 +534,9 @@ def admm_case(torch, P, SI, h, iters, n=512, m=5, beta=1.0):
             "roofline": {"bound": "hbm", "achieved": None if ach is None else round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": None if ach is None else round(ach / HBM_PEAK_GBS, 4),
-                         "traffic": None, "kernel": dom, "avg_us": None if us is None else round(us, 3),
+                         "traffic": None if dom is None else profiled_traffic(dom, "admm_pc512_traffic.md",
+                                                                              ("pd_admm.hip", "pd_admm.h")),
+                         "kernel": dom, "avg_us": None if us is None else round(us, 3),
                          "alg_bytes_per_launch": None if dom is None else alg[dom]}}
 
 

@@ -203,13 +203,18 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(Cx<T> *data, int n, i
     Cx<T> *S = reinterpret_cast<Cx<T> *>(lds_raw);
     const int n8 = n >> 3, nthr = blockDim.x;
     Cx<T> *base = data + (int64_t)blockIdx.y * plane;
+    // column tiles in XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
+    // workgroup b takes tile (b % 8) * per + b / 8 and the tiles that share cache lines (4
+    // columns of 8 bytes each per 128-byte line) run on one XCD, from its L2
+    int bx = blockIdx.x;
+    if (!ROWS && (gridDim.x & 7) == 0) bx = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int line0 = bx * C;
     const Cx<T> *twp = tw;
     if (FFT_TW_LDS && nst > 1) {  // read first in stage 1, after its barrier
         Cx<T> *TW = S + C * n;
         for (int i = threadIdx.x; i < (n >> 1); i += nthr) TW[i] = tw[i];
         twp = TW;
     }
-    const int line0 = blockIdx.x * C;
     Cx<T> v[BG][8];
     int pos[BG][8];
     int gl[BG], gg[BG];
@@ -472,13 +477,15 @@ __global__ void k_admm_padk(const T *u, int R, int m, int n1, int n2, Cx<T> *out
     out[e] = Cx<T>{acc, T(0)};
 }
 
+// mx[k] = max |u_k^| over the plane: grid (blocks, m), one atomic max per workgroup on the
+// value's bit pattern (non-negative IEEE values order like their bits); mx zeroed first
 template <typename T>
 __global__ __launch_bounds__(NTF) void k_admm_absmax(const Cx<T> *uh, int64_t N, T *mx)
 {
     __shared__ T red[NTF];
-    const Cx<T> *p = uh + (int64_t)blockIdx.x * N;
+    const Cx<T> *p = uh + (int64_t)blockIdx.y * N;
     T m = T(0);
-    for (int64_t i = threadIdx.x; i < N; i += NTF) {
+    for (int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x; i < N; i += (int64_t)gridDim.x * NTF) {
         const T a = sqrt(p[i].re * p[i].re + p[i].im * p[i].im);
         m = a > m ? a : m;
     }
@@ -488,7 +495,18 @@ __global__ __launch_bounds__(NTF) void k_admm_absmax(const Cx<T> *uh, int64_t N,
         if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x + s] > red[threadIdx.x] ? red[threadIdx.x + s] : red[threadIdx.x];
         __syncthreads();
     }
-    if (threadIdx.x == 0) mx[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        if constexpr (sizeof(T) == 8)
+            atomicMax(reinterpret_cast<unsigned long long *>(mx) + blockIdx.y, __double_as_longlong(red[0]));
+        else
+            atomicMax(reinterpret_cast<unsigned int *>(mx) + blockIdx.y, __float_as_uint(red[0]));
+    }
+}
+
+template <typename T>
+__global__ void k_fill_zero(T *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = T(0);
 }
 
 // gamma_k = mx_k / sum_j mx_j (1/m when every kernel is zero)
@@ -668,7 +686,10 @@ hipError_t launch_admm_padk(const T *u, int R, int m, int n1, int n2, Cx<T> *out
 template <typename T>
 hipError_t launch_admm_absmax(const Cx<T> *uh, int m, int64_t N, T *mx, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_absmax<T>, dim3(m), dim3(NTF), 0, s, uh, N, mx);
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3(1), dim3(64), 0, s, mx, m);
+    int64_t nb = (N + NTF * 8 - 1) / (NTF * 8);
+    if (nb > 256) nb = 256;
+    hipLaunchKernelGGL(k_admm_absmax<T>, dim3((unsigned)nb, m), dim3(NTF), 0, s, uh, N, mx);
     return hipGetLastError();
 }
 template <typename T>
