@@ -339,7 +339,11 @@ size_t pd_admm_workspace_size(const pd_shape *shape, int32_t dtype, int32_t term
  *           channels, ||g - V f||^2_D, ||z - Psi^* f||^2 and ||z||_{1,w}
  *           (the primal residuals after the multiplier step, and the
  *           penalty), accumulated in FP64; zeroed by the call.
- * Asynchronous on `stream` (no host synchronisation).
+ * Asynchronous on `stream` (no host synchronisation).  Part of each iteration
+ * (the transforms and the zeta / z step) runs on a library-owned second
+ * stream of the current device, ordered by events against `stream` and joined
+ * back into it before the call returns; calls that share a workspace on
+ * different streams race, as for every entry point.
  * Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_TAU (beta), PD_ERR_WORKSPACE,
  * PD_ERR_UNSUPPORTED, PD_ERR_HIP. */
 int pd_admm_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,

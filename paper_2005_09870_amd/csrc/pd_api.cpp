@@ -1467,6 +1467,32 @@ AdmmLayout admm_layout(const pd_shape *sh, size_t es, int m)
     return l;
 }
 
+// A second, library-owned stream per device (default priority) with two events, for work that
+// runs beside the caller's stream inside one call and is joined before the call returns.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+};
+std::mutex g_side_mu;
+
+bool side_stream(SideStream &out)
+{
+    static std::map<int, SideStream> side;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto it = side.find(dev);
+    if (it == side.end()) {
+        SideStream ss;
+        if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&ss.ready, hipEventDisableTiming) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&ss.done, hipEventDisableTiming) != hipSuccess) return false;
+        it = side.emplace(dev, ss).first;
+    }
+    out = it->second;
+    return true;
+}
+
 template <typename T>
 int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w, double beta,
               int iters, const T *f0, T *f_out, T *z_out, double *stats, void *workspace, size_t ws_bytes,
@@ -1481,6 +1507,10 @@ int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, 
     s1.channels = 1;
     Ctx<T> c = make_ctx<T>(&s1, wav, workspace, st, 0);
     if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
+    SideStream side;
+    if (!side_stream(side)) return PD_ERR_HIP;
+    Ctx<T> c2 = c;  // the same transforms and scratch, launched on the side stream
+    c2.st = side.s;
     AdmmArgs<T> a{};
     a.n1 = n1;
     a.n2 = n2;
@@ -1552,6 +1582,16 @@ int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, 
                 }));
             return PD_OK;
         };
+        // Two streams.  The caller's stream runs the g-step (FFTs and the spectral product) and
+        // the f-step; the side stream runs, after each f-step, the analysis of f, the zeta / z
+        // step and the synthesis of the next beta2 z + zeta.  Neither stream touches the other's
+        // buffers between the joins: the g-step reads and writes the complex planes, the side
+        // chain f, z, zeta, Psi^* f, the synthesis buffers and the transforms' scratch pyramid;
+        // the f-step (after a join) reads the synthesis and writes f and the next a_k.
+        PD_TRY_HIP(hipEventRecord(side.ready, st));
+        PD_TRY_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
+        if ((rc = synth_chain<T>(c2, tfz, tfz, T(0), tfs)) != PD_OK) return rc;
+        PD_TRY_HIP(hipEventRecord(side.done, side.s));
         for (int it = 0; it < iters; ++it) {
             const int next = it + 1 < iters;
             a.slots = stats ? c.slots(it) : nullptr;
@@ -1561,17 +1601,22 @@ int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, 
             PD_TRY_HIP(timed(PD_K_ADMM, 1, st, [&] { return launch_admm_accq<T>(a, st); }));
             if ((rc = fft(1)) != PD_OK) return rc;
             // f (the z of this iteration was formed with the previous multiplier step), multipliers
-            if ((rc = synth_chain<T>(c, tfz, tfz, T(0), tfs)) != PD_OK) return rc;
+            PD_TRY_HIP(hipStreamWaitEvent(st, side.done, 0));
             PD_TRY_HIP(timed(PD_K_ADMM, 2, st, [&] { return launch_admm_f<T>(a, next, st); }));
-            if ((rc = analysis_plain<T>(c, a.f, a.tz)) != PD_OK) return rc;
-            PD_TRY_HIP(timed(PD_K_ADMM, 3, st, [&] { return launch_admm_zeta<T>(a, next, st); }));
+            PD_TRY_HIP(hipEventRecord(side.ready, st));
+            PD_TRY_HIP(hipStreamWaitEvent(side.s, side.ready, 0));
+            if ((rc = analysis_plain<T>(c2, a.f, a.tz)) != PD_OK) return rc;
+            PD_TRY_HIP(timed(PD_K_ADMM, 3, side.s, [&] { return launch_admm_zeta<T>(a, next, side.s); }));
             // batches of at most PD_RING - 1 entries, so that the entry of iteration it + 1 (whose
             // penalty term is already in the ring) is never finalised with an older one
             if (stats && (it + 1 - b0 == PD_RING - 1 || it == iters - 1)) {
-                PD_TRY_HIP(launch_stats_finalize(c.ring(), stats, b0, it + 1 - b0, st));
+                PD_TRY_HIP(launch_stats_finalize(c.ring(), stats, b0, it + 1 - b0, side.s));
                 b0 = it + 1;
             }
+            if (next && (rc = synth_chain<T>(c2, tfz, tfz, T(0), tfs)) != PD_OK) return rc;
+            PD_TRY_HIP(hipEventRecord(side.done, side.s));
         }
+        PD_TRY_HIP(hipStreamWaitEvent(st, side.done, 0));  // join before the next channel / return
     }
     return PD_OK;
 }
