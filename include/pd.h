@@ -361,6 +361,36 @@ size_t pd_fft2_workspace_size(int32_t n1, int32_t n2, int32_t dtype);
 int pd_fft2(int32_t n1, int32_t n2, int32_t batch, int32_t dtype, int32_t inverse, void *data, void *workspace,
             size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------ Algorithm 1 --
+ * The wavelet representation of a product-convolution operator H = sum_k U_k V_k
+ * (Section 3.2, Algorithm 1; Section 5): Theta~ = sum_k A~_k B_k with
+ * A_k = Psi^* U_k Psi, B_k = Psi^* V_k Psi, eps_k = eta / (m ||v_k||_inf) and A~_k
+ * the entries of A_k above t_k, the largest entry magnitude whose dropped part E
+ * has Schur bound sqrt(||E||_1 ||E||_inf) <= eps_k; then ||Theta - Theta~||_2 <= eta.
+ * FP64 throughout.  A_k is formed from its circulant sub-band generators (one probe
+ * transform per band and direction), B_k column by column, C_k = A~_k B_k by
+ * spreading each nonzero of a column of B_k over the kept generator entries. */
+
+/* Bytes of device workspace pd_decompose needs for m = terms (channels ignored).
+ * Includes worst-case room for the kept generator entries. 0 on bad arguments. */
+size_t pd_decompose_workspace_size(const pd_shape *shape, int32_t terms);
+
+/* Theta~ by columns (CSC; equivalently the CSR of its transpose).
+ *   shape   n1 x n2, channels = 1, levels >= 1 (as for pd_fwt).
+ *   op      PD_OP_PC with FP64 taps [m][2R+1][2R+1] and mult [m][n2][n1] (device).
+ *   eta     >= 0 (0: every nonzero of A_k kept, Theta~ = Theta up to rounding).
+ *   capacity  room in rows / vals (device int32 / double); *nnz (host) gets the
+ *           number of entries of Theta~; col_ptr (device int64 [n1 n2 + 1]) is always
+ *           written; rows within a column ascend.  If nnz > capacity the entries are
+ *           not all written and PD_ERR_WORKSPACE is returned (call again with
+ *           capacity >= nnz; capacity 0 with rows = vals = NULL only counts).
+ * Synchronises the host with `stream` (the thresholds are chosen on the host).
+ * Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_TAU (eta), PD_ERR_WORKSPACE,
+ * PD_ERR_UNSUPPORTED (not PD_OP_PC), PD_ERR_HIP. */
+int pd_decompose(const pd_shape *shape, const pd_operator *op, const pd_wavelet *wav, double eta, int64_t capacity,
+                 int64_t *nnz, int64_t *col_ptr, int32_t *rows, double *vals, void *workspace, size_t ws_bytes,
+                 void *stream);
+
 /* Diagnostics: per-launch kernel timing.  While enabled, every kernel launch
  * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt / pd_wsolve /
  * pd_admm_solve (its iteration loop) is bracketed by

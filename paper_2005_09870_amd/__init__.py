@@ -15,6 +15,8 @@ from .solver import (  # noqa: F401
     pd_admm_solve,
     pd_admm_workspace_size,
     pd_apply_op,
+    pd_decompose,
+    pd_decompose_workspace_size,
     pd_fft2,
     pd_fwt,
     pd_graphs_enable,

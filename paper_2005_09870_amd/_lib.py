@@ -65,7 +65,7 @@ EXPORTS = [
     "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
     "pd_wsolve_workspace_size", "pd_wsolve", "pd_admm_workspace_size", "pd_admm_solve",
-    "pd_fft2_workspace_size", "pd_fft2",
+    "pd_fft2_workspace_size", "pd_fft2", "pd_decompose_workspace_size", "pd_decompose",
 ]
 
 PD_K_BLUR, PD_K_SYNTH, PD_K_ANALYSIS, PD_K_COARSE, PD_K_OTHER = 1, 2, 3, 4, 5
@@ -144,6 +144,11 @@ def load() -> ctypes.CDLL:
     L.pd_fft2_workspace_size.restype = sz
     L.pd_fft2.argtypes = [i32, i32, i32, i32, i32, vp, vp, sz, vp]
     L.pd_fft2.restype = ctypes.c_int
+    L.pd_decompose_workspace_size.argtypes = [P(pd_shape), i32]
+    L.pd_decompose_workspace_size.restype = sz
+    L.pd_decompose.argtypes = [P(pd_shape), P(pd_operator), P(pd_wavelet), d, ctypes.c_int64,
+                               P(ctypes.c_int64), vp, vp, vp, vp, sz, vp]
+    L.pd_decompose.restype = ctypes.c_int
     L.pd_strerror.argtypes = [i32]
     L.pd_strerror.restype = ctypes.c_char_p
     _lib = L

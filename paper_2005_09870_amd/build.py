@@ -24,7 +24,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-result"]
 
-SOURCES = ["pd_kernels.hip", "pd_wkernels.hip", "pd_pckernels.hip", "pd_admm.hip", "pd_api.cpp", "pd_wapi.cpp", "pd_setup.cpp"]
+SOURCES = ["pd_kernels.hip", "pd_wkernels.hip", "pd_pckernels.hip", "pd_admm.hip", "pd_decomp.hip", "pd_api.cpp", "pd_wapi.cpp", "pd_setup.cpp"]
 
 
 def build(verbose: bool = True) -> str:

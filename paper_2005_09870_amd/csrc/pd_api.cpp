@@ -17,6 +17,7 @@
 #include "pd_kernels.h"
 #include "pd_pckernels.h"
 #include "pd_admm.h"
+#include "pd_decomp.h"
 
 using namespace pd;
 
@@ -1685,4 +1686,334 @@ extern "C" int pd_fft2(int32_t n1, int32_t n2, int32_t batch, int32_t dtype, int
         PD_TRY_HIP(launch_fft2<double>((Cx<double> *)data, n1, n2, batch, t1, t2, inverse != 0, st));
     }
     return PD_OK;
+}
+
+// -------------------------------------------------------------- Algorithm 1 --
+// Theta~ = sum_k A~_k B_k (Section 3.2, Algorithm 1; Section 5), FP64.  Per term:
+// the circulant generators of A_k from one probe per band (Section 5.1), the
+// threshold of A_k on the host from the generators (largest entry magnitude whose
+// dropped part has Schur bound sqrt(||E||_1 ||E||_inf) <= eps_k = eta / (m ||v_k||_inf)),
+// then, for batches of columns mu, B_k e_mu = Psi^* (v_k . Psi e_mu) and
+// C_k e_mu = A~_k B_k e_mu accumulated over k, compacted to CSC.
+namespace {
+
+constexpr int DEC_BATCH = 256;
+
+struct DecLayout {
+    size_t ctx, X, T, Y, ACC, G, pos, cnt, base, bands, off, tcnt, roff, res, ent, total;
+};
+
+int dec_nbands(int L) { return 3 * L + 1; }
+
+// Worst-case table sizes for m terms: every generator entry of a pair's block kept (each block
+// covers one band, nb blocks per band: 2 nb N entries per term) and one residue class per source
+// position of a coarser-target pair (at most nb N per term) plus two offsets per pair.
+DecLayout dec_layout(const pd_shape *sh, int m = 1)
+{
+    const size_t N = (size_t)sh->n1 * sh->n2;
+    const int nb = dec_nbands(sh->levels);
+    const int P = (int)std::max<size_t>(std::min<size_t>(N, DEC_BATCH), (size_t)(2 * nb));
+    pd_shape sc = *sh;
+    sc.channels = P;
+    DecLayout l;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    l.ctx = take(layout(&sc, 8).total);
+    l.X = take((size_t)P * N * 8);
+    l.T = take((size_t)P * N * 8);
+    l.Y = take((size_t)P * N * 8);
+    l.ACC = take((size_t)P * N * 8);
+    l.G = take((size_t)2 * nb * N * 8);
+    l.pos = take((size_t)2 * nb * 4);
+    l.cnt = take((size_t)P * 8);
+    l.base = take((size_t)P * 8);
+    l.bands = take((size_t)nb * sizeof(DecBand));
+    const size_t pairs = (size_t)m * nb * nb;
+    l.off = take(pairs * 8);
+    l.tcnt = take(pairs * 4);
+    l.roff = take(pairs * 8);
+    l.res = take(((size_t)m * nb * N + 2 * pairs) * 4);
+    l.ent = take((size_t)m * 2 * nb * N * sizeof(DecEntry));
+    l.total = off;
+    return l;
+}
+
+std::vector<DecBand> dec_bands(int n1, int n2, int L)
+{
+    std::vector<DecBand> b;
+    for (int lev = 1; lev <= L; ++lev) {
+        const int g2 = n2 >> lev, g1 = n1 >> lev;
+        b.push_back({lev, 0, g1, g2, g1});   // x1 high
+        b.push_back({lev, g2, 0, g2, g1});   // x2 high
+        b.push_back({lev, g2, g1, g2, g1});  // both high
+    }
+    b.push_back({L, 0, 0, n2 >> L, n1 >> L});  // approximation
+    return b;
+}
+
+// Host side of the threshold: col[b'] / row[b] are the generator planes (Mallat layout) of A_k's
+// column at source band b''s origin and of its row at target band b's origin.
+struct DecGen {
+    const std::vector<DecBand> &B;
+    const double *col, *row;  // [nb][N]
+    int n1;
+    int64_t N;
+    double at(const double *g, int which, const DecBand &b, int q2, int q1) const
+    {
+        return std::fabs(g[(int64_t)which * N + (int64_t)(b.o2 + q2) * n1 + b.o1 + q1]);
+    }
+    // max over columns and rows of the dropped magnitudes (|a| <= t), then the Schur bound
+    double bound(double t) const
+    {
+        const int nb = (int)B.size();
+        double colmax = 0.0, rowmax = 0.0;
+        std::vector<double> tot, R;
+        for (int side = 0; side < 2; ++side) {
+            for (int x = 0; x < nb; ++x) {  // side 0: source band x (columns); side 1: target band x (rows)
+                const int lx = B[x].lev;
+                double base = 0.0;
+                int F = 1;
+                for (int y = 0; y < nb; ++y) {
+                    const int ly = B[y].lev;
+                    if (side == 0 ? ly > lx : ly >= lx) F = std::max(F, 1 << std::abs(ly - lx));
+                }
+                tot.assign((size_t)F * F, 0.0);
+                for (int y = 0; y < nb; ++y) {
+                    const int ly = B[y].lev;
+                    // the block's generator and the band its entries lie in
+                    const bool by_col = side == 0 ? ly <= lx : ly >= lx;
+                    const double *g = by_col ? col : row;
+                    const int which = side == 0 ? (by_col ? x : y) : (by_col ? y : x);
+                    const DecBand &eb = side == 0 ? (by_col ? B[y] : B[x]) : (by_col ? B[x] : B[y]);
+                    const bool residues = side == 0 ? ly > lx : ly >= lx;
+                    if (!residues) {
+                        for (int q2 = 0; q2 < eb.g2; ++q2)
+                            for (int q1 = 0; q1 < eb.g1; ++q1) {
+                                const double a = at(g, which, eb, q2, q1);
+                                if (a <= t) base += a;
+                            }
+                        continue;
+                    }
+                    const int f = 1 << std::abs(ly - lx);
+                    R.assign((size_t)f * f, 0.0);
+                    for (int q2 = 0; q2 < eb.g2; ++q2)
+                        for (int q1 = 0; q1 < eb.g1; ++q1) {
+                            const double a = at(g, which, eb, q2, q1);
+                            if (a <= t) R[(q2 % f) * f + (q1 % f)] += a;
+                        }
+                    for (int r2 = 0; r2 < F; ++r2)
+                        for (int r1 = 0; r1 < F; ++r1) tot[(size_t)r2 * F + r1] += R[(r2 % f) * f + (r1 % f)];
+                }
+                double mx = 0.0;
+                for (double v : tot) mx = std::max(mx, v);
+                mx += base;
+                if (side == 0)
+                    colmax = std::max(colmax, mx);
+                else
+                    rowmax = std::max(rowmax, mx);
+            }
+        }
+        return std::sqrt(colmax * rowmax);
+    }
+    // every entry magnitude of A_k (each block's generator over its band), nonzero, sorted, unique
+    std::vector<double> candidates() const
+    {
+        const int nb = (int)B.size();
+        std::vector<double> v;
+        for (int bp = 0; bp < nb; ++bp)
+            for (int b = 0; b < nb; ++b) {
+                const bool by_col = B[b].lev <= B[bp].lev;
+                const DecBand &eb = by_col ? B[b] : B[bp];
+                for (int q2 = 0; q2 < eb.g2; ++q2)
+                    for (int q1 = 0; q1 < eb.g1; ++q1) {
+                        const double a = at(by_col ? col : row, by_col ? bp : b, eb, q2, q1);
+                        if (a != 0.0) v.push_back(a);
+                    }
+            }
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        return v;
+    }
+};
+
+int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, double eta, int64_t capacity,
+                   int64_t *nnz_out, int64_t *col_ptr, int32_t *rows, double *vals, void *workspace,
+                   size_t ws_bytes, hipStream_t st)
+{
+    const int n1 = sh->n1, n2 = sh->n2, L = sh->levels, m = op->terms, R = op->radius;
+    const int64_t N = (int64_t)n1 * n2;
+    const int nb = dec_nbands(L);
+    const DecLayout Ly = dec_layout(sh, m);
+    if (ws_bytes < Ly.total) return PD_ERR_WORKSPACE;
+    char *ws = (char *)workspace;
+    const int P = (int)std::max<int64_t>(std::min<int64_t>(N, DEC_BATCH), 2 * nb);
+    double *X = (double *)(ws + Ly.X), *T = (double *)(ws + Ly.T), *Y = (double *)(ws + Ly.Y);
+    double *ACC = (double *)(ws + Ly.ACC), *G = (double *)(ws + Ly.G);
+    int *dpos = (int *)(ws + Ly.pos);
+    int64_t *dcnt = (int64_t *)(ws + Ly.cnt), *dbase = (int64_t *)(ws + Ly.base);
+    const std::vector<DecBand> bands = dec_bands(n1, n2, L);
+    PD_TRY_HIP(hipMemcpyAsync(ws + Ly.bands, bands.data(), nb * sizeof(DecBand), hipMemcpyHostToDevice, st));
+    // probes: a Dirac at every band origin (columns, then rows)
+    std::vector<int> pos(2 * nb);
+    for (int b = 0; b < nb; ++b) pos[b] = pos[nb + b] = bands[b].o2 * n1 + bands[b].o1;
+    PD_TRY_HIP(hipMemcpyAsync(dpos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, st));
+    // multipliers on the host for ||v_k||_inf
+    std::vector<double> hv((size_t)m * N), hg((size_t)2 * nb * N), hu((size_t)m * (2 * R + 1) * (2 * R + 1));
+    PD_TRY_HIP(hipMemcpyAsync(hv.data(), op->mult, hv.size() * 8, hipMemcpyDeviceToHost, st));
+    pd_shape sc = *sh;
+    sc.channels = 2 * nb;
+    {
+        Ctx<double> c = make_ctx<double>(&sc, wav, ws + Ly.ctx, st, 0);
+        if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
+        std::vector<int64_t> off, roff;
+        std::vector<int> cnt, res;
+        std::vector<DecEntry> ent;
+        off.reserve((size_t)m * nb * nb);
+        for (int k = 0; k < m; ++k) {
+            const double *uk = (const double *)op->taps + (int64_t)k * (2 * R + 1) * (2 * R + 1);
+            PD_TRY_HIP(launch_dec_dirac_at(X, dpos, 2 * nb, N, st));
+            int rc;
+            if ((rc = synth_chain<double>(c, X, X, 0.0, T)) != PD_OK) return rc;
+            PD_TRY_HIP(launch_dec_conv(T, X, nb, uk, R, n1, n2, 0, st));
+            PD_TRY_HIP(launch_dec_conv(T + (int64_t)nb * N, X + (int64_t)nb * N, nb, uk, R, n1, n2, 1, st));
+            if ((rc = analysis_plain<double>(c, X, G)) != PD_OK) return rc;
+            PD_TRY_HIP(hipMemcpyAsync(hg.data(), G, hg.size() * 8, hipMemcpyDeviceToHost, st));
+            PD_TRY_HIP(hipStreamSynchronize(st));
+            double vinf = 0.0;
+            for (int64_t i = 0; i < N; ++i) vinf = std::max(vinf, std::fabs(hv[(size_t)k * N + i]));
+            DecGen gen{bands, hg.data(), hg.data() + (size_t)nb * N, n1, N};
+            double t = 0.0;
+            bool keep_none = false;
+            if (vinf == 0.0) {
+                keep_none = true;  // V_k = 0: the term contributes nothing
+            } else {
+                const double eps = eta / ((double)m * vinf);
+                const std::vector<double> cand = gen.candidates();
+                int lo = 0, hi = (int)cand.size() - 1;
+                while (lo <= hi) {  // the bound grows with t: bisect over the sorted magnitudes
+                    const int mid = (lo + hi) / 2;
+                    if (gen.bound(cand[mid]) <= eps) {
+                        t = cand[mid];
+                        lo = mid + 1;
+                    } else {
+                        hi = mid - 1;
+                    }
+                }
+            }
+            // kept generator entries per (source, target) pair; coarser targets grouped by residue
+            for (int bp = 0; bp < nb; ++bp)
+                for (int b = 0; b < nb; ++b) {
+                    const bool by_col = bands[b].lev <= bands[bp].lev;
+                    const DecBand &eb = by_col ? bands[b] : bands[bp];
+                    const double *g = by_col ? gen.col + (int64_t)bp * N : gen.row + (int64_t)b * N;
+                    off.push_back((int64_t)ent.size());
+                    roff.push_back((int64_t)res.size());
+                    const int f = by_col ? 1 : 1 << (bands[b].lev - bands[bp].lev);
+                    std::vector<std::vector<DecEntry>> cls((size_t)f * f);
+                    if (!keep_none)
+                        for (int q2 = 0; q2 < eb.g2; ++q2)
+                            for (int q1 = 0; q1 < eb.g1; ++q1) {
+                                const double a = g[(int64_t)(eb.o2 + q2) * n1 + eb.o1 + q1];
+                                if (std::fabs(a) > t) cls[(q2 % f) * f + (q1 % f)].push_back({q2, q1, a});
+                            }
+                    int run = 0;
+                    for (auto &v : cls) {
+                        res.push_back(run);
+                        ent.insert(ent.end(), v.begin(), v.end());
+                        run += (int)v.size();
+                    }
+                    res.push_back(run);
+                    cnt.push_back(run);
+                }
+        }
+        // the tables, in the workspace (sized for the worst case)
+        if (res.size() * 4 > Ly.ent - Ly.res || ent.size() * sizeof(DecEntry) > Ly.total - Ly.ent) return PD_ERR_HIP;
+        DecTables tb{};
+        tb.nb = nb;
+        tb.n1 = n1;
+        tb.n2 = n2;
+        tb.bands = (const DecBand *)(ws + Ly.bands);
+        tb.off = (const int64_t *)(ws + Ly.off);
+        tb.cnt = (const int *)(ws + Ly.tcnt);
+        tb.roff = (const int64_t *)(ws + Ly.roff);
+        tb.res = (const int *)(ws + Ly.res);
+        tb.ent = (const DecEntry *)(ws + Ly.ent);
+        PD_TRY_HIP(hipMemcpyAsync(ws + Ly.off, off.data(), off.size() * 8, hipMemcpyHostToDevice, st));
+        PD_TRY_HIP(hipMemcpyAsync(ws + Ly.tcnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st));
+        PD_TRY_HIP(hipMemcpyAsync(ws + Ly.roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice, st));
+        PD_TRY_HIP(hipMemcpyAsync(ws + Ly.res, res.data(), res.size() * 4, hipMemcpyHostToDevice, st));
+        if (!ent.empty())
+            PD_TRY_HIP(hipMemcpyAsync(ws + Ly.ent, ent.data(), ent.size() * sizeof(DecEntry), hipMemcpyHostToDevice, st));
+        {
+            // columns in batches of P
+            pd_shape sb = *sh;
+            sb.channels = P;
+            Ctx<double> cb = make_ctx<double>(&sb, wav, ws + Ly.ctx, st, 0);
+            if (cb.ts.nt > 0 && !cb.tail) return PD_ERR_HIP;
+            std::vector<int64_t> hc(P), hbase(P), cp((size_t)N + 1, 0);
+            int64_t total = 0;
+            for (int64_t j0 = 0; j0 < N; j0 += P) {
+                const int np = (int)std::min<int64_t>(P, N - j0);
+                int r;
+                PD_TRY_HIP(launch_dec_dirac(T, j0, P, N, st));
+                if ((r = synth_chain<double>(cb, T, T, 0.0, X)) != PD_OK) return r;  // psi_mu
+                PD_TRY_HIP(launch_fill<double>(ACC, 0.0, (int64_t)P * N, st));
+                for (int k = 0; k < m; ++k) {
+                    PD_TRY_HIP(launch_dec_mul(X, (const double *)op->mult + (int64_t)k * N, T, P, N, st));
+                    if ((r = analysis_plain<double>(cb, T, Y)) != PD_OK) return r;  // B_k e_mu
+                    PD_TRY_HIP(launch_dec_acc(Y, ACC, np, tb, k, st));
+                }
+                PD_TRY_HIP(launch_dec_count(ACC, np, N, dcnt, st));
+                PD_TRY_HIP(hipMemcpyAsync(hc.data(), dcnt, np * 8, hipMemcpyDeviceToHost, st));
+                PD_TRY_HIP(hipStreamSynchronize(st));
+                for (int j = 0; j < np; ++j) {
+                    hbase[j] = total;
+                    total += hc[j];
+                    cp[(size_t)(j0 + j) + 1] = total;
+                }
+                if (total <= capacity && rows && vals) {
+                    PD_TRY_HIP(hipMemcpyAsync(dbase, hbase.data(), np * 8, hipMemcpyHostToDevice, st));
+                    PD_TRY_HIP(launch_dec_fill(ACC, np, N, dbase, rows, vals, st));
+                    PD_TRY_HIP(hipStreamSynchronize(st));  // hbase is rewritten by the next batch
+                }
+            }
+            *nnz_out = total;
+            PD_TRY_HIP(hipMemcpyAsync(col_ptr, cp.data(), cp.size() * 8, hipMemcpyHostToDevice, st));
+            PD_TRY_HIP(hipStreamSynchronize(st));  // the host tables and cp live until here
+            return total <= capacity ? PD_OK : PD_ERR_WORKSPACE;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" size_t pd_decompose_workspace_size(const pd_shape *shape, int32_t terms)
+{
+    if (!shape || shape->levels < 1 || terms < 1 || terms > PD_MAX_PC) return 0;
+    pd_shape s = *shape;
+    s.channels = 1;
+    if (check_shape(&s) != PD_OK) return 0;
+    return dec_layout(&s, terms).total;
+}
+
+extern "C" int pd_decompose(const pd_shape *shape, const pd_operator *op, const pd_wavelet *wav, double eta,
+                            int64_t capacity, int64_t *nnz, int64_t *col_ptr, int32_t *rows, double *vals,
+                            void *workspace, size_t ws_bytes, void *stream)
+{
+    int rc;
+    if (!shape) return PD_ERR_ARG;
+    pd_shape s = *shape;
+    if (s.channels != 1) return PD_ERR_SHAPE;
+    if ((rc = check_shape(&s)) || (rc = check_op(op, &s)) || (rc = check_wavelet(wav))) return rc;
+    if (s.levels < 1) return PD_ERR_SHAPE;
+    if (op->kind != PD_OP_PC) return PD_ERR_UNSUPPORTED;
+    if (!std::isfinite(eta) || eta < 0.0) return PD_ERR_TAU;
+    if (!nnz || !col_ptr || !workspace || capacity < 0 || (capacity > 0 && (!rows || !vals))) return PD_ERR_ARG;
+    if ((int64_t)s.n1 * s.n2 > INT32_MAX) return PD_ERR_UNSUPPORTED;
+    return decompose_impl(&s, op, wav, eta, capacity, nnz, col_ptr, rows, vals, workspace, ws_bytes,
+                          (hipStream_t)stream);
 }

@@ -525,3 +525,51 @@ def pd_fft2(x: torch.Tensor, inverse: bool = False) -> torch.Tensor:
                           _stream(y.device))
     C.check(rc, "pd_fft2")
     return y
+
+
+# ------------------------------------------------------------- Algorithm 1 ---
+def pd_decompose_workspace_size(n1: int, n2: int, levels: int, terms: int) -> int:
+    shape = C.pd_shape(n1, n2, 1, levels)
+    return int(C.load().pd_decompose_workspace_size(ctypes.byref(shape), int(terms)))
+
+
+def pd_decompose(op: Operator, h, levels: int, n2: int, n1: int, eta: float, capacity: int | None = None,
+                 ws: torch.Tensor | None = None) -> Csr:
+    """Algorithm 1 (Section 3.2): Theta~ = sum_k A~_k B_k for the FP64
+    product-convolution operator `op` (Operator.pc with dtype float64) on an
+    n2 x n1 image, eps_k = eta / (m ||v_k||_inf).  Returns Theta~ by columns,
+    i.e. the CSR of its transpose (pd_csr_transpose gives Theta~ by rows).
+    capacity None: a first call sizes the output, a second fills it."""
+    if op.kind != C.PD_OP_PC or op.taps.dtype != torch.float64 or op.mult.dtype != torch.float64:
+        raise ValueError("pd_decompose needs a float64 product-convolution operator")
+    _check_dev(op.taps, op.mult)
+    dev = op.taps.device
+    shape = C.pd_shape(int(n1), int(n2), 1, int(levels))
+    wav, _hk = _wavelet(h)
+    oc = op.c()
+    m = int(op.mult.shape[0])
+    need = pd_decompose_workspace_size(n1, n2, levels, m)
+    if need == 0:
+        raise ValueError("pd_decompose: unsupported shape or terms")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    N = int(n1) * int(n2)
+    col_ptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64(0)
+    L = C.load()
+    st = _stream(dev)
+
+    def call(cap, rows, vals):
+        return L.pd_decompose(ctypes.byref(shape), ctypes.byref(oc), ctypes.byref(wav), float(eta), int(cap),
+                              ctypes.byref(nnz), _ptr(col_ptr), _ptr(rows), _ptr(vals), _ptr(ws), ws.numel(), st)
+
+    if capacity is None:
+        rc = call(0, None, None)
+        if rc not in (C.PD_OK, C.PD_ERR_WORKSPACE):
+            C.check(rc, "pd_decompose")
+        capacity = nnz.value
+    rows = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=dev)
+    vals = torch.empty(max(int(capacity), 1), dtype=torch.float64, device=dev)
+    C.check(call(capacity, rows if capacity else None, vals if capacity else None), "pd_decompose")
+    k = nnz.value
+    return Csr(col_ptr, rows[:k], vals[:k])

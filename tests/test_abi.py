@@ -205,3 +205,30 @@ def test_admm_argument_errors_without_gpu_work():
     assert L.pd_fft2(64, 32, 1, C.PD_F32, 0, None, _fake(2), 1 << 20, None) == C.PD_ERR_ARG
     assert L.pd_fft2(64, 32, 1, C.PD_F32, 0, _fake(1), _fake(2), 8, None) == C.PD_ERR_WORKSPACE
     assert L.pd_fft2(64, 32, 0, C.PD_F32, 0, None, None, 0, None) == C.PD_OK
+
+
+def test_decompose_argument_errors_without_gpu_work():
+    L = C.load()
+    h = S.pd_symmlet(6)
+    wav = C.pd_wavelet(12, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    op = C.pd_operator(C.PD_OP_PC, 1, _fake(8), 2, _fake(9))
+    nnz = ctypes.c_int64(0)
+
+    def call(shape, op=op, eta=0.1, cap=0, rows=None, vals=None, ws=4, ws_bytes=1 << 40, cp=5):
+        return L.pd_decompose(ctypes.byref(shape), ctypes.byref(op), ctypes.byref(wav), eta, cap, ctypes.byref(nnz),
+                              _fake(cp) if cp else None, rows, vals, _fake(ws) if ws else None, ws_bytes, None)
+
+    ok = C.pd_shape(32, 16, 1, 2)
+    assert call(C.pd_shape(32, 16, 2, 2)) == C.PD_ERR_SHAPE
+    assert call(C.pd_shape(32, 16, 1, 0)) == C.PD_ERR_SHAPE
+    assert call(ok, op=C.pd_operator(C.PD_OP_ROWBLUR, 1, _fake(8), 0, None)) == C.PD_ERR_UNSUPPORTED
+    assert call(ok, eta=-1.0) == C.PD_ERR_TAU
+    assert call(ok, eta=float("inf")) == C.PD_ERR_TAU
+    assert call(ok, cap=-1) == C.PD_ERR_ARG
+    assert call(ok, cap=10) == C.PD_ERR_ARG          # capacity without rows / vals
+    assert call(ok, cp=0) == C.PD_ERR_ARG
+    need = L.pd_decompose_workspace_size(ctypes.byref(ok), 2)
+    assert need > 4 * 256 * 512 * 8
+    assert L.pd_decompose_workspace_size(ctypes.byref(ok), 3) > need
+    assert L.pd_decompose_workspace_size(ctypes.byref(ok), 0) == 0
+    assert call(ok, ws_bytes=need - 1) == C.PD_ERR_WORKSPACE

@@ -1,0 +1,92 @@
+"""GPU parity of Algorithm 1 (Section 3.2; Section 5): pd_decompose against the
+dense FP64 oracle on the same expansion.  Both sides threshold in FP64 with
+the same rule; Theta~ is compared entry by entry (1e-12 of its largest
+magnitude), and the certificate ||Theta - Theta~||_2 <= eta is checked on the
+GPU's output with an exact spectral norm.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O  # noqa: E402
+from oracle import decomposition as D  # noqa: E402
+from oracle import product_convolution as PC  # noqa: E402
+from oracle import wavelet_domain as W  # noqa: E402
+import paper_2005_09870_amd as P  # noqa: E402
+from paper_2005_09870_amd import _lib as C  # noqa: E402
+
+DEV = "cuda"
+H6 = O.symmlet(6)
+
+
+def _case(n2, n1, m, R, seed):
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((m, 2 * R + 1, 2 * R + 1)) / (2 * R + 1)
+    y2, y1 = np.meshgrid(np.arange(n2) / n2, np.arange(n1) / n1, indexing="ij")
+    v = np.stack([1.0 + 0.5 * np.cos(2 * np.pi * (a * y1 + b * y2) + c) for a, b, c in rng.uniform(0, 2, (m, 3))])
+    return u, v
+
+
+def _dense(cols: "P.Csr", N: int) -> np.ndarray:
+    cp = cols.row_ptr.cpu().numpy()
+    r = cols.col.cpu().numpy()
+    v = cols.val.cpu().numpy()
+    M = np.zeros((N, N))
+    for j in range(N):
+        M[r[cp[j]:cp[j + 1]], j] = v[cp[j]:cp[j + 1]]
+    return M
+
+
+def _gpu(u, v, L, eta, **kw):
+    n2, n1 = v.shape[1:]
+    op = P.Operator.pc(u, v, dtype=torch.float64, device=DEV)
+    return P.pd_decompose(op, H6, L, n2, n1, eta, **kw)
+
+
+@pytest.mark.parametrize("n2,n1,L,m,R", [(16, 16, 2, 3, 2), (16, 32, 3, 2, 1), (32, 16, 2, 2, 3)])
+@pytest.mark.parametrize("eta", [0.0, 1e-2, 0.1])
+def test_decompose_matches_oracle(n2, n1, L, m, R, eta):
+    u, v = _case(n2, n1, m, R, n1 + 7 * m)
+    ref = D.decompose(u, v, L, H6, eta)["theta"]
+    cols = _gpu(u, v, L, eta)
+    got = _dense(cols, n1 * n2)
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    cp = cols.row_ptr.cpu().numpy()
+    assert cp[0] == 0 and np.all(np.diff(cp) >= 0) and cp[-1] == cols.nnz
+    r = cols.col.cpu().numpy()
+    for j in range(0, n1 * n2, 17):
+        assert np.all(np.diff(r[cp[j]:cp[j + 1]]) > 0)
+
+
+def test_exact_operator1_expansion_is_theta():
+    """eta = 0 with the full-rank expansion of Operator 1: Theta~ = Psi^* H Psi."""
+    n = 16
+    kt, R = O.op1_profiles(n)
+    u, vr, _ = PC.pc_expansion(kt, R)
+    v = PC.rows_to_pixels(vr, n)
+    ref = W.theta_dense(O.Problem(n, n, 1, 2, h=H6))
+    got = _dense(_gpu(u, v, 2, 0.0), n * n)
+    assert np.abs(got - ref).max() < 1e-11
+
+
+def test_certificate_on_gpu_output():
+    n2 = n1 = 32
+    L = 3
+    u, v = _case(n2, n1, 3, 2, 11)
+    theta = D.wavelet_matrix(lambda x: PC.apply_pc(u, v, x), n2, n1, L, H6)
+    for eta in (0.02, 0.2):
+        got = _dense(_gpu(u, v, L, eta), n1 * n2)
+        assert np.linalg.norm(theta - got, 2) <= eta * (1 + 1e-10)
+
+
+def test_capacity_and_count_only():
+    u, v = _case(16, 16, 2, 1, 3)
+    full = _gpu(u, v, 2, 0.05)
+    with pytest.raises(C.PDError) as e:
+        _gpu(u, v, 2, 0.05, capacity=max(full.nnz // 2, 1))
+    assert e.value.code == C.PD_ERR_WORKSPACE
+    again = _gpu(u, v, 2, 0.05, capacity=full.nnz)
+    assert torch.equal(again.row_ptr, full.row_ptr) and torch.equal(again.col, full.col)
+    assert torch.allclose(again.val, full.val, rtol=0, atol=1e-15)
