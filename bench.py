@@ -540,6 +540,41 @@ def admm_case(torch, P, SI, h, iters, n=512, m=5, beta=1.0):
                          "alg_bytes_per_launch": None if dom is None else alg[dom]}}
 
 
+def decompose_case(torch, P, h, n=128, m=5, eta=1.0):
+    """Algorithm 1 (Section 3.2) on an n x n image: the wavelet representation of
+    the rank-m expansion of Operator 1 (FP64), eps_k = eta / (m ||v_k||_inf).
+    Wall time of one pd_decompose (after a sizing call), nnz of Theta~ and the
+    per-kernel breakdown (HIP events on the launch stream)."""
+    import time
+    from paper_2005_09870_amd import pc as PCX
+    dev = "cuda"
+    taps, R = P.pd_op1_taps(n)
+    op = PCX.rowblur_pc_operator(taps, R, m, n, dtype=torch.float64, device=dev)
+    L = n.bit_length() - 1
+    ws = P.solver.workspace(P.pd_decompose_workspace_size(n, n, L, m), dev)
+    first = P.pd_decompose(op, h, L, n, n, eta, ws=ws)   # sizes the output (and warms up)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cols = P.pd_decompose(op, h, L, n, n, eta, capacity=first.nnz, ws=ws)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    P.solver.pd_timing_enable(True)
+    P.pd_decompose(op, h, L, n, n, eta, capacity=first.nnz, ws=ws)
+    torch.cuda.synchronize()
+    rows = P.solver.pd_timing_read()
+    P.solver.pd_timing_enable(False)
+    tot = {f"{r['kernel']}/{r['level']}": r["total_ms"] for r in rows}
+    gpu_ms = sum(tot.values())
+    dom = max(tot, key=tot.get)
+    log(f"[bench] decompose {n}^2 m={m} eta={eta}: {sec:.3f} s, nnz {cols.nnz} "
+        f"({cols.nnz / (n * n):.1f} per column), kernels {gpu_ms:.1f} ms, dominant {dom}")
+    return {"workload": f"{n}x{n} FP64, Operator 1's rank-{m} expansion, Symmlet-6, {L} levels, eta {eta}",
+            "seconds": round(sec, 4), "nnz": int(cols.nnz), "nnz_per_column": round(cols.nnz / (n * n), 2),
+            "kernel_ms_total": round(gpu_ms, 2),
+            "kernels_ms": {k: round(v, 3) for k, v in sorted(tot.items(), key=lambda kv: -kv[1])[:8]},
+            "dominant": dom}
+
+
 def copy_calibration(torch, nbytes=256 << 20):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -569,6 +604,8 @@ def main():
     ap.add_argument("--wavelet-iters", type=int, default=200)
     ap.add_argument("--no-admm", action="store_true")
     ap.add_argument("--admm-iters", type=int, default=200)
+    ap.add_argument("--no-decompose", action="store_true")
+    ap.add_argument("--decompose-n", type=int, default=128)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -644,6 +681,9 @@ def main():
     if not args.no_admm:
         log(f"[bench] ADMM-PC 512^2, {args.admm_iters} iterations")
         line["admm_pc_512"] = admm_case(torch, P, SI, h, args.admm_iters)
+    if not args.no_decompose:
+        log(f"[bench] Algorithm 1 {args.decompose_n}^2")
+        line["decompose"] = decompose_case(torch, P, h, n=args.decompose_n)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(SI)

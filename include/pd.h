@@ -393,7 +393,7 @@ int pd_decompose(const pd_shape *shape, const pd_operator *op, const pd_wavelet 
 
 /* Diagnostics: per-launch kernel timing.  While enabled, every kernel launch
  * made by pd_solve / pd_solve_batched / pd_backward / pd_fwt / pd_wsolve /
- * pd_admm_solve (its iteration loop) is bracketed by
+ * pd_admm_solve (its iteration loop) / pd_decompose is bracketed by
  * two HIP events recorded on its launch stream, keyed by kernel class and
  * decomposition level.  Adds one event pair per launch; not thread-safe.   */
 typedef enum {
@@ -406,8 +406,10 @@ typedef enum {
     PD_K_WPROX = 7,     /* wavelet domain: Theta_L^T u, prox and momentum      */
     PD_K_FFT = 8,       /* ADMM-PC: one 2-D FFT pass over the m planes (level 0/1
                            forward rows/columns, 2/3 inverse rows/columns)     */
-    PD_K_ADMM = 9       /* ADMM-PC element-wise steps (level 1 spectral, 2 f and
+    PD_K_ADMM = 9,      /* ADMM-PC element-wise steps (level 1 spectral, 2 f and
                            multipliers, 3 zeta and z)                          */
+    PD_K_DECOMP = 10    /* Algorithm 1: level 0 probe convolutions, 1 multiplier,
+                           2 spreading of B_k columns over A~_k, 3 count, 4 fill */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */

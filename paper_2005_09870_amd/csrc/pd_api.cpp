@@ -1878,8 +1878,10 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
             PD_TRY_HIP(launch_dec_dirac_at(X, dpos, 2 * nb, N, st));
             int rc;
             if ((rc = synth_chain<double>(c, X, X, 0.0, T)) != PD_OK) return rc;
-            PD_TRY_HIP(launch_dec_conv(T, X, nb, uk, R, n1, n2, 0, st));
-            PD_TRY_HIP(launch_dec_conv(T + (int64_t)nb * N, X + (int64_t)nb * N, nb, uk, R, n1, n2, 1, st));
+            PD_TRY_HIP(timed(PD_K_DECOMP, 0, st, [&] { return launch_dec_conv(T, X, nb, uk, R, n1, n2, 0, st); }));
+            PD_TRY_HIP(timed(PD_K_DECOMP, 0, st, [&] {
+                return launch_dec_conv(T + (int64_t)nb * N, X + (int64_t)nb * N, nb, uk, R, n1, n2, 1, st);
+            }));
             if ((rc = analysis_plain<double>(c, X, G)) != PD_OK) return rc;
             PD_TRY_HIP(hipMemcpyAsync(hg.data(), G, hg.size() * 8, hipMemcpyDeviceToHost, st));
             PD_TRY_HIP(hipStreamSynchronize(st));
@@ -1963,11 +1965,13 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
                 if ((r = synth_chain<double>(cb, T, T, 0.0, X)) != PD_OK) return r;  // psi_mu
                 PD_TRY_HIP(launch_fill<double>(ACC, 0.0, (int64_t)P * N, st));
                 for (int k = 0; k < m; ++k) {
-                    PD_TRY_HIP(launch_dec_mul(X, (const double *)op->mult + (int64_t)k * N, T, P, N, st));
+                    PD_TRY_HIP(timed(PD_K_DECOMP, 1, st, [&] {
+                        return launch_dec_mul(X, (const double *)op->mult + (int64_t)k * N, T, P, N, st);
+                    }));
                     if ((r = analysis_plain<double>(cb, T, Y)) != PD_OK) return r;  // B_k e_mu
-                    PD_TRY_HIP(launch_dec_acc(Y, ACC, np, tb, k, st));
+                    PD_TRY_HIP(timed(PD_K_DECOMP, 2, st, [&] { return launch_dec_acc(Y, ACC, np, tb, k, st); }));
                 }
-                PD_TRY_HIP(launch_dec_count(ACC, np, N, dcnt, st));
+                PD_TRY_HIP(timed(PD_K_DECOMP, 3, st, [&] { return launch_dec_count(ACC, np, N, dcnt, st); }));
                 PD_TRY_HIP(hipMemcpyAsync(hc.data(), dcnt, np * 8, hipMemcpyDeviceToHost, st));
                 PD_TRY_HIP(hipStreamSynchronize(st));
                 for (int j = 0; j < np; ++j) {
@@ -1977,7 +1981,8 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
                 }
                 if (total <= capacity && rows && vals) {
                     PD_TRY_HIP(hipMemcpyAsync(dbase, hbase.data(), np * 8, hipMemcpyHostToDevice, st));
-                    PD_TRY_HIP(launch_dec_fill(ACC, np, N, dbase, rows, vals, st));
+                    PD_TRY_HIP(
+                        timed(PD_K_DECOMP, 4, st, [&] { return launch_dec_fill(ACC, np, N, dbase, rows, vals, st); }));
                     PD_TRY_HIP(hipStreamSynchronize(st));  // hbase is rewritten by the next batch
                 }
             }
