@@ -384,6 +384,10 @@ size_t pd_decompose_workspace_size(const pd_shape *shape, int32_t terms);
  *           written; rows within a column ascend.  If nnz > capacity the entries are
  *           not all written and PD_ERR_WORKSPACE is returned (call again with
  *           capacity >= nnz; capacity 0 with rows = vals = NULL only counts).
+ * The FP64 sums are accumulated with atomic adds in no fixed order: two calls agree
+ * to rounding, and an entry that cancels can be exactly zero in one call and not
+ * in the other, so a count from one call may be short for the next by a few
+ * entries (size with some slack; col_ptr / rows / vals of one call are consistent).
  * Synchronises the host with `stream` (the thresholds are chosen on the host).
  * Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_TAU (eta), PD_ERR_WORKSPACE,
  * PD_ERR_UNSUPPORTED (not PD_OP_PC), PD_ERR_HIP. */

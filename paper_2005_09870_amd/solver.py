@@ -563,13 +563,22 @@ def pd_decompose(op: Operator, h, levels: int, n2: int, n1: int, eta: float, cap
         return L.pd_decompose(ctypes.byref(shape), ctypes.byref(oc), ctypes.byref(wav), float(eta), int(cap),
                               ctypes.byref(nnz), _ptr(col_ptr), _ptr(rows), _ptr(vals), _ptr(ws), ws.numel(), st)
 
-    if capacity is None:
+    sized = capacity is None
+    if sized:
         rc = call(0, None, None)
         if rc not in (C.PD_OK, C.PD_ERR_WORKSPACE):
             C.check(rc, "pd_decompose")
-        capacity = nnz.value
-    rows = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=dev)
-    vals = torch.empty(max(int(capacity), 1), dtype=torch.float64, device=dev)
-    C.check(call(capacity, rows if capacity else None, vals if capacity else None), "pd_decompose")
+        # the FP64 atomic sums are not bitwise reproducible, so an entry that cancels can be
+        # exactly zero in one call and not in the next: size with slack, refit if still short
+        capacity = nnz.value + max(1024, nnz.value // 64)
+    for attempt in range(3):
+        rows = torch.empty(max(int(capacity), 1), dtype=torch.int32, device=dev)
+        vals = torch.empty(max(int(capacity), 1), dtype=torch.float64, device=dev)
+        rc = call(capacity, rows if capacity else None, vals if capacity else None)
+        if rc == C.PD_ERR_WORKSPACE and sized and attempt < 2:
+            capacity = nnz.value + max(1024, nnz.value // 64)
+            continue
+        C.check(rc, "pd_decompose")
+        break
     k = nnz.value
     return Csr(col_ptr, rows[:k], vals[:k])
