@@ -8,8 +8,8 @@
 // coarser target, the row of a target at l is the generator row shifted by
 // 2^(lev_b - lev_b') l in b''s grid.  C_k = A~_k B_k is formed column by column:
 // every nonzero of a column of B_k spreads its generator entries into a dense
-// FP64 accumulator of that column (one workgroup per column), which is then
-// compacted in row order.
+// FP64 accumulator of that column held in LDS (one workgroup per column and
+// 16384-row part), which is then added to the column and compacted in row order.
 #include <hip/hip_runtime.h>
 
 #include "pd_decomp.h"
@@ -75,12 +75,21 @@ __device__ __forceinline__ int band_index(int i2, int i1, int n1, int n2, int nb
     return nb - 1;
 }
 
-__global__ __launch_bounds__(NTD) void k_dec_acc(const double *y, double *acc, DecTables t, int k)
+// Accumulator of one part of a column in LDS: 16384 FP64 values (128 KiB of the CU's 160 KiB);
+// part p of the grid covers Mallat positions [p DEC_LDS, (p + 1) DEC_LDS).
+constexpr int DEC_LDS = 16384;
+constexpr int NTA = 512;
+
+__global__ __launch_bounds__(NTA) void k_dec_acc(const double *y, double *acc, DecTables t, int k)
 {
+    __shared__ double part[DEC_LDS];
     const int64_t N = (int64_t)t.n1 * t.n2;
+    const int64_t p0 = (int64_t)blockIdx.y * DEC_LDS;
+    const int64_t plen = N - p0 < DEC_LDS ? N - p0 : DEC_LDS;
+    for (int i = threadIdx.x; i < DEC_LDS; i += NTA) part[i] = 0.0;
+    __syncthreads();
     const double *yc = y + (int64_t)blockIdx.x * N;
-    double *ac = acc + (int64_t)blockIdx.x * N;
-    for (int64_t nu = threadIdx.x; nu < N; nu += NTD) {
+    for (int64_t nu = threadIdx.x; nu < N; nu += NTA) {
         const double yv = yc[nu];
         if (yv == 0.0) continue;
         const int i2 = (int)(nu / t.n1), i1 = (int)(nu - (int64_t)i2 * t.n1);
@@ -89,6 +98,9 @@ __global__ __launch_bounds__(NTD) void k_dec_acc(const double *y, double *acc, D
         const int l2 = i2 - S.o2, l1 = i1 - S.o1;
         for (int b = 0; b < t.nb; ++b) {
             const DecBand B = t.bands[b];
+            // skip a target band whose rows lie outside this part
+            const int64_t first = (int64_t)B.o2 * t.n1, last = (int64_t)(B.o2 + B.g2) * t.n1;
+            if (last <= p0 || first >= p0 + plen) continue;
             const int64_t p = ((int64_t)k * t.nb + bs) * t.nb + b;
             const DecEntry *e = t.ent + t.off[p];
             if (B.lev <= S.lev) {  // finer-or-equal target: the generator column shifted by f l'
@@ -97,7 +109,8 @@ __global__ __launch_bounds__(NTD) void k_dec_acc(const double *y, double *acc, D
                 for (int q = 0; q < c; ++q) {
                     const DecEntry en = e[q];
                     const int r2 = (en.q2 + f * l2) % B.g2, r1 = (en.q1 + f * l1) % B.g1;
-                    atomicAdd(ac + (int64_t)(B.o2 + r2) * t.n1 + B.o1 + r1, yv * en.val);
+                    const int64_t ti = (int64_t)(B.o2 + r2) * t.n1 + B.o1 + r1 - p0;
+                    if (ti >= 0 && ti < plen) atomicAdd(part + ti, yv * en.val);
                 }
             } else {  // coarser target: the generator rows whose shift lands on l'
                 const int f = 1 << (B.lev - S.lev);
@@ -107,11 +120,15 @@ __global__ __launch_bounds__(NTD) void k_dec_acc(const double *y, double *acc, D
                     const DecEntry en = e[q];
                     const int r2 = ((((l2 - en.q2) / f) % B.g2) + B.g2) % B.g2;
                     const int r1 = ((((l1 - en.q1) / f) % B.g1) + B.g1) % B.g1;
-                    atomicAdd(ac + (int64_t)(B.o2 + r2) * t.n1 + B.o1 + r1, yv * en.val);
+                    const int64_t ti = (int64_t)(B.o2 + r2) * t.n1 + B.o1 + r1 - p0;
+                    if (ti >= 0 && ti < plen) atomicAdd(part + ti, yv * en.val);
                 }
             }
         }
     }
+    __syncthreads();
+    double *ac = acc + (int64_t)blockIdx.x * N + p0;
+    for (int i = threadIdx.x; i < plen; i += NTA) ac[i] += part[i];
 }
 
 __global__ __launch_bounds__(NTD) void k_dec_count(const double *acc, int64_t N, int64_t *cnt)
@@ -194,7 +211,9 @@ hipError_t launch_dec_mul(const double *in, const double *v, double *out, int P,
 
 hipError_t launch_dec_acc(const double *y, double *acc, int P, const DecTables &t, int k, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dec_acc, dim3(P), dim3(NTD), 0, s, y, acc, t, k);
+    const int64_t N = (int64_t)t.n1 * t.n2;
+    const unsigned parts = (unsigned)((N + DEC_LDS - 1) / DEC_LDS);
+    hipLaunchKernelGGL(k_dec_acc, dim3(P, parts), dim3(NTA), 0, s, y, acc, t, k);
     return hipGetLastError();
 }
 

@@ -95,3 +95,22 @@ def test_capacity_and_count_only():
     a, b = _dense(full, 256), _dense(again, 256)
     assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
     assert abs(again.nnz - full.nnz) <= full.nnz // 100
+
+
+def test_two_accumulator_parts_exact_columns():
+    """96 x 256 (N = 24576: two accumulator parts, the second partial), eta = 0:
+    sampled columns of Theta~ equal Psi^* H Psi e_mu from the oracle."""
+    n2, n1, L = 96, 256, 3
+    u, v = _case(n2, n1, 2, 1, 21)
+    cols = _gpu(u, v, L, 0.0)
+    cp, r, val = (t.cpu().numpy() for t in (cols.row_ptr, cols.col, cols.val))
+    N = n1 * n2
+    rng = np.random.default_rng(4)
+    picks = list(rng.choice(N, 12, replace=False)) + [0, 5, n1 * (n2 // 8) + 3, N - 1]
+    for mu in picks:
+        e = np.zeros(N)
+        e[mu] = 1.0
+        ref = O.fwt(PC.apply_pc(u, v, O.ifwt(e.reshape(n2, n1), L, H6)), L, H6).ravel()
+        got = np.zeros(N)
+        got[r[cp[mu]:cp[mu + 1]]] = val[cp[mu]:cp[mu + 1]]
+        assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), mu
