@@ -11,6 +11,7 @@
 #include <utility>
 #include <vector>
 #include <mutex>
+#include <thread>
 
 #include "pd.h"
 #include "pd_internal.h"
@@ -1862,17 +1863,16 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
     for (int b = 0; b < nb; ++b) pos[b] = pos[nb + b] = bands[b].o2 * n1 + bands[b].o1;
     PD_TRY_HIP(hipMemcpyAsync(dpos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, st));
     // multipliers on the host for ||v_k||_inf
-    std::vector<double> hv((size_t)m * N), hg((size_t)2 * nb * N), hu((size_t)m * (2 * R + 1) * (2 * R + 1));
+    std::vector<double> hv((size_t)m * N);
     PD_TRY_HIP(hipMemcpyAsync(hv.data(), op->mult, hv.size() * 8, hipMemcpyDeviceToHost, st));
     pd_shape sc = *sh;
     sc.channels = 2 * nb;
     {
         Ctx<double> c = make_ctx<double>(&sc, wav, ws + Ly.ctx, st, 0);
         if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
-        std::vector<int64_t> off, roff;
-        std::vector<int> cnt, res;
-        std::vector<DecEntry> ent;
-        off.reserve((size_t)m * nb * nb);
+        // generators of every term (probe transforms on the device), then the thresholds and
+        // kept lists of the terms in parallel host threads, merged in term order
+        std::vector<double> hga((size_t)m * 2 * nb * N);
         for (int k = 0; k < m; ++k) {
             const double *uk = (const double *)op->taps + (int64_t)k * (2 * R + 1) * (2 * R + 1);
             PD_TRY_HIP(launch_dec_dirac_at(X, dpos, 2 * nb, N, st));
@@ -1883,16 +1883,24 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
                 return launch_dec_conv(T + (int64_t)nb * N, X + (int64_t)nb * N, nb, uk, R, n1, n2, 1, st);
             }));
             if ((rc = analysis_plain<double>(c, X, G)) != PD_OK) return rc;
-            PD_TRY_HIP(hipMemcpyAsync(hg.data(), G, hg.size() * 8, hipMemcpyDeviceToHost, st));
-            PD_TRY_HIP(hipStreamSynchronize(st));
+            PD_TRY_HIP(hipMemcpyAsync(hga.data() + (size_t)k * 2 * nb * N, G, (size_t)2 * nb * N * 8,
+                                      hipMemcpyDeviceToHost, st));
+        }
+        PD_TRY_HIP(hipStreamSynchronize(st));
+        struct Kept {
+            std::vector<int64_t> off, roff;
+            std::vector<int> cnt, res;
+            std::vector<DecEntry> ent;
+        };
+        std::vector<Kept> kept(m);
+        auto select = [&](int k) {
+            const double *hg = hga.data() + (size_t)k * 2 * nb * N;
             double vinf = 0.0;
             for (int64_t i = 0; i < N; ++i) vinf = std::max(vinf, std::fabs(hv[(size_t)k * N + i]));
-            DecGen gen{bands, hg.data(), hg.data() + (size_t)nb * N, n1, N};
+            DecGen gen{bands, hg, hg + (size_t)nb * N, n1, N};
             double t = 0.0;
-            bool keep_none = false;
-            if (vinf == 0.0) {
-                keep_none = true;  // V_k = 0: the term contributes nothing
-            } else {
+            const bool keep_none = vinf == 0.0;  // V_k = 0: the term contributes nothing
+            if (!keep_none) {
                 const double eps = eta / ((double)m * vinf);
                 const std::vector<double> cand = gen.candidates();
                 int lo = 0, hi = (int)cand.size() - 1;
@@ -1907,13 +1915,14 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
                 }
             }
             // kept generator entries per (source, target) pair; coarser targets grouped by residue
+            Kept &K = kept[k];
             for (int bp = 0; bp < nb; ++bp)
                 for (int b = 0; b < nb; ++b) {
                     const bool by_col = bands[b].lev <= bands[bp].lev;
                     const DecBand &eb = by_col ? bands[b] : bands[bp];
                     const double *g = by_col ? gen.col + (int64_t)bp * N : gen.row + (int64_t)b * N;
-                    off.push_back((int64_t)ent.size());
-                    roff.push_back((int64_t)res.size());
+                    K.off.push_back((int64_t)K.ent.size());
+                    K.roff.push_back((int64_t)K.res.size());
                     const int f = by_col ? 1 : 1 << (bands[b].lev - bands[bp].lev);
                     std::vector<std::vector<DecEntry>> cls((size_t)f * f);
                     if (!keep_none)
@@ -1924,13 +1933,30 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
                             }
                     int run = 0;
                     for (auto &v : cls) {
-                        res.push_back(run);
-                        ent.insert(ent.end(), v.begin(), v.end());
+                        K.res.push_back(run);
+                        K.ent.insert(K.ent.end(), v.begin(), v.end());
                         run += (int)v.size();
                     }
-                    res.push_back(run);
-                    cnt.push_back(run);
+                    K.res.push_back(run);
+                    K.cnt.push_back(run);
                 }
+        };
+        {
+            std::vector<std::thread> pool;
+            for (int k = 1; k < m; ++k) pool.emplace_back(select, k);
+            select(0);
+            for (auto &th : pool) th.join();
+        }
+        std::vector<int64_t> off, roff;
+        std::vector<int> cnt, res;
+        std::vector<DecEntry> ent;
+        for (int k = 0; k < m; ++k) {
+            const int64_t eb = (int64_t)ent.size(), rb = (int64_t)res.size();
+            for (int64_t o : kept[k].off) off.push_back(eb + o);
+            for (int64_t o : kept[k].roff) roff.push_back(rb + o);
+            cnt.insert(cnt.end(), kept[k].cnt.begin(), kept[k].cnt.end());
+            res.insert(res.end(), kept[k].res.begin(), kept[k].res.end());
+            ent.insert(ent.end(), kept[k].ent.begin(), kept[k].ent.end());
         }
         // the tables, in the workspace (sized for the worst case)
         if (res.size() * 4 > Ly.ent - Ly.res || ent.size() * sizeof(DecEntry) > Ly.total - Ly.ent) return PD_ERR_HIP;
