@@ -173,3 +173,20 @@ def test_admm_rejects_non_pc_operator():
     op = P.Operator.pc(u, v)
     with pytest.raises(C.PDError):
         P.pd_admm_solve(f0, op, H6, 3, -1.0, 3, level_w=np.zeros(4))
+
+
+@pytest.mark.parametrize("n2,n1,L", [(4, 16, 1), (16, 4, 2), (8, 32, 3)])
+def test_admm_single_term_small_and_flat_images(n2, n1, L):
+    """m = 1 on images with a side below 8 points (the short-line FFT path) and a
+    flat 8 x 32 image, FP64 against the oracle."""
+    rng = np.random.default_rng(n1 * 7 + n2)
+    u = rng.standard_normal((1, 3, 3)) * 0.1
+    u[0, 1, 1] += 1.0
+    v = 1.0 + 0.2 * rng.random((1, n2, n1))
+    f0 = rng.random((n2, n1))
+    w = np.full((n2, n1), 0.05)
+    ref = AD.admm_pc(u, v, H6, L, f0, w, 0.8, 20)
+    op = P.Operator.pc(u, v, dtype=torch.float64)
+    out = P.pd_admm_solve(_t(f0[None], torch.float64), op, H6, L, 0.8, 20, coeff_w=_t(w, torch.float64))
+    assert np.abs(_np(out["f"])[0] - ref["f"]).max() < 1e-10
+    assert np.abs(_np(out["z"])[0] - ref["z"]).max() < 1e-10

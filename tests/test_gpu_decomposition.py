@@ -114,3 +114,12 @@ def test_two_accumulator_parts_exact_columns():
         got = np.zeros(N)
         got[r[cp[mu]:cp[mu + 1]]] = val[cp[mu]:cp[mu + 1]]
         assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()), mu
+
+
+def test_single_level_flat_image():
+    """levels = 1 on a flat 8 x 32 image (four bands), eta 0 and 0.05."""
+    u, v = _case(8, 32, 2, 2, 31)
+    for eta in (0.0, 0.05):
+        ref = D.decompose(u, v, 1, H6, eta)["theta"]
+        got = _dense(_gpu(u, v, 1, eta), 8 * 32)
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
