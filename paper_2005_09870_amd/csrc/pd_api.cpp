@@ -1856,14 +1856,30 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
     double *ACC = (double *)(ws + Ly.ACC), *G = (double *)(ws + Ly.G);
     int *dpos = (int *)(ws + Ly.pos);
     int64_t *dcnt = (int64_t *)(ws + Ly.cnt), *dbase = (int64_t *)(ws + Ly.base);
-    const std::vector<DecBand> bands = dec_bands(n1, n2, L);
+    // host buffers that asynchronous copies read or write, and a join that runs before they are
+    // destroyed on every return path (declared after them, so destroyed first)
+    struct DecHost {
+        std::vector<DecBand> bands;
+        std::vector<int> pos, cnt, res;
+        std::vector<double> hv, hga;
+        std::vector<int64_t> off, roff, hc, hbase, cp;
+        std::vector<DecEntry> ent;
+    } H;
+    struct StreamJoin {
+        hipStream_t s;
+        ~StreamJoin() { (void)hipStreamSynchronize(s); }
+    } join{st};
+    H.bands = dec_bands(n1, n2, L);
+    const std::vector<DecBand> &bands = H.bands;
     PD_TRY_HIP(hipMemcpyAsync(ws + Ly.bands, bands.data(), nb * sizeof(DecBand), hipMemcpyHostToDevice, st));
     // probes: a Dirac at every band origin (columns, then rows)
-    std::vector<int> pos(2 * nb);
+    H.pos.assign(2 * nb, 0);
+    std::vector<int> &pos = H.pos;
     for (int b = 0; b < nb; ++b) pos[b] = pos[nb + b] = bands[b].o2 * n1 + bands[b].o1;
     PD_TRY_HIP(hipMemcpyAsync(dpos, pos.data(), pos.size() * 4, hipMemcpyHostToDevice, st));
     // multipliers on the host for ||v_k||_inf
-    std::vector<double> hv((size_t)m * N);
+    H.hv.assign((size_t)m * N, 0.0);
+    std::vector<double> &hv = H.hv;
     PD_TRY_HIP(hipMemcpyAsync(hv.data(), op->mult, hv.size() * 8, hipMemcpyDeviceToHost, st));
     pd_shape sc = *sh;
     sc.channels = 2 * nb;
@@ -1872,7 +1888,8 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
         if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
         // generators of every term (probe transforms on the device), then the thresholds and
         // kept lists of the terms in parallel host threads, merged in term order
-        std::vector<double> hga((size_t)m * 2 * nb * N);
+        H.hga.assign((size_t)m * 2 * nb * N, 0.0);
+        std::vector<double> &hga = H.hga;
         for (int k = 0; k < m; ++k) {
             const double *uk = (const double *)op->taps + (int64_t)k * (2 * R + 1) * (2 * R + 1);
             PD_TRY_HIP(launch_dec_dirac_at(X, dpos, 2 * nb, N, st));
@@ -1947,9 +1964,9 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
             select(0);
             for (auto &th : pool) th.join();
         }
-        std::vector<int64_t> off, roff;
-        std::vector<int> cnt, res;
-        std::vector<DecEntry> ent;
+        std::vector<int64_t> &off = H.off, &roff = H.roff;
+        std::vector<int> &cnt = H.cnt, &res = H.res;
+        std::vector<DecEntry> &ent = H.ent;
         for (int k = 0; k < m; ++k) {
             const int64_t eb = (int64_t)ent.size(), rb = (int64_t)res.size();
             for (int64_t o : kept[k].off) off.push_back(eb + o);
@@ -1982,7 +1999,10 @@ int decompose_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *
             sb.channels = P;
             Ctx<double> cb = make_ctx<double>(&sb, wav, ws + Ly.ctx, st, 0);
             if (cb.ts.nt > 0 && !cb.tail) return PD_ERR_HIP;
-            std::vector<int64_t> hc(P), hbase(P), cp((size_t)N + 1, 0);
+            H.hc.assign(P, 0);
+            H.hbase.assign(P, 0);
+            H.cp.assign((size_t)N + 1, 0);
+            std::vector<int64_t> &hc = H.hc, &hbase = H.hbase, &cp = H.cp;
             int64_t total = 0;
             for (int64_t j0 = 0; j0 < N; j0 += P) {
                 const int np = (int)std::min<int64_t>(P, N - j0);
