@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NTF) void k_fft_cols(Cx<T> *data, int n1, int n2, i
 // stage reads the line from global memory and the last one writes it back
 // (both at positions g + t n/8, so a line's loads and stores are contiguous);
 // the stages in between exchange through one LDS tile, in place (all reads of
-// a stage, barrier, all writes, barrier).  The inverse conjugates on load and
+// a stage, barrier, all writes, barrier), padded by one point in every 8.  The inverse conjugates on load and
 // store.
 
 template <typename T>
@@ -209,9 +209,13 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(Cx<T> *data, int n, i
     int bx = blockIdx.x;
     if (!ROWS && (gridDim.x & 7) == 0) bx = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
     const int line0 = bx * C;
+    // tile index of point e of line l: one pad element every 8 points, so that the stride-8
+    // writes of a radix-8 stage do not fall on the same banks
+    const int np = n + (n >> 3);
+    auto lidx = [&](int l, int e) { return ROWS ? l * np + e + (e >> 3) : (e + (e >> 3)) * C + l; };
     const Cx<T> *twp = tw;
     if (FFT_TW_LDS && nst > 1) {  // read first in stage 1, after its barrier
-        Cx<T> *TW = S + C * n;
+        Cx<T> *TW = S + C * np;
         for (int i = threadIdx.x; i < (n >> 1); i += nthr) TW[i] = tw[i];
         twp = TW;
     }
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(Cx<T> *data, int n, i
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     const int e = gg[b] + t * n8;
-                    v[b][t] = S[ROWS ? gl[b] * n + e : e * C + gl[b]];
+                    v[b][t] = S[lidx(gl[b], e)];
                 }
             __syncthreads();
         }
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_lines(Cx<T> *data, int n, i
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     const int e = pos[b][t];
-                    S[ROWS ? gl[b] * n + e : e * C + gl[b]] = v[b][t];
+                    S[lidx(gl[b], e)] = v[b][t];
                 }
         }
     }
@@ -588,7 +592,7 @@ hipError_t launch_lines(Cx<T> *data, int n, int n1, int64_t plane, int lines, in
     const int bg = groups / nthr;
     // the kernel's indexing assumes C | lines, whole groups per thread and at most 4 of them
     if (C < 1 || lines % C || groups % nthr || (bg != 1 && bg != 2 && bg != 4)) return hipErrorInvalidValue;
-    const size_t lds = nst > 1 ? ((size_t)C * n + (FFT_TW_LDS ? n / 2 : 0)) * sizeof(Cx<T>) : 0;
+    const size_t lds = nst > 1 ? ((size_t)C * (n + n / 8) + (FFT_TW_LDS ? n / 2 : 0)) * sizeof(Cx<T>) : 0;
     const dim3 grid(lines / C, batch);
     if (bg == 1)
         hipLaunchKernelGGL((k_fft_lines<T, ROWS, 1>), grid, dim3(nthr), lds, s, data, n, n1, plane, C, tw, first, nst,
@@ -613,9 +617,9 @@ hipError_t launch_fft_pass(Cx<T> *data, int n1, int n2, int batch, const Cx<T> *
     if (n >= 8) {
         // tiles within 64 KiB of LDS and at most 4 groups of 8 points per thread; columns: at
         // most FFT_COL_TILE per tile so that a wide image still gives many workgroups
-        const int cap = (int)(65536 / sizeof(Cx<T>)) - (FFT_TW_LDS ? n / 2 : 0);
+        const int cap = (int)(65536 / sizeof(Cx<T>)) - (FFT_TW_LDS ? n / 2 : 0);  // padded tile points
         int C = (cols ? 32 * FFT_THREADS : FFT_ROW_POINTS) / n;
-        if (C * n > cap) C = cap / n;
+        if (C * (n + n / 8) > cap) C = cap / (n + n / 8);
         if (C * n > 32 * FFT_THREADS) C = 32 * FFT_THREADS / n;
         if (cols && C > FFT_COL_TILE) C = FFT_COL_TILE;
         if (C > lines) C = lines;
