@@ -358,26 +358,52 @@ __global__ __launch_bounds__(NTF) void k_admm_a(AdmmArgs<T> a)
     }
 }
 
-template <typename T>
+// M > 0: the term count as a compile-time constant (m <= 8), so that every term's operands are
+// loaded before the first use; M == 0: any m, one term at a time.
+template <typename T, int M>
 __global__ __launch_bounds__(NTF) void k_admm_accq(AdmmArgs<T> a)
 {
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
     if (i >= a.N) return;
     Cx<T> t{T(0), T(0)};
-    for (int k = 0; k < a.m; ++k) {
-        const int64_t o = (int64_t)k * a.N + i;
-        const Cx<T> p = cmul(a.uh[o], a.cb[o]);
-        t.re += p.re;
-        t.im += p.im;
-    }
-    const T im = T(1) / a.mh[i];
-    t.re *= im;
-    t.im *= im;
-    for (int k = 0; k < a.m; ++k) {
-        const int64_t o = (int64_t)k * a.N + i;
-        Cx<T> u = a.uh[o];
-        u.im = -u.im;
-        a.cb[o] = cmul(u, t);
+    if constexpr (M > 0) {
+        Cx<T> u[M], c[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            u[k] = a.uh[(int64_t)k * a.N + i];
+            c[k] = a.cb[(int64_t)k * a.N + i];
+        }
+        const T im = T(1) / a.mh[i];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const Cx<T> p = cmul(u[k], c[k]);
+            t.re += p.re;
+            t.im += p.im;
+        }
+        t.re *= im;
+        t.im *= im;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            Cx<T> w = u[k];
+            w.im = -w.im;
+            a.cb[(int64_t)k * a.N + i] = cmul(w, t);
+        }
+    } else {
+        for (int k = 0; k < a.m; ++k) {
+            const int64_t o = (int64_t)k * a.N + i;
+            const Cx<T> p = cmul(a.uh[o], a.cb[o]);
+            t.re += p.re;
+            t.im += p.im;
+        }
+        const T im = T(1) / a.mh[i];
+        t.re *= im;
+        t.im *= im;
+        for (int k = 0; k < a.m; ++k) {
+            const int64_t o = (int64_t)k * a.N + i;
+            Cx<T> u = a.uh[o];
+            u.im = -u.im;
+            a.cb[o] = cmul(u, t);
+        }
     }
 }
 
@@ -400,35 +426,74 @@ __global__ __launch_bounds__(NTF) void k_admm_z(AdmmArgs<T> a)
     if (a.slots) slots_add2(st, a.slots + 2 * PD_NSLOT, 0.0, nullptr);
 }
 
-template <typename T>
+template <typename T, int M>
 __global__ __launch_bounds__(NTF) void k_admm_f(AdmmArgs<T> a, int next)
 {
     const int64_t i = (int64_t)blockIdx.x * NTF + threadIdx.x;
     double st = 0.0;
     if (i < a.N) {
-        // g-step completion and f-step
-        T acc = a.tfs[i];
-        for (int k = 0; k < a.m; ++k) {
-            const int64_t o = (int64_t)k * a.N + i;
-            const T bg = a.beta1 * a.gam[k];
-            const T gk = a.g[o] - a.cb[o].re / bg;
-            acc += a.v[o] * (a.xi[o] + bg * gk);
-        }
-        const T f = acc / a.den[i];
-        a.f[i] = f;
-        // multiplier step, then the next iteration's a_k
-        for (int k = 0; k < a.m; ++k) {
-            const int64_t o = (int64_t)k * a.N + i;
-            const T bg = a.beta1 * a.gam[k];
-            const T vk = a.v[o];
-            const T r = a.g[o] - a.cb[o].re / bg - vk * f;
-            const T xk = a.xi[o] + bg * r;
-            a.xi[o] = xk;
-            st += (double)a.gam[k] * (double)r * (double)r;
-            if (next) {
-                const T ak = (a.utf0[o] - xk) / bg + vk * f;
-                a.g[o] = ak;
-                a.cb[o] = Cx<T>{ak, T(0)};
+        if constexpr (M > 0) {
+            T ak[M], cr[M], xk[M], vk[M], uf[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = (int64_t)k * a.N + i;
+                ak[k] = a.g[o];
+                cr[k] = a.cb[o].re;
+                xk[k] = a.xi[o];
+                vk[k] = a.v[o];
+                uf[k] = a.utf0[o];
+            }
+            // g-step completion and f-step
+            T gk[M];
+            T acc = a.tfs[i];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const T bg = a.beta1 * a.gam[k];
+                gk[k] = ak[k] - cr[k] / bg;
+                acc += vk[k] * (xk[k] + bg * gk[k]);
+            }
+            const T f = acc / a.den[i];
+            a.f[i] = f;
+            // multiplier step, then the next iteration's a_k
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = (int64_t)k * a.N + i;
+                const T bg = a.beta1 * a.gam[k];
+                const T r = gk[k] - vk[k] * f;
+                const T x = xk[k] + bg * r;
+                a.xi[o] = x;
+                st += (double)a.gam[k] * (double)r * (double)r;
+                if (next) {
+                    const T an = (uf[k] - x) / bg + vk[k] * f;
+                    a.g[o] = an;
+                    a.cb[o] = Cx<T>{an, T(0)};
+                }
+            }
+        } else {
+            // g-step completion and f-step
+            T acc = a.tfs[i];
+            for (int k = 0; k < a.m; ++k) {
+                const int64_t o = (int64_t)k * a.N + i;
+                const T bg = a.beta1 * a.gam[k];
+                const T gk = a.g[o] - a.cb[o].re / bg;
+                acc += a.v[o] * (a.xi[o] + bg * gk);
+            }
+            const T f = acc / a.den[i];
+            a.f[i] = f;
+            // multiplier step, then the next iteration's a_k
+            for (int k = 0; k < a.m; ++k) {
+                const int64_t o = (int64_t)k * a.N + i;
+                const T bg = a.beta1 * a.gam[k];
+                const T vk = a.v[o];
+                const T r = a.g[o] - a.cb[o].re / bg - vk * f;
+                const T xk = a.xi[o] + bg * r;
+                a.xi[o] = xk;
+                st += (double)a.gam[k] * (double)r * (double)r;
+                if (next) {
+                    const T ak = (a.utf0[o] - xk) / bg + vk * f;
+                    a.g[o] = ak;
+                    a.cb[o] = Cx<T>{ak, T(0)};
+                }
             }
         }
     }
@@ -660,7 +725,18 @@ hipError_t launch_admm_a(const AdmmArgs<T> &a, hipStream_t s)
 template <typename T>
 hipError_t launch_admm_accq(const AdmmArgs<T> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_accq<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a);
+    const dim3 g(nblk(a.N)), b(NTF);
+    switch (a.m) {
+    case 1: hipLaunchKernelGGL((k_admm_accq<T, 1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_admm_accq<T, 2>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_admm_accq<T, 3>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_admm_accq<T, 4>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_admm_accq<T, 5>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_admm_accq<T, 6>), g, b, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_admm_accq<T, 7>), g, b, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_admm_accq<T, 8>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_admm_accq<T, 0>), g, b, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 template <typename T>
@@ -672,7 +748,18 @@ hipError_t launch_admm_z(const AdmmArgs<T> &a, hipStream_t s)
 template <typename T>
 hipError_t launch_admm_f(const AdmmArgs<T> &a, int next, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_admm_f<T>, dim3(nblk(a.N)), dim3(NTF), 0, s, a, next);
+    const dim3 g(nblk(a.N)), b(NTF);
+    switch (a.m) {
+    case 1: hipLaunchKernelGGL((k_admm_f<T, 1>), g, b, 0, s, a, next); break;
+    case 2: hipLaunchKernelGGL((k_admm_f<T, 2>), g, b, 0, s, a, next); break;
+    case 3: hipLaunchKernelGGL((k_admm_f<T, 3>), g, b, 0, s, a, next); break;
+    case 4: hipLaunchKernelGGL((k_admm_f<T, 4>), g, b, 0, s, a, next); break;
+    case 5: hipLaunchKernelGGL((k_admm_f<T, 5>), g, b, 0, s, a, next); break;
+    case 6: hipLaunchKernelGGL((k_admm_f<T, 6>), g, b, 0, s, a, next); break;
+    case 7: hipLaunchKernelGGL((k_admm_f<T, 7>), g, b, 0, s, a, next); break;
+    case 8: hipLaunchKernelGGL((k_admm_f<T, 8>), g, b, 0, s, a, next); break;
+    default: hipLaunchKernelGGL((k_admm_f<T, 0>), g, b, 0, s, a, next); break;
+    }
     return hipGetLastError();
 }
 template <typename T>

@@ -190,3 +190,18 @@ def test_admm_single_term_small_and_flat_images(n2, n1, L):
     out = P.pd_admm_solve(_t(f0[None], torch.float64), op, H6, L, 0.8, 20, coeff_w=_t(w, torch.float64))
     assert np.abs(_np(out["f"])[0] - ref["f"]).max() < 1e-10
     assert np.abs(_np(out["z"])[0] - ref["z"]).max() < 1e-10
+
+
+def test_admm_many_terms_generic_path():
+    """m = 10 (beyond the unrolled term counts), 16 x 16, FP64 against the oracle."""
+    n, m = 16, 10
+    rng = np.random.default_rng(10)
+    u = rng.standard_normal((m, 3, 3)) * 0.05
+    u[:, 1, 1] += 1.0 / m
+    v = 1.0 + 0.2 * rng.random((m, n, n))
+    f0 = rng.random((n, n))
+    w = np.full((n, n), 0.03)
+    ref = AD.admm_pc(u, v, H6, 2, f0, w, 1.0, 15)
+    op = P.Operator.pc(u, v, dtype=torch.float64)
+    out = P.pd_admm_solve(_t(f0[None], torch.float64), op, H6, 2, 1.0, 15, coeff_w=_t(w, torch.float64))
+    assert np.abs(_np(out["f"])[0] - ref["f"]).max() < 1e-10
