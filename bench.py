@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 FMA without packed instructions (which this build does not emit): 256 CU x 4 SIMD x 16 lanes
+# FP32 FMA without packed instructions (which libpd does not emit): 256 CU x 4 SIMD x 16 lanes
 # x 2 FLOP x 2.4 GHz
 FP32_PEAK_TFLOPS = 78.6
 

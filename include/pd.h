@@ -57,7 +57,7 @@ typedef enum {
     PD_ERR_TAU = -4,         /* step size <= 0 or not finite                    */
     PD_ERR_NONFINITE = -5,   /* a prox argument was NaN/Inf (check_finite only) */
     PD_ERR_HIP = -6,         /* a HIP runtime call failed                       */
-    PD_ERR_UNSUPPORTED = -7  /* valid request outside what this build supports  */
+    PD_ERR_UNSUPPORTED = -7  /* valid request outside what libpd supports       */
 } pd_status;
 
 typedef enum { PD_F32 = 0, PD_F64 = 1 } pd_dtype;
