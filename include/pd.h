@@ -328,7 +328,7 @@ size_t pd_admm_workspace_size(const pd_shape *shape, int32_t dtype, int32_t term
 /* Run `iters` ADMM-PC iterations on each channel (the same operator).
  *   shape   n1 x n2 x channels, levels; n1 and n2 powers of two in [2, 4096]
  *           (FP32) or [2, 2048] (FP64), else PD_ERR_UNSUPPORTED.
- *   op      kind PD_OP_PC (taps [m][2R+1][2R+1], mult [m][n2][n1] device).
+ *   op      kind PD_OP_PC (taps [m][2R+1][2R+1], mult [m][n2][n1], device, in the dtype).
  *   w       level_w (host) or coeff_w (device [n2][n1], every channel);
  *           joint must be 0.
  *   beta    beta1 = beta2 > 0 (finite).
