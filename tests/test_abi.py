@@ -232,3 +232,18 @@ def test_decompose_argument_errors_without_gpu_work():
     assert L.pd_decompose_workspace_size(ctypes.byref(ok), 3) > need
     assert L.pd_decompose_workspace_size(ctypes.byref(ok), 0) == 0
     assert call(ok, ws_bytes=need - 1) == C.PD_ERR_WORKSPACE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N > 1 exits with a message (the solver runs on one GPU),
+    before importing torch or touching a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
