@@ -222,10 +222,13 @@ void host_analysis(std::vector<double> &x, int M1, int M2, int nt, const Filt<do
 // [2][tn][tn]: the tail's analysis matrix (row i = output i) and its transpose.
 // Cached per (shape, filter, dtype); the cache keeps the host copy alive for
 // asynchronous uploads.
+std::mutex g_tail_mu;
+
 template <typename T>
 const std::vector<T> &tail_matrices(const TailShape &ts, const pd_wavelet *wav)
 {
-    static std::map<std::vector<double>, std::vector<T>> cache;
+    static std::map<std::vector<double>, std::vector<T>> cache;  // entries are never erased
+    std::lock_guard<std::mutex> lk(g_tail_mu);
     std::vector<double> key{(double)ts.tM1, (double)ts.tM2, (double)ts.nt};
     for (int k = 0; k < wav->len; ++k) key.push_back(wav->h[k]);
     auto it = cache.find(key);
@@ -530,10 +533,11 @@ hipStream_t capture_stream(int dev)
 
 // Returns the executable graph for the chunk starting at local index it_a
 // (and the event to record after launching it), capturing it if allowed.
+// The caller holds g_graph_mu.
 template <typename T>
-hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc,
-                           T *zp, int it_a, int count, double *stats, int i_first, bool may_capture,
-                           hipEvent_t *done)
+hipGraphExec_t chunk_graph_locked(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0,
+                                  T *zc, T *zp, int it_a, int count, double *stats, int i_first, bool may_capture,
+                                  hipEvent_t *done)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
@@ -559,7 +563,6 @@ hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weig
     key_put(key, zp);
     key_put(key, stats);
     key_put(key, i_first);
-    std::lock_guard<std::mutex> lock(g_graph_mu);
     sweep_retired();
     for (size_t k = 0; k < g_graph_cache.size(); ++k)
         if (g_graph_cache[k].key == key) {
@@ -608,6 +611,30 @@ hipGraphExec_t chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weig
     return ex;
 }
 
+// Launches the executable graph of the chunk starting at local index it_a on
+// the caller's stream (capturing it first if allowed): stores the chunk's first
+// iteration number, replays the graph and records its completion event, all
+// under the cache lock, so that no other thread can retire and destroy the
+// graph between the lookup and the event record.  Returns false when there is
+// no graph (the caller runs the chunk eagerly) and sets *err on a HIP error.
+template <typename T>
+bool launch_chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc,
+                        T *zp, int it_a, int count, double *stats, int i_first, bool may_capture, int *err)
+{
+    hipEvent_t done = nullptr;
+    hipGraphExec_t ex = nullptr;
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    ex = chunk_graph_locked<T>(c, op, w, tau, f0, zc, zp, it_a, count, stats, i_first, may_capture, &done);
+    if (!ex) return false;
+    hipError_t e;
+    if ((e = launch_set_int(c.it_dev(), i_first + it_a, c.st)) != hipSuccess ||
+        (e = hipGraphLaunch(ex, c.st)) != hipSuccess || (e = hipEventRecord(done, c.st)) != hipSuccess) {
+        (void)e;
+        *err = PD_ERR_HIP;
+    }
+    return true;
+}
+
 // Iterations i = i_first .. i_first+count-1 of the recursion from the state
 // (zc, zp) = (z(i_first-1), z(i_first-2)); on return the pointers hold
 // (z(last), z(last-1)).  z(i) is written in place of z(i-2).  stats (nullable)
@@ -628,13 +655,9 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
     const bool may_capture = chunks >= 4;
     for (int it = 0; it < count;) {
         if (graphs && it % PD_RING == 1 && it + PD_RING < count) {
-            hipEvent_t done = nullptr;
-            hipGraphExec_t ex =
-                chunk_graph<T>(c, op, w, tau, f0, zc, zp, it, count, stats, i_first, may_capture, &done);
-            if (ex) {
-                PD_TRY_HIP(launch_set_int(c.it_dev(), i_first + it, st));
-                PD_TRY_HIP(hipGraphLaunch(ex, st));
-                PD_TRY_HIP(hipEventRecord(done, st));
+            int err = PD_OK;
+            if (launch_chunk_graph<T>(c, op, w, tau, f0, zc, zp, it, count, stats, i_first, may_capture, &err)) {
+                if (err != PD_OK) return err;
                 it += PD_RING;  // an even number of swaps: (zc, zp) unchanged
                 continue;
             }
@@ -675,8 +698,9 @@ int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav,
                const pd_params *prm, const T *f0, T *z_cur, T *z_prev, int init, T *f_out,
                double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
 {
+    // size check before make_ctx, which queues the tail-matrix upload into the workspace
+    if (ws_bytes < layout(sh, sizeof(T)).total) return PD_ERR_WORKSPACE;
     Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, w->joint);
-    if (ws_bytes < c.lay.total) return PD_ERR_WORKSPACE;
     const int64_t NC = c.N() * sh->channels;
     int rc;
     if (init) {
@@ -1180,8 +1204,8 @@ extern "C" int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wa
     hipStream_t st = (hipStream_t)stream;
     auto run = [&](auto tag) -> int {
         using T = decltype(tag);
+        if (ws_bytes < layout(shape, sizeof(T)).total) return PD_ERR_WORKSPACE;
         Ctx<T> c = make_ctx<T>(shape, wav, workspace, st, 0);
-        if (ws_bytes < c.lay.total) return PD_ERR_WORKSPACE;
         if (inverse) return synth_chain<T>(c, (const T *)in, (const T *)in, T(0), (T *)out);
         return analysis_plain<T>(c, (const T *)in, (T *)out);
     };
@@ -1469,31 +1493,44 @@ AdmmLayout admm_layout(const pd_shape *sh, size_t es, int m)
     return l;
 }
 
-// A second, library-owned stream per device (default priority) with two events, for work that
-// runs beside the caller's stream inside one call and is joined before the call returns.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t ready = nullptr, done = nullptr;
-};
+// A second, library-owned stream per device (default priority), for work that runs beside the
+// caller's stream inside one call.  Each call orders its work with events of its own (concurrent
+// calls never record each other's events) and joins the side stream back into the caller's stream
+// on every return path.
 std::mutex g_side_mu;
 
-bool side_stream(SideStream &out)
+hipStream_t side_stream()
 {
-    static std::map<int, SideStream> side;
+    static std::map<int, hipStream_t> side;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(g_side_mu);
     auto it = side.find(dev);
     if (it == side.end()) {
-        SideStream ss;
-        if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) return false;
-        if (hipEventCreateWithFlags(&ss.ready, hipEventDisableTiming) != hipSuccess) return false;
-        if (hipEventCreateWithFlags(&ss.done, hipEventDisableTiming) != hipSuccess) return false;
-        it = side.emplace(dev, ss).first;
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        it = side.emplace(dev, s).first;
     }
-    out = it->second;
-    return true;
+    return it->second;
 }
+
+struct SideCall {
+    hipStream_t s = nullptr, st = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    bool open(hipStream_t caller)
+    {
+        st = caller;
+        s = side_stream();
+        return s && hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess;
+    }
+    ~SideCall()
+    {
+        if (s && done && hipEventRecord(done, s) == hipSuccess) (void)hipStreamWaitEvent(st, done, 0);
+        if (ready) (void)hipEventDestroy(ready);
+        if (done) (void)hipEventDestroy(done);
+    }
+};
 
 template <typename T>
 int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w, double beta,
@@ -1509,8 +1546,8 @@ int admm_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, 
     s1.channels = 1;
     Ctx<T> c = make_ctx<T>(&s1, wav, workspace, st, 0);
     if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
-    SideStream side;
-    if (!side_stream(side)) return PD_ERR_HIP;
+    SideCall side;
+    if (!side.open(st)) return PD_ERR_HIP;
     Ctx<T> c2 = c;  // the same transforms and scratch, launched on the side stream
     c2.st = side.s;
     AdmmArgs<T> a{};

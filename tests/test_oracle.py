@@ -382,3 +382,104 @@ def test_reverse_mode_matches_finite_differences():
         fd = (loss(f0, w + eps * d) - loss(f0, w - eps * d)) / (2 * eps)
         an = float(np.sum(wb * d))
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), ("w", t, fd, an)
+
+
+# ------------------------------------------------ colour extension, bands ----
+def _joint_problem(g):
+    w = np.broadcast_to(np.array(g["weights"]), (3, 2, 2))
+    return O.Problem(2, 2, 3, levels=1, h=HAAR, op="identity", w=w, joint=True)
+
+
+def test_joint_prox_hand(golden_dir):
+    """Group soft-thresholding of the channel vector (the colour extension of
+    the Appendix A.1 prox): hand values of tests/golden/joint_prox_hand.json,
+    including the tie ||v|| = tau w and v = 0, reached as the first FISTA
+    iterate with H = Id and tau = 1."""
+    g = json.load(open(os.path.join(golden_dir, "joint_prox_hand.json")))
+    c = np.array(g["coeffs"])
+    f0 = O.ifwt(c, 1, HAAR)
+    out = O.fista(_joint_problem(g), f0, tau=1.0, iters=1)
+    np.testing.assert_allclose(out["z"], np.array(g["z1"]), atol=1e-14)
+    # tau scales the threshold: tau = 1/2 halves it at (0,0): 1 - 1.25/5 = 3/4
+    half = O.fista(_joint_problem(g), f0, tau=0.5, iters=1)
+    np.testing.assert_allclose(half["z"][:, 0, 0], [2.25, 3.0, 0.0], atol=1e-14)
+
+
+def test_joint_penalty_hand(golden_dir):
+    """Penalty of eq. 4.1 in the colour extension, sum w ||z||_2 over the
+    channel vectors (hand values), via the energy and via the FISTA log, whose
+    second term is the penalty at y(1) = Psi^* f0."""
+    g = json.load(open(os.path.join(golden_dir, "joint_prox_hand.json")))
+    pb = _joint_problem(g)
+    c = np.array(g["coeffs"])
+    f0 = O.ifwt(c, 1, HAAR)
+    _, terms = O.energy(pb, f0, np.array(g["z1"]))
+    assert abs(terms[1] - g["penalty_at_z1"]) < 1e-13
+    _, terms = O.energy(pb, f0, c)
+    assert abs(terms[1] - g["penalty_at_coeffs"]) < 1e-13
+    assert abs(terms[0]) < 1e-25  # H = Id and f = f0: no data misfit
+    lg = O.fista(pb, f0, tau=1.0, iters=1, log=True)["log"]
+    assert abs(lg[0, 1] - g["penalty_at_coeffs"]) < 1e-12
+
+
+def test_band_map_hand(golden_dir):
+    """Band index of every Mallat position and the Fig. 5 weights
+    w = 2e-2 |lambda| (hand-drawn maps, tests/golden/band_map_hand.json)."""
+    g = json.load(open(os.path.join(golden_dir, "band_map_hand.json")))
+    for case in g["cases"]:
+        n1, n2, L = case["n1"], case["n2"], case["levels"]
+        np.testing.assert_array_equal(O.band_of(n1, n2, L), np.array(case["band"]))
+        np.testing.assert_allclose(O.paper_level_weights(L), case["paper_weights"], atol=1e-17)
+        w = O.expand_level_weights(O.paper_level_weights(L), n1, n2, L, C=2)
+        np.testing.assert_allclose(w, np.broadcast_to(np.array(case["paper_weights"])[np.array(case["band"])],
+                                                      (2, n2, n1)), atol=1e-17)
+
+
+def _circular_extent(mask):
+    """Length of the shortest circular interval that holds every True entry."""
+    idx = np.nonzero(mask)[0]
+    n = len(mask)
+    gaps = np.diff(np.concatenate([idx, idx[:1] + n]))
+    return n - int(gaps.max()) + 1
+
+
+def test_band_index_is_the_scale():
+    """Section 2.1: supp psi_{j,0} and supp phi_{j,0} span (2^(J-j) - 1)(2 delta - 1) + 1
+    samples.  The synthesis of a unit coefficient of band k (Symmlet-6,
+    delta = 6, 64 x 64, J = 6) spans exactly that many rows and columns with
+    j = k - 1, which fixes the band order of the weights (finest band = largest
+    j = largest weight)."""
+    n, J = 64, 6
+    band = O.band_of(n, n, J)
+    for lev in (1, 2):  # levels whose support does not wrap around the torus
+        h2 = n >> lev
+        for (r, c) in ((0, h2), (h2, 0), (h2, h2)):  # one coefficient of each orientation
+            k = int(band[r + 1, c + 1])
+            j = k - 1
+            e = np.zeros((n, n))
+            e[r + 1, c + 1] = 1.0
+            x = O.ifwt(e, J, H6)
+            nz = np.abs(x) > 1e-14
+            span = (2 ** (J - j) - 1) * (2 * 6 - 1) + 1
+            assert _circular_extent(nz.any(0)) == span, (lev, r, c, k)
+            assert _circular_extent(nz.any(1)) == span, (lev, r, c, k)
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_step_size_is_the_spectral_bound(n):
+    """Appendix A.1 asks tau <= ||H||^-2: the oracle's power iteration gives
+    ||H^T H|| to 1e-12 of the largest eigenvalue of the dense H^T H
+    (numpy.linalg.eigvalsh on Operator 1 built column by column), and its
+    step satisfies the bound."""
+    pb = O.Problem(n, n, 1)
+    N = n * n
+    H = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros((n, n))
+        e.flat[j] = 1.0
+        H[:, j] = O.apply_H(pb, e).ravel()
+    lam = np.linalg.eigvalsh(H.T @ H)[-1]
+    assert abs(O.lipschitz(pb) - lam) <= 1e-12 * lam
+    tau = O.step_size(pb)
+    assert tau * lam <= 1.0 and tau * lam > 1.0 - 1e-5
+    assert O.step_size(O.Problem(n, n, 1, op="identity")) * 1.0 <= 1.0
