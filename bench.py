@@ -135,9 +135,10 @@ def kernel_table(torch, P, step):
     return rows
 
 
-def cpu_baseline(SI, seconds_target=15.0):
-    """The oracle (plain FP64 C, OpenMP over rows) on the same 512^2 workload,
-    for a bounded number of iterations."""
+def cpu_baseline(SI, tau, seconds_target=15.0):
+    """The oracle (plain FP64 C, OpenMP over rows) on the same 512^2 workload
+    with the GPU step's tau, for a bounded number of iterations (the full 2000
+    would take about two minutes of host time)."""
     import numpy as np
     from oracle import oracle as O
     case = SI.case_512()
@@ -145,7 +146,6 @@ def cpu_baseline(SI, seconds_target=15.0):
     pb = O.Problem(n, n, 1, case.levels, h=O.symmlet(6),
                    w=O.expand_level_weights(case.level_w, n, n, case.levels))
     f0 = O.apply_H(pb, case.clean) + case.noise
-    tau = 0.89
     t = time.perf_counter()
     O.fista(pb, f0, tau, 2)
     per_it = (time.perf_counter() - t) / 2
@@ -165,9 +165,22 @@ def cpu_baseline(SI, seconds_target=15.0):
                       f"{dt:.1f} s"}
 
 
+def coarse_first_level(n1: int, n2: int, levels: int) -> int:
+    """First level the single-workgroup coarse kernel takes (FP32): the first l
+    whose input approximation is at most 64 x 64; levels + 1 if none."""
+    for lc in range(1, levels + 1):
+        if (n1 >> (lc - 1)) <= 64 and (n2 >> (lc - 1)) <= 64:
+            return lc
+    return levels + 1
+
+
 def batched_vs_per_image(torch, P, SI, h, iters, count):
     """Uneven sizes (sides uniform on {96..1024 step 32}, per-image lambda):
-    one pd_solve_batched call vs a loop of pd_solve calls on one stream."""
+    one pd_solve_batched call vs a loop of pd_solve calls on one stream, both
+    replaying their middle iterations from captured graphs.  The roofline is
+    that of the batched run's dominant kernel class (an instrumented 100-
+    iteration batched solve: per-launch events, eager launches), with the
+    algorithmic bytes of one launch summed over the images it covers."""
     cases = SI.case_batch(count)
     dev = "cuda"
     f0s, ops, taus, lws, levels = [], [], [], [], []
@@ -199,10 +212,35 @@ def batched_vs_per_image(torch, P, SI, h, iters, count):
         res[name] = px * iters / (time.perf_counter() - t) / 1e6
         res[name + "_out"] = outs
     same = all(torch.equal(a, b) for a, b in zip(res["per_image_out"], res["batched_out"]))
+    # roofline of the dominant kernel class of the batched launches
+    P.solver.pd_timing_enable(True)
+    P.pd_solve_batched(f0s, ops, lws, taus, h, levels, 100)
+    torch.cuda.synchronize()
+    rows = P.solver.pd_timing_read()
+    P.solver.pd_timing_enable(False)
+    lcs = [coarse_first_level(c.n1, c.n2, c.levels) for c in cases]
+    for rw in rows:
+        k, lev = rw["kernel"], rw["level"]
+        tot = 0.0
+        for c, lc in zip(cases, lcs):
+            if k == "coarse" and lc <= c.levels:
+                tot += alg_bytes("coarse", lc, c.n1, c.n2, 1, 4, False)
+            elif k in ("synthesis", "analysis") and 1 <= lev < lc:
+                tot += alg_bytes(k, lev, c.n1, c.n2, 1, 4, False)
+            elif k == "blur":
+                tot += alg_bytes("blur", 0, c.n1, c.n2, 1, 4, False)
+        rw["alg_bytes_per_launch"] = tot
+    dom = max(rows, key=lambda rw: rw["total_ms"])
+    ach = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
     return {"images": count, "iters": iters, "pixels": px,
             "batched_mpx_it_s": round(res["batched"], 1),
             "per_image_mpx_it_s": round(res["per_image"], 1),
-            "speedup": round(res["batched"] / res["per_image"], 3), "bitwise_equal": same}
+            "speedup": round(res["batched"] / res["per_image"], 3), "bitwise_equal": same,
+            "alg_frac_20B": round(res["batched"] * 1e6 * 20 / (HBM_PEAK_GBS * 1e9), 5),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": f"{dom['kernel']}/{dom['level']}",
+                         "avg_us": round(dom["avg_us"], 3), "alg_bytes_per_launch": dom["alg_bytes_per_launch"]},
+            "kernels_us": {f"{rw['kernel']}/{rw['level']}": round(rw["avg_us"], 2) for rw in rows}}
 
 
 def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20, streams=4):
@@ -593,7 +631,7 @@ def main():
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-iters", type=int, default=100)
+    ap.add_argument("--batched-iters", type=int, default=1000)
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-colour", action="store_true")
@@ -686,7 +724,7 @@ def main():
         line["decompose"] = decompose_case(torch, P, h, n=args.decompose_n)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(SI)
+        line["cpu_baseline"] = cpu_baseline(SI, tau)
     print(json.dumps(line), flush=True)
 
 

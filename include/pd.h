@@ -156,13 +156,15 @@ int pd_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op,
 
 /* One image of a batch for pd_solve_batched.  Arrays of image b start at
  * element `offset` of the packed buffers (each image planar C x n2 x n1).
- * op.taps is the image's own device tap table; level_w its host band weights. */
+ * op: PD_OP_ROWBLUR with the image's own device tap table.  w: the image's
+ * weights as for pd_solve (host level_w, or coeff_w = the image's own device
+ * [C][n2][n1] map; joint = group prox over its channels). */
 typedef struct {
     pd_shape shape;
     int64_t offset;
     double tau;
     pd_operator op;
-    const double *level_w;
+    pd_weights w;
 } pd_image_desc;
 
 /* Bytes of device workspace pd_solve_batched needs for these images. */
@@ -171,9 +173,16 @@ size_t pd_batched_workspace_size(int32_t batch, const pd_image_desc *descs, int3
 /* Solve `batch` independent instances of eq. 4.1 of uneven sizes from the
  * default initial guess, `iters` iterations each, in lock-step launches that
  * cover every image (the same per-image arithmetic as pd_solve, so results
- * match pd_solve bit for bit).  f0_packed / f_out_packed: device, packed as
- * described by descs[b].offset.  stats: device double [batch][iters][3] or
- * NULL.  descs is a host array. */
+ * match pd_solve bit for bit).  f0_packed / f_out_packed: device, packed
+ * back to back in order as described by descs[b].offset.  stats: device
+ * double [batch][iters][3] or NULL (caller-zeroed, as for pd_solve).  descs
+ * is a host array, read during the call.  Every image of a batch takes the
+ * same prox: all scalar, or all joint with one channel count (else
+ * PD_ERR_UNSUPPORTED).  The per-image descriptor tables are copied into the
+ * workspace through a library-owned pinned staging buffer, so the call
+ * returns without synchronising the host.  The iterations between the first
+ * and the last run in replayed graph chunks as for pd_solve (pd_graphs_enable),
+ * with bitwise the same results.  Errors as pd_solve. */
 int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32_t dtype,
                      const pd_wavelet *wav, int32_t iters, const void *f0_packed,
                      void *f_out_packed, double *stats, void *workspace,

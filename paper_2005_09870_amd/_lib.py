@@ -55,7 +55,7 @@ class pd_csr(ctypes.Structure):
 
 class pd_image_desc(ctypes.Structure):
     _fields_ = [("shape", pd_shape), ("offset", ctypes.c_int64), ("tau", ctypes.c_double),
-                ("op", pd_operator), ("level_w", ctypes.POINTER(ctypes.c_double))]
+                ("op", pd_operator), ("w", pd_weights)]
 
 
 # every symbol include/pd.h declares

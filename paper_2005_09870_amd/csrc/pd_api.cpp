@@ -531,17 +531,74 @@ hipStream_t capture_stream(int dev)
     return s;
 }
 
-// Returns the executable graph for the chunk starting at local index it_a
-// (and the event to record after launching it), capturing it if allowed.
-// The caller holds g_graph_mu.
-template <typename T>
-hipGraphExec_t chunk_graph_locked(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0,
-                                  T *zc, T *zp, int it_a, int count, double *stats, int i_first, bool may_capture,
-                                  hipEvent_t *done)
+// Looks up the executable graph cached under `key`, or, if allowed, captures
+// one by running record(capture_stream) and caches it; then stores `it_value`
+// in *it_dev, replays the graph on st and records its completion event, all
+// under the cache lock (no other thread can retire and destroy the graph
+// between the lookup and the record).  Returns false when there is no graph
+// (the caller runs the work eagerly) and sets *err on a HIP error.
+template <typename F>
+bool replay_graph(const std::vector<char> &key, bool may_capture, F &&record, int *it_dev, int it_value,
+                  hipStream_t st, int *err)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    sweep_retired();
+    hipGraphExec_t ex = nullptr;
+    hipEvent_t done = nullptr;
+    for (size_t k = 0; k < g_graph_cache.size(); ++k)
+        if (g_graph_cache[k].key == key) {
+            CachedGraph e = g_graph_cache[k];
+            g_graph_cache.erase(g_graph_cache.begin() + k);
+            g_graph_cache.push_back(e);
+            ex = e.exec;
+            done = e.done;
+            break;
+        }
+    if (!ex) {
+        if (!may_capture) return false;
+        hipStream_t cs = capture_stream(dev);
+        if (!cs) return false;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        const int rc = record(cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc == PD_OK && e == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
+            ex = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        if (!ex) return false;
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            (void)hipGetLastError();
+            return false;
+        }
+        if (g_graph_cache.size() >= GRAPH_CACHE) {  // it may still be queued: retire, destroy later
+            g_graph_retired.push_back(g_graph_cache.front());
+            g_graph_cache.erase(g_graph_cache.begin());
+        }
+        g_graph_cache.push_back(CachedGraph{key, ex, done});
+    }
+    if (launch_set_int(it_dev, it_value, st) != hipSuccess || hipGraphLaunch(ex, st) != hipSuccess ||
+        hipEventRecord(done, st) != hipSuccess)
+        *err = PD_ERR_HIP;
+    return true;
+}
+
+// Replays (capturing first if allowed) the chunk of PD_RING iterations that
+// starts at local index it_a.  The key holds everything the launches bake in.
+template <typename T>
+bool launch_chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc,
+                        T *zp, int it_a, int count, double *stats, int i_first, bool may_capture, int *err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
     std::vector<char> key;
+    key_put(key, 'S');
     key_put(key, (int)sizeof(T));
     key_put(key, dev);
     key_put(key, *c.sh);
@@ -563,76 +620,19 @@ hipGraphExec_t chunk_graph_locked(const Ctx<T> &c, const pd_operator *op, const 
     key_put(key, zp);
     key_put(key, stats);
     key_put(key, i_first);
-    sweep_retired();
-    for (size_t k = 0; k < g_graph_cache.size(); ++k)
-        if (g_graph_cache[k].key == key) {
-            CachedGraph e = g_graph_cache[k];
-            g_graph_cache.erase(g_graph_cache.begin() + k);
-            g_graph_cache.push_back(e);
-            *done = e.done;
-            return e.exec;
+    auto record = [&](hipStream_t cs) -> int {
+        Ctx<T> cc = c;
+        cc.st = cs;
+        int rc = PD_OK;
+        T *a = zc, *b = zp;
+        for (int j = 0; j < PD_RING && rc == PD_OK; ++j) {
+            rc = one_iteration<T>(cc, op, w, tau, f0, a, b, it_a + j, i_first + it_a + j, count, stats, i_first,
+                                  DevIter{c.it_dev(), j});
+            std::swap(a, b);
         }
-    if (!may_capture) return nullptr;
-    hipStream_t cs = capture_stream(dev);
-    if (!cs) return nullptr;
-    Ctx<T> cc = c;
-    cc.st = cs;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    int rc = PD_OK;
-    T *a = zc, *b = zp;
-    for (int j = 0; j < PD_RING && rc == PD_OK; ++j) {
-        rc = one_iteration<T>(cc, op, w, tau, f0, a, b, it_a + j, i_first + it_a + j, count, stats, i_first,
-                              DevIter{c.it_dev(), j});
-        std::swap(a, b);
-    }
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(cs, &g);
-    hipGraphExec_t ex = nullptr;
-    if (rc == PD_OK && e == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
-        ex = nullptr;
-    if (g) (void)hipGraphDestroy(g);
-    (void)hipGetLastError();
-    if (!ex) return nullptr;
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGraphExecDestroy(ex);
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    if (g_graph_cache.size() >= GRAPH_CACHE) {  // it may still be queued: retire, destroy later
-        g_graph_retired.push_back(g_graph_cache.front());
-        g_graph_cache.erase(g_graph_cache.begin());
-    }
-    g_graph_cache.push_back(CachedGraph{key, ex, ev});
-    *done = ev;
-    return ex;
-}
-
-// Launches the executable graph of the chunk starting at local index it_a on
-// the caller's stream (capturing it first if allowed): stores the chunk's first
-// iteration number, replays the graph and records its completion event, all
-// under the cache lock, so that no other thread can retire and destroy the
-// graph between the lookup and the event record.  Returns false when there is
-// no graph (the caller runs the chunk eagerly) and sets *err on a HIP error.
-template <typename T>
-bool launch_chunk_graph(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc,
-                        T *zp, int it_a, int count, double *stats, int i_first, bool may_capture, int *err)
-{
-    hipEvent_t done = nullptr;
-    hipGraphExec_t ex = nullptr;
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    ex = chunk_graph_locked<T>(c, op, w, tau, f0, zc, zp, it_a, count, stats, i_first, may_capture, &done);
-    if (!ex) return false;
-    hipError_t e;
-    if ((e = launch_set_int(c.it_dev(), i_first + it_a, c.st)) != hipSuccess ||
-        (e = hipGraphLaunch(ex, c.st)) != hipSuccess || (e = hipEventRecord(done, c.st)) != hipSuccess) {
-        (void)e;
-        *err = PD_ERR_HIP;
-    }
-    return true;
+        return rc;
+    };
+    return replay_graph(key, may_capture, record, c.it_dev(), i_first + it_a, c.st, err);
 }
 
 // Iterations i = i_first .. i_first+count-1 of the recursion from the state
@@ -747,7 +747,7 @@ struct BImg {
 struct BLayout {
     std::vector<BImg> img;
     int64_t total;        // packed elements
-    size_t zA, zB, x, s, flag, tab, tab_bytes, total_bytes;
+    size_t zA, zB, x, s, flag, it, tab, tab_bytes, total_bytes;
     int maxfine;
 };
 
@@ -782,7 +782,7 @@ BLayout batched_layout(int batch, const pd_image_desc *d)
     for (int b = 0; b < batch; ++b) {
         BImg im;
         im.sh = d[b].shape;
-        im.lc = coarse_level<T>(&im.sh, 0);
+        im.lc = coarse_level<T>(&im.sh, d[b].w.joint);
         im.off = L.total;
         L.total += (int64_t)im.sh.n1 * im.sh.n2 * im.sh.channels;
         L.maxfine = std::max(L.maxfine, im.lc - 1);
@@ -810,11 +810,50 @@ BLayout batched_layout(int batch, const pd_image_desc *d)
     }
     L.flag = off;
     off = align_up(off + 256);
+    L.it = off;  // device iteration number of replayed graphs
+    off = align_up(off + 256);
     L.tab = off;
     L.tab_bytes = table_bytes_upper(batch, maxl);
     off += L.tab_bytes;
     L.total_bytes = off;
     return L;
+}
+
+// Pinned host staging for the descriptor tables: the upload is asynchronous
+// and a buffer is reused only after the event recorded behind its last copy
+// has completed, so the call never waits for the device.
+struct Staging {
+    void *host;
+    size_t bytes;
+    hipEvent_t done;
+};
+std::mutex g_stage_mu;
+std::vector<Staging> g_stage;
+
+int upload_async(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging *use = nullptr;
+    for (auto &e : g_stage)
+        if (e.bytes >= bytes && hipEventQuery(e.done) == hipSuccess) {
+            use = &e;
+            break;
+        }
+    (void)hipGetLastError();  // a pending event reports hipErrorNotReady
+    if (!use) {
+        Staging e{nullptr, std::max(bytes, (size_t)1 << 16), nullptr};
+        if (hipHostMalloc(&e.host, e.bytes, hipHostMallocDefault) != hipSuccess) return PD_ERR_HIP;
+        if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(e.host);
+            return PD_ERR_HIP;
+        }
+        g_stage.push_back(e);
+        use = &g_stage.back();
+    }
+    std::memcpy(use->host, src, bytes);
+    PD_TRY_HIP(hipMemcpyAsync(dst, use->host, bytes, hipMemcpyHostToDevice, st));
+    PD_TRY_HIP(hipEventRecord(use->done, st));
+    return PD_OK;
 }
 
 template <typename T>
@@ -827,6 +866,9 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     const Filt<T> f = make_filt<T>(wav);
     T *zA = (T *)(ws + L.zA), *zB = (T *)(ws + L.zB), *X = (T *)(ws + L.x), *S = (T *)(ws + L.s);
     int *flag = (int *)(ws + L.flag);
+    int *it_dev = (int *)(ws + L.it);
+    // joint prox: every image has the same channel count (checked by the caller)
+    const int nch = d[0].w.joint ? d[0].shape.channels : 0;
 
     // tables: init (plain analysis, coarse plain), iteration (coarse syn, synth,
     // blur, analysis, coarse prox[+syn]), final synthesis into f_out
@@ -855,11 +897,12 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         for (int j = 0; j <= PD_MAXL; ++j) c.lay.apx[j] = im.apx[j];
         const int64_t N = (int64_t)sh->n1 * sh->n2;
         const int n1 = sh->n1, n2 = sh->n2, Lv = sh->levels, C = sh->channels;
+        const int groups = nch ? 1 : C;  // tile sets / coarse workgroups per image
         double *slots = stats ? (double *)(ws + im.slots) : nullptr;
         double *stb = stats ? stats + (size_t)b * iters * 3 : nullptr;
         slots_tab[b] = slots;
         stats_tab[b] = stb;
-        pd_weights w{d[b].level_w, nullptr, 0};
+        const pd_weights &w = d[b].w;
         T *zAb = zA + im.off, *zBb = zB + im.off, *Xb = X + im.off, *Sb = S + im.off;
         const T *F0b = f0p + im.off;
         T *FOb = fop + im.off;
@@ -867,6 +910,7 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         pp.flag = flag;
         ProxArgs<T> pplain = prox_args<T>(c, nullptr, nullptr, zAb, T(0), T(0), nullptr, nullptr);
         pplain.flag = flag;
+        pplain.joint = pp.joint;  // same tile grouping in the plain transform
         const bool coarse = im.lc <= Lv;
         // fine levels
         for (int lev = 1; lev <= im.lc - 1; ++lev) {
@@ -882,7 +926,7 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
             a.apx_plane = (int64_t)(n1 >> lev) * (n2 >> lev);
             a.band_detail = Lv + 1 - lev;
             tiles_analysis(a.M1c, a.M2c, &a.tx, &a.ty);
-            const int tiles = a.tx * a.ty * C;
+            const int tiles = a.tx * a.ty * groups;
             a.mode = MODE_PROX;
             a.p = pp;
             t_ana[lev].add(a, tiles);
@@ -961,19 +1005,19 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
             }
             ca.ops = COARSE_ANA | COARSE_PROX | COARSE_SYN;
             ca.p = pp;
-            t_coprox_syn.add(ca, C);
+            t_coprox_syn.add(ca, groups);
             ca.ops = COARSE_ANA | COARSE_PROX;
-            t_coprox.add(ca, C);
+            t_coprox.add(ca, groups);
             ca.ops = COARSE_SYN;
-            t_cosyn.add(ca, C);
+            t_cosyn.add(ca, groups);
             ca.p.zc = ca.p.zp = f_zfinal + im.off;
             if (im.lc == 1) ca.apx_out = FOb;
-            t_fcosyn.add(ca, C);
+            t_fcosyn.add(ca, groups);
             ca.ops = COARSE_ANA;
             ca.p = pplain;
             if (im.lc == 1) ca.apx_in = F0b;
             ca.apx_out = nullptr;
-            t_init_co.add(ca, C);
+            t_init_co.add(ca, groups);
         }
     }
 
@@ -1007,9 +1051,8 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     std::memcpy(host.data() + o_st, stats_tab.data(), batch * sizeof(double *));
     if (host.size() > L.tab_bytes) return PD_ERR_UNSUPPORTED;
     char *tab = ws + L.tab;
-    PD_TRY_HIP(hipMemcpyAsync(tab, host.data(), host.size(), hipMemcpyHostToDevice, st));
-    // the pageable source must stay valid until the copy has been consumed
-    PD_TRY_HIP(hipStreamSynchronize(st));
+    int rc;
+    if ((rc = upload_async(tab, host.data(), host.size(), st)) != PD_OK) return rc;
 
     auto targs = [&](auto &t) {
         using A = typename std::decay_t<decltype(t.args)>::value_type;
@@ -1022,64 +1065,116 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     size_t colds = 0;
     for (auto &im : L.img)
         if (im.lc <= im.sh.levels)
-            colds = std::max(colds, coarse_lds_bytes<T>(im.sh.n1 >> (im.lc - 1), im.sh.n2 >> (im.lc - 1), 1));
+            colds = std::max(colds, coarse_lds_bytes<T>(im.sh.n1 >> (im.lc - 1), im.sh.n2 >> (im.lc - 1),
+                                                        nch ? nch : 1));
 
-    auto run_coarse = [&](Table<CoarseArgs<T>> &t, Dyn<T> dy) -> int {
+    auto run_coarse = [&](Table<CoarseArgs<T>> &t, Dyn<T> dy, hipStream_t s) -> int {
         if (t.n() == 0) return PD_OK;
-        PD_TRY_HIP(timed(PD_K_COARSE, 0, st, [&] {
-            return launch_coarse_b<T>(targs(t), tstart(t), t.n(), t.tiles(), colds, dy, st);
+        PD_TRY_HIP(timed(PD_K_COARSE, 0, s, [&] {
+            return launch_coarse_b<T>(targs(t), tstart(t), t.n(), t.tiles(), colds, nch, dy, s);
         }));
         return PD_OK;
     };
-    auto run_synth = [&](std::vector<Table<SynthArgs<T>>> &ts, Dyn<T> dy) -> int {
+    auto run_synth = [&](std::vector<Table<SynthArgs<T>>> &ts, Dyn<T> dy, hipStream_t s) -> int {
         for (int lev = MF; lev >= 1; --lev) {
             auto &t = ts[lev];
             if (t.n() == 0) continue;
-            PD_TRY_HIP(timed(PD_K_SYNTH, lev, st,
-                             [&] { return launch_synth_b<T>(targs(t), tstart(t), t.n(), t.tiles(), dy, st); }));
+            PD_TRY_HIP(timed(PD_K_SYNTH, lev, s,
+                             [&] { return launch_synth_b<T>(targs(t), tstart(t), t.n(), t.tiles(), dy, s); }));
         }
         return PD_OK;
     };
-    auto run_ana = [&](std::vector<Table<AnalysisArgs<T>>> &ts, Dyn<T> dy) -> int {
+    auto run_ana = [&](std::vector<Table<AnalysisArgs<T>>> &ts, Dyn<T> dy, hipStream_t s) -> int {
         for (int lev = 1; lev <= MF; ++lev) {
             auto &t = ts[lev];
             if (t.n() == 0) continue;
-            PD_TRY_HIP(timed(PD_K_ANALYSIS, lev, st, [&] {
-                return launch_analysis_b<T>(targs(t), tstart(t), t.n(), t.tiles(), false, dy, st);
+            PD_TRY_HIP(timed(PD_K_ANALYSIS, lev, s, [&] {
+                return launch_analysis_b<T>(targs(t), tstart(t), t.n(), t.tiles(), nch, dy, s);
             }));
         }
         return PD_OK;
     };
+    // One iteration (local index it, i = it + 1).  dy carries the momenta, or
+    // (replay) the device iteration number they are computed from; the stats
+    // fold reads its first entry as it0 (+ *it_dev when replayed).
+    auto one_it = [&](int it, Dyn<T> dy, int fold_it0, hipStream_t s) -> int {
+        int r;
+        if (it == 0 && (r = run_coarse(t_cosyn, dy, s)) != PD_OK) return r;
+        if ((r = run_synth(t_syn, dy, s)) != PD_OK) return r;
+        PD_TRY_HIP(timed(PD_K_BLUR, 0, s, [&] {
+            return launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), dy.ring, s);
+        }));
+        if ((r = run_ana(t_ana, dy, s)) != PD_OK) return r;
+        if ((r = run_coarse(it == iters - 1 ? t_coprox : t_coprox_syn, dy, s)) != PD_OK) return r;
+        if (stats && ((it + 1) % PD_RING == 0 || it == iters - 1)) {
+            const int cnt = (it % PD_RING) + 1;
+            PD_TRY_HIP(launch_stats_finalize_b((double *const *)(tab + o_sl), (double *const *)(tab + o_st), batch,
+                                               fold_it0, cnt, dy.it_dev, s));
+        }
+        return PD_OK;
+    };
 
-    int rc;
-    Dyn<T> d0{T(0), T(0), 0, 0};
+    Dyn<T> d0{T(0), T(0), 0, 0, nullptr, 0};
     // init: z(0) = Psi^* f0 into zA, copied to zB
-    if ((rc = run_ana(t_init_ana, d0)) != PD_OK) return rc;
-    if ((rc = run_coarse(t_init_co, d0)) != PD_OK) return rc;
+    if ((rc = run_ana(t_init_ana, d0, st)) != PD_OK) return rc;
+    if ((rc = run_coarse(t_init_co, d0, st)) != PD_OK) return rc;
     PD_TRY_HIP(launch_copy<T>(zA, zB, L.total, st));
     if (stats)
         for (int b = 0; b < batch; ++b)
             PD_TRY_HIP(launch_fill<double>(slots_tab[b], 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
-    for (int it = 0; it < iters; ++it) {
-        const int i = 1 + it;
-        Dyn<T> dy{(T)beta_y(i), (T)beta_y(i + 1), it & 1, it % PD_RING};
-        if (it == 0 && (rc = run_coarse(t_cosyn, dy)) != PD_OK) return rc;
-        if ((rc = run_synth(t_syn, dy)) != PD_OK) return rc;
-        PD_TRY_HIP(timed(PD_K_BLUR, 0, st, [&] {
-            return launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), it % PD_RING, st);
-        }));
-        if ((rc = run_ana(t_ana, dy)) != PD_OK) return rc;
-        if ((rc = run_coarse(it == iters - 1 ? t_coprox : t_coprox_syn, dy)) != PD_OK) return rc;
-        if (stats && ((it + 1) % PD_RING == 0 || it == iters - 1)) {
-            const int cnt = (it % PD_RING) + 1, it0 = it + 1 - cnt;
-            PD_TRY_HIP(launch_stats_finalize_b((double *const *)(tab + o_sl), (double *const *)(tab + o_st), batch,
-                                               it0, cnt, st));
+    // the middle iterations run in replayed chunks of PD_RING (as pd_solve's)
+    const bool graphs = g_graphs && !g_timing;
+    int chunks = 0;
+    for (int it = 1; it + PD_RING < iters; it += PD_RING) ++chunks;
+    const bool may_capture = chunks >= 4;
+    std::vector<char> key;
+    if (graphs && chunks > 0) {
+        int dev = 0;
+        PD_TRY_HIP(hipGetDevice(&dev));
+        key_put(key, 'B');
+        key_put(key, (int)sizeof(T));
+        key_put(key, dev);
+        key_put(key, ws);
+        key_put(key, f0p);
+        key_put(key, stats);
+        key_put(key, iters);
+        key_put(key, batch);
+        key_put(key, f);
+        // the tables are rebuilt each call from these: equal bytes, equal launches
+        const size_t h0 = key.size();
+        key.resize(h0 + host.size());
+        std::memcpy(key.data() + h0, host.data(), host.size());
+    }
+    for (int it = 0; it < iters;) {
+        if (graphs && it % PD_RING == 1 && it + PD_RING < iters) {
+            const int it_a = it;
+            auto record = [&](hipStream_t cs) -> int {
+                int r = PD_OK;
+                for (int j = 0; j < PD_RING && r == PD_OK; ++j) {
+                    const int itj = it_a + j;
+                    const int cnt = (itj % PD_RING) + 1;
+                    // i = *it_dev + j with *it_dev = it_a + 1; fold entries from (i - 1) + 1 - cnt
+                    Dyn<T> dy{T(0), T(0), itj & 1, itj % PD_RING, it_dev, j};
+                    r = one_it(itj, dy, j - cnt, cs);
+                }
+                return r;
+            };
+            int err = PD_OK;
+            if (replay_graph(key, may_capture, record, it_dev, it_a + 1, st, &err)) {
+                if (err != PD_OK) return err;
+                it += PD_RING;
+                continue;
+            }
         }
+        const int i = 1 + it;
+        Dyn<T> dy{(T)beta_y(i), (T)beta_y(i + 1), it & 1, it % PD_RING, nullptr, 0};
+        if ((rc = one_it(it, dy, it + 1 - ((it % PD_RING) + 1), st)) != PD_OK) return rc;
+        ++it;
     }
     // f = Psi z(K)
-    Dyn<T> dz{T(0), T(0), 0, 0};
-    if ((rc = run_coarse(t_fcosyn, dz)) != PD_OK) return rc;
-    if ((rc = run_synth(t_fsyn, dz)) != PD_OK) return rc;
+    Dyn<T> dz{T(0), T(0), 0, 0, nullptr, 0};
+    if ((rc = run_coarse(t_fcosyn, dz, st)) != PD_OK) return rc;
+    if ((rc = run_synth(t_fsyn, dz, st)) != PD_OK) return rc;
     return PD_OK;
 }
 
@@ -1104,12 +1199,14 @@ extern "C" int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32
     if ((rc = check_dtype(dtype)) || (rc = check_wavelet(wav))) return rc;
     for (int b = 0; b < batch; ++b) {
         const pd_image_desc &d = descs[b];
-        if ((rc = check_shape(&d.shape)) || (rc = check_op(&d.op, &d.shape))) return rc;
+        if ((rc = check_shape(&d.shape)) || (rc = check_op(&d.op, &d.shape)) || (rc = check_weights(&d.w, &d.shape)))
+            return rc;
         if (d.op.kind != PD_OP_ROWBLUR) return PD_ERR_UNSUPPORTED;
-        if (!d.level_w || d.offset < 0) return PD_ERR_ARG;
-        for (int k = 0; k <= d.shape.levels; ++k)
-            if (!std::isfinite(d.level_w[k]) || d.level_w[k] < 0.0) return PD_ERR_ARG;
+        if (d.offset < 0) return PD_ERR_ARG;
         if (!std::isfinite(d.tau) || d.tau <= 0.0) return PD_ERR_TAU;
+        // one launch per phase: every image takes the same prox kind (and, joint, channel count)
+        if ((d.w.joint != 0) != (descs[0].w.joint != 0)) return PD_ERR_UNSUPPORTED;
+        if (d.w.joint && d.shape.channels != descs[0].shape.channels) return PD_ERR_UNSUPPORTED;
     }
     // images must be packed back to back in order (offset = running sum)
     int64_t run = 0;

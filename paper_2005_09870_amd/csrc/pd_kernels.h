@@ -145,6 +145,8 @@ struct Dyn {
     T beta, beta_next;      // momentum of y(i) and of y(i+1)
     int parity;             // 1: the table's zc/zp are swapped this iteration
     int ring;               // statistics ring entry of this iteration
+    const int *it_dev;      // replayed graph: beta, beta_next from i = *it_dev + it_off
+    int it_off;
 };
 
 template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s);
@@ -156,18 +158,20 @@ template <typename T> hipError_t launch_blur_single(const BlurArgs<T> &a, int tr
 template <typename T> hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_synth_b(const SynthArgs<T> *tab, const int *start, int n, int tiles, Dyn<T> d, hipStream_t s);
+// nch = 0: scalar prox (tiles and coarse groups per channel); 1..4: joint prox
+// over that many channels (tiles and coarse groups per image).
 template <typename T>
-hipError_t launch_analysis_b(const AnalysisArgs<T> *tab, const int *start, int n, int tiles, bool joint, Dyn<T> d,
+hipError_t launch_analysis_b(const AnalysisArgs<T> *tab, const int *start, int n, int tiles, int nch, Dyn<T> d,
                              hipStream_t s);
 template <typename T>
-hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, int groups, size_t lds, Dyn<T> d,
-                           hipStream_t s);
+hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, int groups, size_t lds, int nch,
+                           Dyn<T> d, hipStream_t s);
 template <typename T>
 hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s);
 // stats[it0+j][q] += sum of ring entry (it0+j) % PD_RING, then zeroed, for
 // j < count; batched: one image per grid row, ring/stats bases from tables.
 hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, int n, int it0, int count,
-                                   hipStream_t s);
+                                   const int *it_dev, hipStream_t s);  // it_dev: it0 += *it_dev
 void tiles_synth(int M1c, int M2c, int *tx, int *ty);
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty);
 void tiles_blur(int n1, int n2, int *tx, int *ty);

@@ -996,9 +996,10 @@ __global__ void k_set_int(int *dst, int v)
 }
 
 __global__ __launch_bounds__(256) void k_stats_finalize_b(double *const *__restrict__ ring,
-                                                           double *const *__restrict__ stats, int it0)
+                                                           double *const *__restrict__ stats, int it0,
+                                                           const int *it_dev)
 {
-    const int it = it0 + blockIdx.x, img = blockIdx.y;
+    const int it = (it_dev ? *it_dev : 0) + it0 + blockIdx.x, img = blockIdx.y;
     finalize_entry(ring[img] + (size_t)(it % PD_RING) * 3 * PD_NSLOT, stats[img] + 3 * (size_t)it);
 }
 
@@ -1452,10 +1453,23 @@ __device__ __forceinline__ Live<T> live_dyn(const ProxArgs<T> &p, const Dyn<T> &
                    p.slots ? p.slots + (size_t)d.ring * 3 * PD_NSLOT : nullptr};
 }
 
+// Momenta of a replayed launch from the device iteration number.
+template <typename T>
+__device__ __forceinline__ Dyn<T> dyn_at(Dyn<T> d)
+{
+    if (d.it_dev) {
+        const int i = *d.it_dev + d.it_off;
+        d.beta = beta_at<T>(i);
+        d.beta_next = beta_at<T>(i + 1);
+    }
+    return d;
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_synth_b(const SynthArgs<T> *__restrict__ tab, const int *__restrict__ start,
                                                  int n, Dyn<T> d)
 {
+    d = dyn_at<T>(d);
     const int g = xcd_tile(start[n]);
     if (g < 0) return;
     const int img = locate(start, n, g);
@@ -1468,10 +1482,13 @@ __global__ __launch_bounds__(NT) void k_synth_b(const SynthArgs<T> *__restrict__
     synth_body<T>(a, lv, bx, loc % ty, loc / ty);
 }
 
-template <typename T>
+// NCH = 0: scalar prox, one tile set per channel; NCH >= 1: joint prox over
+// NCH channels per tile (every image of the launch has NCH channels).
+template <typename T, int NCH>
 __global__ __launch_bounds__(NT) void k_analysis_b(const AnalysisArgs<T> *__restrict__ tab,
                                                     const int *__restrict__ start, int n, Dyn<T> d)
 {
+    d = dyn_at<T>(d);
     const int g = xcd_tile(start[n]);
     if (g < 0) return;
     const int img = locate(start, n, g);
@@ -1481,13 +1498,16 @@ __global__ __launch_bounds__(NT) void k_analysis_b(const AnalysisArgs<T> *__rest
     const int tx = a.tx, ty = a.ty;
     const int bx = loc % tx;
     loc /= tx;
-    analysis_body<T, 0>(a, lv, bx, loc % ty, loc / ty);
+    analysis_body<T, NCH>(a, lv, bx, loc % ty, loc / ty);
 }
 
-template <typename T>
+// NCH as for the joint coarse kernel: 1 with one workgroup per channel (scalar
+// prox), or the channel count of joint images (one workgroup per image).
+template <typename T, int NCH, bool JOINT>
 __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restrict__ tab, const int *__restrict__ start,
                                                    int n, Dyn<T> d)
 {
+    d = dyn_at<T>(d);
     const int img = locate(start, n, blockIdx.x);
     const CoarseArgs<T> &a = tab[img];
     Live<T> lv;
@@ -1499,7 +1519,7 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
     } else {
         lv = live_of<T>(a.p, T(0));
     }
-    coarse_body<T, 1>(a, lv, blockIdx.x - start[img]);
+    coarse_body<T, NCH>(a, lv, JOINT ? 0 : blockIdx.x - start[img]);
 }
 
 template <typename T>
@@ -1616,19 +1636,33 @@ hipError_t launch_synth_b(const SynthArgs<T> *tab, const int *start, int n, int 
 }
 
 template <typename T>
-hipError_t launch_analysis_b(const AnalysisArgs<T> *tab, const int *start, int n, int tiles, bool joint, Dyn<T> d,
+hipError_t launch_analysis_b(const AnalysisArgs<T> *tab, const int *start, int n, int tiles, int nch, Dyn<T> d,
                              hipStream_t s)
 {
-    if (joint) return hipErrorInvalidValue;  // lock-step batches use per-channel weights only
-    hipLaunchKernelGGL(k_analysis_b<T>, dim3(xcd_grid(tiles)), dim3(NT), 0, s, tab, start, n, d);
+    const dim3 grid(xcd_grid(tiles));
+    switch (nch) {
+    case 0: hipLaunchKernelGGL((k_analysis_b<T, 0>), grid, dim3(NT), 0, s, tab, start, n, d); break;
+    case 1: hipLaunchKernelGGL((k_analysis_b<T, 1>), grid, dim3(NT), 0, s, tab, start, n, d); break;
+    case 2: hipLaunchKernelGGL((k_analysis_b<T, 2>), grid, dim3(NT), 0, s, tab, start, n, d); break;
+    case 3: hipLaunchKernelGGL((k_analysis_b<T, 3>), grid, dim3(NT), 0, s, tab, start, n, d); break;
+    case 4: hipLaunchKernelGGL((k_analysis_b<T, 4>), grid, dim3(NT), 0, s, tab, start, n, d); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, int groups, size_t lds, Dyn<T> d,
-                           hipStream_t s)
+hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, int groups, size_t lds, int nch,
+                           Dyn<T> d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coarse_b<T>, dim3(groups), dim3(NTC), lds, s, tab, start, n, d);
+    switch (nch) {
+    case 0: hipLaunchKernelGGL((k_coarse_b<T, 1, false>), dim3(groups), dim3(NTC), lds, s, tab, start, n, d); break;
+    case 1: hipLaunchKernelGGL((k_coarse_b<T, 1, true>), dim3(groups), dim3(NTC), lds, s, tab, start, n, d); break;
+    case 2: hipLaunchKernelGGL((k_coarse_b<T, 2, true>), dim3(groups), dim3(NTC), lds, s, tab, start, n, d); break;
+    case 3: hipLaunchKernelGGL((k_coarse_b<T, 3, true>), dim3(groups), dim3(NTC), lds, s, tab, start, n, d); break;
+    case 4: hipLaunchKernelGGL((k_coarse_b<T, 4, true>), dim3(groups), dim3(NTC), lds, s, tab, start, n, d); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1640,9 +1674,9 @@ hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int ti
 }
 
 hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, int n, int it0, int count,
-                                   hipStream_t s)
+                                   const int *it_dev, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stats_finalize_b, dim3(count, n), dim3(256), 0, s, ring, stats, it0);
+    hipLaunchKernelGGL(k_stats_finalize_b, dim3(count, n), dim3(256), 0, s, ring, stats, it0, it_dev);
     return hipGetLastError();
 }
 
@@ -1731,9 +1765,9 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
     template hipError_t launch_blur_single<T>(const BlurArgs<T> &, int, hipStream_t);      \
     template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                   \
     template hipError_t launch_synth_b<T>(const SynthArgs<T> *, const int *, int, int, Dyn<T>, hipStream_t); \
-    template hipError_t launch_analysis_b<T>(const AnalysisArgs<T> *, const int *, int, int, bool, Dyn<T>,     \
+    template hipError_t launch_analysis_b<T>(const AnalysisArgs<T> *, const int *, int, int, int, Dyn<T>,     \
                                              hipStream_t);                                                      \
-    template hipError_t launch_coarse_b<T>(const CoarseArgs<T> *, const int *, int, int, size_t, Dyn<T>,       \
+    template hipError_t launch_coarse_b<T>(const CoarseArgs<T> *, const int *, int, int, size_t, int, Dyn<T>,  \
                                            hipStream_t);                                                        \
     template hipError_t launch_blur_b<T>(const BlurArgs<T> *, const int *, int, int, int, hipStream_t);
 PD_INST(float)

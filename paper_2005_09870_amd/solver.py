@@ -217,10 +217,15 @@ def step_size(op: Operator, n1: int, n2: int, device="cuda") -> float:
 
 # ----------------------------------------------------------------- batched ---
 def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, taus, h,
-                     levels: list[int], iters: int, stats: bool = False):
-    """Solve a batch of uneven-size problems; returns the list of f = Psi z."""
+                     levels: list[int], iters: int, stats: bool = False, coeff_ws=None, joint: bool = False):
+    """Solve a batch of uneven-size problems in lock-step launches; returns the
+    list of f = Psi z and the (batch, iters, 3) FP64 statistics (or None).
+    Weights per image: level_ws[b] (host band weights) or, when coeff_ws is
+    given and coeff_ws[b] is not None, that image's device weight map; joint
+    applies the group prox to every image (all with one channel count)."""
     dev = f0s[0].device
     dtype = f0s[0].dtype
+    _check_dev(*f0s, *([] if coeff_ws is None else [c for c in coeff_ws if c is not None]))
     sizes = [t.numel() for t in f0s]
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
     f0p = torch.cat([t.reshape(-1) for t in f0s]).contiguous()
@@ -228,13 +233,21 @@ def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, tau
     descs = (C.pd_image_desc * len(f0s))()
     keep = []
     for b, t in enumerate(f0s):
-        lw = np.ascontiguousarray(np.asarray(level_ws[b], dtype=np.float64))
-        keep.append(lw)
+        cw = None if coeff_ws is None else coeff_ws[b]
+        lw = None
+        if cw is None:
+            lw = np.ascontiguousarray(np.asarray(level_ws[b], dtype=np.float64))
+            if lw.shape != (levels[b] + 1,):
+                raise ValueError("level_w needs levels+1 entries")
+            keep.append(lw)
+        elif cw.shape != t.shape or cw.dtype != dtype or not cw.is_contiguous():
+            raise ValueError("coeff_w must match its image's shape and dtype, contiguous")
         descs[b].shape = _shape(t, levels[b])
         descs[b].offset = int(offs[b])
         descs[b].tau = float(taus[b])
         descs[b].op = ops[b].c()
-        descs[b].level_w = _dptr(lw)
+        descs[b].w = C.pd_weights(_dptr(lw) if lw is not None else None, None if cw is None else cw.data_ptr(),
+                                  1 if joint else 0)
     wav, hh = _wavelet(h)
     L = C.load()
     dt = _dtype_code(dtype)

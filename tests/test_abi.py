@@ -247,3 +247,43 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_batched_argument_errors_without_gpu_work():
+    """pd_solve_batched checks every descriptor on the host first: one prox kind
+    per batch (and one channel count when joint), weights as for pd_solve,
+    images packed back to back, a large enough workspace."""
+    L = C.load()
+    h = S.pd_symmlet(6)
+    wav = C.pd_wavelet(12, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    lw = np.full(4, 0.1)
+    lwp = lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def descs(specs):
+        d = (C.pd_image_desc * len(specs))()
+        off = 0
+        for b, (n, ch, joint, coeff) in enumerate(specs):
+            d[b].shape = C.pd_shape(n, n, ch, 3)
+            d[b].offset = off
+            d[b].tau = 0.5
+            d[b].op = C.pd_operator(C.PD_OP_ROWBLUR, 9, _fake(7))
+            d[b].w = C.pd_weights(None if coeff else lwp, _fake(8) if coeff else None, joint)
+            off += n * n * ch
+        return d
+
+    def call(d, ws_bytes=1 << 40):
+        return L.pd_solve_batched(len(d), d, C.PD_F32, ctypes.byref(wav), 10, _fake(1), _fake(2), None,
+                                  _fake(3), ws_bytes, None)
+
+    assert call(descs([(32, 3, 1, 0), (64, 1, 0, 0)])) == C.PD_ERR_UNSUPPORTED   # joint and scalar mixed
+    assert call(descs([(32, 3, 1, 0), (64, 2, 1, 0)])) == C.PD_ERR_UNSUPPORTED   # joint, channel counts differ
+    assert call(descs([(32, 2, 1, 1)])) == C.PD_ERR_UNSUPPORTED                  # joint needs band weights
+    both = descs([(32, 1, 0, 0)])
+    both[0].w = C.pd_weights(lwp, _fake(8), 0)
+    assert call(both) == C.PD_ERR_ARG                                             # exactly one weight kind
+    d = descs([(32, 1, 0, 0), (64, 1, 0, 1)])
+    d[1].offset += 1
+    assert call(d) == C.PD_ERR_ARG                                                # not packed back to back
+    d = descs([(32, 1, 0, 0), (64, 1, 0, 1)])
+    need = L.pd_batched_workspace_size(2, d, C.PD_F32)
+    assert need > 0 and call(d, need - 1) == C.PD_ERR_WORKSPACE

@@ -310,3 +310,65 @@ def test_colour_2048_full_size():
     op = P.Operator.from_taps(pb.kt, pb.R, dtype=torch.float32)
     out = P.pd_solve(_t(f0, torch.float32), op, _h(), c.levels, tau, 2, level_w=c.level_w, joint=True)
     assert np.abs(_np(out["f"]) - ref["f"]).max() < 1e-5
+
+
+def _batch_inputs(shapes, C=1, seed=70, coeff=False, iters=None):
+    f0s, ops, lws, cws, taus, levels, pbs = [], [], [], [], [], [], []
+    for b, (n1, n2) in enumerate(shapes):
+        pb, f0, case = _problem(n1, n2, C=C, seed=seed + b, coeff=coeff, joint=False)
+        f0s.append(_t(f0, torch.float32))
+        ops.append(_op(pb, torch.float32))
+        lws.append(case.level_w)
+        cws.append(_t(pb.w, torch.float32) if coeff else None)
+        taus.append(0.8 + 0.02 * b)
+        levels.append(pb.levels)
+        pbs.append((pb, f0, case))
+    return f0s, ops, lws, cws, taus, levels, pbs
+
+
+def test_batched_graph_replay_is_bitwise():
+    """300 iterations (the middle ones replayed from captured graph chunks):
+    pd_solve_batched equals itself with graph replay off and pd_solve per image
+    bit for bit; the statistics agree to the rounding of their FP64 atomics."""
+    shapes = [(96, 128), (160, 96), (64, 64)]
+    f0s, ops, lws, _, taus, levels, _ = _batch_inputs(shapes)
+    K = 300
+    runs = {}
+    try:
+        for g in (True, False):
+            P.pd_graphs_enable(g)
+            runs[g] = [P.pd_solve_batched(f0s, ops, lws, taus, _h(), levels, K, stats=True) for _ in range(2)]
+    finally:
+        P.pd_graphs_enable(True)
+    for b in range(len(shapes)):
+        single = P.pd_solve(f0s[b], ops[b], _h(), levels[b], taus[b], K, level_w=lws[b], stats=True)
+        for g in (True, False):
+            for r in range(2):
+                assert torch.equal(runs[g][r][0][b], single["f"]), (b, g, r)
+                np.testing.assert_allclose(_np(runs[g][r][1][b]), _np(single["stats"]), rtol=1e-12)
+
+
+def test_batched_weight_maps_and_joint_prox():
+    """Per-coefficient weight maps and the joint colour prox in lock-step
+    batches: bitwise equal to pd_solve per image, and the joint batch against
+    the oracle."""
+    shapes = [(96, 64), (64, 128), (32, 32)]
+    f0s, ops, lws, cws, taus, levels, _ = _batch_inputs(shapes, coeff=True, seed=80)
+    outs, _ = P.pd_solve_batched(f0s, ops, lws, taus, _h(), levels, 60, coeff_ws=cws)
+    for b in range(len(shapes)):
+        ref = P.pd_solve(f0s[b], ops[b], _h(), levels[b], taus[b], 60, coeff_w=cws[b])["f"]
+        assert torch.equal(outs[b], ref), b
+    f0s, ops, lws, _, taus, levels, pbs = _batch_inputs(shapes, C=3, seed=90)
+    outs, st = P.pd_solve_batched(f0s, ops, lws, taus, _h(), levels, 60, joint=True, stats=True)
+    for b in range(len(shapes)):
+        ref = P.pd_solve(f0s[b], ops[b], _h(), levels[b], taus[b], 60, level_w=lws[b], joint=True, stats=True)
+        assert torch.equal(outs[b], ref["f"]), b
+        np.testing.assert_allclose(_np(st[b]), _np(ref["stats"]), rtol=1e-12)
+        pb, f0, case = pbs[b]
+        pbj = O.Problem(pb.n1, pb.n2, 3, pb.levels, h=_h(), w=pb.w, joint=True)
+        orc = O.fista(pbj, f0, taus[b], 60)
+        assert np.abs(_np(outs[b]) - orc["f"]).max() < 1e-5
+    with pytest.raises(P.PDError) as e:  # every image of a batch takes the same prox kind
+        f0m = [f0s[0], f0s[1][:1].contiguous()]
+        P.pd_solve_batched(f0m, ops[:2], lws[:2], taus[:2], _h(), levels[:2], 5, joint=True)
+    assert e.value.code == -7
