@@ -154,6 +154,27 @@ int pd_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op,
              void *f_out, double *stats, void *workspace, size_t ws_bytes,
              void *stream);
 
+/* Scratch bytes pd_solve_noalloc holds per GPU: pd_workspace_size of the
+ * problem must not exceed it (16 MiB: e.g. 1024 x 1024 FP32 with one channel,
+ * 512 x 512 with up to 4 channels, or 512 x 512 FP64). */
+#define PD_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* pd_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments without the workspace, the same results bit for bit.  Its
+ * scratch is a fixed device array of PD_NOALLOC_SCRATCH_BYTES inside the
+ * library (one per GPU, held until the process ends); the call allocates
+ * nothing and does not replay graphs (every iteration is launched).  Every
+ * call on one GPU shares that array and leaves its contents behind (the
+ * call clears what it needs cleared), so calls that overlap on one GPU --
+ * from several threads or on several streams -- race.  A problem whose
+ * pd_workspace_size exceeds PD_NOALLOC_SCRATCH_BYTES is rejected with
+ * PD_ERR_WORKSPACE before anything is enqueued.  Other errors as pd_solve. */
+int pd_solve_noalloc(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                     const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                     const void *f0, void *z_cur, void *z_prev, int32_t init_from_f0,
+                     void *f_out, double *stats, void *stream);
+
 /* One image of a batch for pd_solve_batched.  Arrays of image b start at
  * element `offset` of the packed buffers (each image planar C x n2 x n1).
  * op: PD_OP_ROWBLUR with the image's own device tap table.  w: the image's

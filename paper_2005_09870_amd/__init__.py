@@ -23,6 +23,7 @@ from .solver import (  # noqa: F401
     pd_op1_taps,
     pd_solve,
     pd_solve_batched,
+    pd_solve_noalloc,
     pd_symmlet,
     pd_workspace_size,
     pd_csr_transpose,

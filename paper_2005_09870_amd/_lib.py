@@ -60,7 +60,7 @@ class pd_image_desc(ctypes.Structure):
 
 # every symbol include/pd.h declares
 EXPORTS = [
-    "pd_workspace_size", "pd_solve", "pd_batched_workspace_size", "pd_solve_batched",
+    "pd_workspace_size", "pd_solve", "pd_solve_noalloc", "pd_batched_workspace_size", "pd_solve_batched",
     "pd_backward_workspace_size", "pd_backward", "pd_fwt", "pd_apply_op", "pd_symmlet",
     "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
@@ -98,6 +98,9 @@ def load() -> ctypes.CDLL:
     L.pd_solve.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights),
                            P(pd_params), vp, vp, vp, i32, vp, vp, vp, sz, vp]
     L.pd_solve.restype = ctypes.c_int
+    L.pd_solve_noalloc.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights),
+                                   P(pd_params), vp, vp, vp, i32, vp, vp, vp]
+    L.pd_solve_noalloc.restype = ctypes.c_int
     L.pd_batched_workspace_size.argtypes = [i32, P(pd_image_desc), i32]
     L.pd_batched_workspace_size.restype = sz
     L.pd_solve_batched.argtypes = [i32, P(pd_image_desc), i32, P(pd_wavelet), i32, vp, vp, vp,

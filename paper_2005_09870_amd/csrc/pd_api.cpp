@@ -155,6 +155,7 @@ struct Ctx {
     Layout lay;
     hipStream_t st;
     int lc;  // first level handled by the coarse kernel (levels + 1: none)
+    bool eager = false;  // no graph replay (the allocation-free entry point)
     TailShape ts;
     const T *tail;  // device copy of the tail matrices (nullptr: none)
     int64_t N() const { return (int64_t)sh->n1 * sh->n2; }
@@ -646,7 +647,7 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
 {
     const hipStream_t st = c.st;
     const int64_t NC = c.N() * c.sh->channels;
-    const bool graphs = g_graphs && !g_timing && !seg;
+    const bool graphs = g_graphs && !g_timing && !seg && !c.eager;
     int rc;
     if (stats && count > 0) PD_TRY_HIP(launch_fill<double>(c.ring(), 0.0, (int64_t)PD_RING * 3 * PD_NSLOT, st));
     // capturing pays off only when the graph is replayed several times
@@ -696,18 +697,19 @@ int iterate_seg(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T t
 template <typename T>
 int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
                const pd_params *prm, const T *f0, T *z_cur, T *z_prev, int init, T *f_out,
-               double *stats, void *workspace, size_t ws_bytes, hipStream_t st)
+               double *stats, void *workspace, size_t ws_bytes, hipStream_t st, bool eager = false)
 {
     // size check before make_ctx, which queues the tail-matrix upload into the workspace
     if (ws_bytes < layout(sh, sizeof(T)).total) return PD_ERR_WORKSPACE;
     Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, w->joint);
+    c.eager = eager;
     const int64_t NC = c.N() * sh->channels;
     int rc;
     if (init) {
         if ((rc = analysis_plain<T>(c, f0, z_cur)) != PD_OK) return rc;
         PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, z_prev, NC, st); }));
     }
-    if (prm->check_finite) PD_TRY_HIP(hipMemsetAsync(c.flag(), 0, sizeof(int), st));
+    if (prm->check_finite) PD_TRY_HIP(launch_set_int(c.flag(), 0, st));  // a kernel, not a memset node
     T *zc = z_cur, *zp = z_prev;
     if ((rc = iterate<T>(c, op, w, (T)prm->tau, f0, zc, zp, prm->iter_offset + 1, prm->iters, stats, nullptr)) != PD_OK)
         return rc;
@@ -1270,11 +1272,12 @@ extern "C" size_t pd_workspace_size(const pd_shape *shape, int32_t dtype)
     return layout(shape, dtype == PD_F64 ? 8 : 4).total;
 }
 
-extern "C" int pd_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op,
-                        const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
-                        const void *f0, void *z_cur, void *z_prev, int32_t init_from_f0,
-                        void *f_out, double *stats, void *workspace, size_t ws_bytes,
-                        void *stream)
+namespace {
+
+int solve_checked(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                  const pd_weights *w, const pd_params *prm, const void *f0, void *z_cur, void *z_prev,
+                  int32_t init_from_f0, void *f_out, double *stats, void *workspace, size_t ws_bytes,
+                  void *stream, bool eager)
 {
     int rc;
     if ((rc = check_shape(shape)) || (rc = check_dtype(dtype)) || (rc = check_op(op, shape)) ||
@@ -1285,10 +1288,66 @@ extern "C" int pd_solve(const pd_shape *shape, int32_t dtype, const pd_operator 
     if (dtype == PD_F32)
         return solve_impl<float>(shape, op, wav, w, prm, (const float *)f0, (float *)z_cur,
                                  (float *)z_prev, init_from_f0, (float *)f_out, stats, workspace,
-                                 ws_bytes, st);
+                                 ws_bytes, st, eager);
     return solve_impl<double>(shape, op, wav, w, prm, (const double *)f0, (double *)z_cur,
                               (double *)z_prev, init_from_f0, (double *)f_out, stats, workspace,
-                              ws_bytes, st);
+                              ws_bytes, st, eager);
+}
+
+// ------------------------------------------------------ allocation-free --
+// pd_solve_noalloc's scratch: a fixed device array in this library's code
+// object (one copy per GPU, alive until the process ends).  Host code never
+// passes `scratch` itself to a kernel (its host-side name is not a device
+// address): the device address is taken once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_BYTES = (size_t)PD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+int scratch_address(void **out)
+{
+    int dev = 0;
+    PD_TRY_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return PD_ERR_HIP;
+        }
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return PD_OK;
+}
+
+}  // namespace
+
+extern "C" int pd_solve(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                        const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                        const void *f0, void *z_cur, void *z_prev, int32_t init_from_f0,
+                        void *f_out, double *stats, void *workspace, size_t ws_bytes,
+                        void *stream)
+{
+    return solve_checked(shape, dtype, op, wav, w, prm, f0, z_cur, z_prev, init_from_f0, f_out, stats,
+                         workspace, ws_bytes, stream, false);
+}
+
+extern "C" int pd_solve_noalloc(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                                const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                                const void *f0, void *z_cur, void *z_prev, int32_t init_from_f0,
+                                void *f_out, double *stats, void *stream)
+{
+    int rc;
+    if ((rc = check_shape(shape)) || (rc = check_dtype(dtype))) return rc;
+    if (layout(shape, dtype == PD_F64 ? 8 : 4).total > NOALLOC_BYTES) return PD_ERR_WORKSPACE;
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws)) != PD_OK) return rc;
+    return solve_checked(shape, dtype, op, wav, w, prm, f0, z_cur, z_prev, init_from_f0, f_out, stats, ws,
+                         NOALLOC_BYTES, stream, true);
 }
 
 extern "C" int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wav, int32_t inverse,

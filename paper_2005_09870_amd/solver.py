@@ -215,6 +215,35 @@ def step_size(op: Operator, n1: int, n2: int, device="cuda") -> float:
     return 1.0 / (lipschitz(op, n1, n2, device=device) * (1.0 + 1e-6))
 
 
+def pd_solve_noalloc(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
+                     level_w=None, coeff_w: torch.Tensor | None = None, joint: bool = False,
+                     z_cur: torch.Tensor | None = None, z_prev: torch.Tensor | None = None,
+                     init: bool = True, iter_offset: int = 0, f_out: torch.Tensor | None = None,
+                     stats: torch.Tensor | None = None, check_finite: bool = False):
+    """pd_solve on the library's fixed scratch (no workspace argument, no
+    device allocation inside the call).  Every output buffer the caller does
+    not pass is allocated here, by torch, before the call."""
+    _check_dev(f0, coeff_w, z_cur, z_prev, f_out, stats)
+    shape = _shape(f0, levels)
+    wav, hh = _wavelet(h)
+    lw = None
+    if level_w is not None:
+        lw = np.ascontiguousarray(np.asarray(level_w, dtype=np.float64))
+        if lw.shape != (levels + 1,):
+            raise ValueError("level_w needs levels+1 entries")
+    w = C.pd_weights(_dptr(lw) if lw is not None else None,
+                     None if coeff_w is None else coeff_w.data_ptr(), 1 if joint else 0)
+    prm = C.pd_params(float(tau), int(iters), int(iter_offset), 1 if check_finite else 0)
+    z_cur = torch.empty_like(f0) if z_cur is None else z_cur
+    z_prev = torch.empty_like(f0) if z_prev is None else z_prev
+    opc = op.c()
+    rc = C.load().pd_solve_noalloc(ctypes.byref(shape), _dtype_code(f0.dtype), ctypes.byref(opc),
+                                   ctypes.byref(wav), ctypes.byref(w), ctypes.byref(prm), _ptr(f0), _ptr(z_cur),
+                                   _ptr(z_prev), 1 if init else 0, _ptr(f_out), _ptr(stats), _stream(f0.device))
+    C.check(rc, "pd_solve_noalloc")
+    return {"f": f_out, "z_cur": z_cur, "z_prev": z_prev, "stats": stats}
+
+
 # ----------------------------------------------------------------- batched ---
 def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, taus, h,
                      levels: list[int], iters: int, stats: bool = False, coeff_ws=None, joint: bool = False):

@@ -287,3 +287,26 @@ def test_batched_argument_errors_without_gpu_work():
     d = descs([(32, 1, 0, 0), (64, 1, 0, 1)])
     need = L.pd_batched_workspace_size(2, d, C.PD_F32)
     assert need > 0 and call(d, need - 1) == C.PD_ERR_WORKSPACE
+
+
+def test_noalloc_size_limit_without_gpu_work():
+    """pd_solve_noalloc rejects a problem whose workspace exceeds its fixed
+    scratch (PD_NOALLOC_SCRATCH_BYTES, 16 MiB) before touching the device."""
+    L = C.load()
+    h = S.pd_symmlet(6)
+    wav = C.pd_wavelet(12, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    big = C.pd_shape(2048, 2048, 1, 11)
+    small = C.pd_shape(1024, 1024, 1, 10)
+    assert L.pd_workspace_size(ctypes.byref(big), C.PD_F32) > (16 << 20)
+    assert L.pd_workspace_size(ctypes.byref(small), C.PD_F32) <= (16 << 20)
+    lw = np.zeros(12)
+    w = C.pd_weights(lw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, 0)
+    op = C.pd_operator(C.PD_OP_IDENTITY, 0, None)
+    prm = C.pd_params(0.5, 10, 0, 0)
+    rc = L.pd_solve_noalloc(ctypes.byref(big), C.PD_F32, ctypes.byref(op), ctypes.byref(wav), ctypes.byref(w),
+                            ctypes.byref(prm), _fake(1), _fake(2), _fake(3), 1, None, None, None)
+    assert rc == C.PD_ERR_WORKSPACE
+    bad = C.pd_shape(100, 64, 1, 3)
+    rc = L.pd_solve_noalloc(ctypes.byref(bad), C.PD_F32, ctypes.byref(op), ctypes.byref(wav), ctypes.byref(w),
+                            ctypes.byref(prm), _fake(1), _fake(2), _fake(3), 1, None, None, None)
+    assert rc == C.PD_ERR_SHAPE
