@@ -29,6 +29,11 @@ HBM_PEAK_GBS = 8000.0
 # FP32 FMA without packed instructions (which libpd does not emit): 256 CU x 4 SIMD x 16 lanes
 # x 2 FLOP x 2.4 GHz
 FP32_PEAK_TFLOPS = 78.6
+# Compulsory FP32 bytes per pixel-iteration of forward + backward with a per-coefficient weight map:
+# forward 24 (read z(i-1), z(i-2), f0, w; write z(i); in the (y, z_prev) form of the paper 20 + 4),
+# recompute 28 (the same + z(i) into the segment buffer), adjoint 40 (read zbar, zbar carry, z(i), w,
+# wbar, f0bar; write zbar, zbar carry, wbar, f0bar).
+FWD_BWD_BYTES = 92
 
 
 def log(msg: str) -> None:
@@ -299,6 +304,7 @@ def fwd_bwd(torch, P, SI, h, iters=200, count=16, n=256, ce=20, streams=4):
     rate = lambda dt: round(count * n * n * iters / dt / 1e6, 1)
     return {"workload": f"{count} x {n}^2 FP32, softplus weights, {iters} iterations, checkpoint {ce}",
             "fwd_bwd_mpx_it_s": rate(res["streams"][0]), "ms": round(1e3 * res["streams"][0], 2),
+            "alg_frac_92B": round(rate(res["streams"][0]) * 1e6 * FWD_BWD_BYTES / (HBM_PEAK_GBS * 1e9), 5),
             "streams": streams, "sequential_mpx_it_s": rate(res["seq"][0]),
             "sequential_ms": round(1e3 * res["seq"][0], 2), "bitwise_equal": same}
 
@@ -341,6 +347,8 @@ def fwd_bwd_512(torch, P, SI, h, iters=200, ce=20):
     rate = lambda dt: round(n * n * iters / dt / 1e6, 1)
     return {"workload": f"512^2 FP32, softplus weights, {iters} iterations, checkpoint {ce}",
             "fwd_bwd_mpx_it_s": rate(res["fwd_bwd"]), "fwd_mpx_it_s": rate(res["fwd"]),
+            "alg_frac_92B": round(rate(res["fwd_bwd"]) * 1e6 * FWD_BWD_BYTES / (HBM_PEAK_GBS * 1e9), 5),
+            "fwd_bwd_over_fwd": round(res["fwd_bwd"] / res["fwd"], 3),
             "ms_fwd_bwd": round(1e3 * res["fwd_bwd"], 2), "ms_fwd": round(1e3 * res["fwd"], 2)}
 
 

@@ -229,6 +229,29 @@ int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operator *op,
                 int32_t checkpoint_every, void *workspace, size_t ws_bytes,
                 void *stream);
 
+/* Forward solve that keeps what pd_backward needs: from the default initial
+ * guess, `prm->iters` iterations (iter_offset = 0, scalar prox) with
+ * (z(i), z(i-1)) stored at the start of every segment of `checkpoint_every`
+ * iterations in `workspace` (pd_backward_workspace_size bytes), and
+ * f_out (device [C][n2][n1]) = Psi z(iters), bitwise the f of pd_solve.  A
+ * following pd_backward_checkpointed with the same arguments and workspace
+ * then skips its own forward pass.  Errors as pd_backward. */
+int pd_solve_checkpointed(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                          const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                          const void *f0, void *f_out, int32_t checkpoint_every, void *workspace,
+                          size_t ws_bytes, void *stream);
+
+/* pd_backward reading the checkpoints that pd_solve_checkpointed stored in
+ * `workspace` (same shape, operator, weights, parameters and f0; the
+ * workspace untouched in between) instead of recomputing them: the same
+ * gradients bit for bit, one forward pass less.  The checkpoints are only
+ * read, so it may be called again for another grad_f.  Errors as pd_backward. */
+int pd_backward_checkpointed(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                             const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                             const void *f0, const void *grad_f, void *grad_f0, void *grad_w,
+                             int32_t checkpoint_every, void *workspace, size_t ws_bytes,
+                             void *stream);
+
 /* Building blocks, exposed for tests and for setting up a solve.            */
 
 /* Forward (inverse == 0: out = Psi^* in) or inverse (out = Psi in) periodic

@@ -10,6 +10,7 @@ from .solver import (  # noqa: F401
     FistaSolve,
     Operator,
     pd_backward,
+    pd_solve_checkpointed,
     solve_autograd,
     lipschitz,
     pd_admm_solve,

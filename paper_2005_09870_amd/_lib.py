@@ -61,7 +61,7 @@ class pd_image_desc(ctypes.Structure):
 # every symbol include/pd.h declares
 EXPORTS = [
     "pd_workspace_size", "pd_solve", "pd_solve_noalloc", "pd_batched_workspace_size", "pd_solve_batched",
-    "pd_backward_workspace_size", "pd_backward", "pd_fwt", "pd_apply_op", "pd_symmlet",
+    "pd_backward_workspace_size", "pd_backward", "pd_solve_checkpointed", "pd_backward_checkpointed", "pd_fwt", "pd_apply_op", "pd_symmlet",
     "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
     "pd_wsolve_workspace_size", "pd_wsolve", "pd_admm_workspace_size", "pd_admm_solve",
@@ -111,6 +111,11 @@ def load() -> ctypes.CDLL:
     L.pd_backward.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights),
                               P(pd_params), vp, vp, vp, vp, i32, vp, sz, vp]
     L.pd_backward.restype = ctypes.c_int
+    L.pd_solve_checkpointed.argtypes = [P(pd_shape), i32, P(pd_operator), P(pd_wavelet), P(pd_weights),
+                                        P(pd_params), vp, vp, i32, vp, sz, vp]
+    L.pd_solve_checkpointed.restype = ctypes.c_int
+    L.pd_backward_checkpointed.argtypes = L.pd_backward.argtypes
+    L.pd_backward_checkpointed.restype = ctypes.c_int
     L.pd_fwt.argtypes = [P(pd_shape), i32, P(pd_wavelet), i32, vp, vp, vp, sz, vp]
     L.pd_fwt.restype = ctypes.c_int
     L.pd_apply_op.argtypes = [P(pd_shape), i32, P(pd_operator), i32, vp, vp, vp]

@@ -1454,10 +1454,51 @@ BwdLayout bwd_layout(const pd_shape *sh, size_t es, int iters, int C)
     return b;
 }
 
+// The forward recursion from z(0) = Psi^* f0 with (z(i), z(i-1)) stored at
+// the start of every segment of C iterations in the checkpoint area of a
+// backward workspace.  With f_out, every segment is run and f = Psi z(K)
+// written; without, the last segment is left to the reverse sweep (which
+// recomputes it first anyway).
+template <typename T>
+int forward_checkpoints(const Ctx<T> &c, const BwdLayout &L, const pd_operator *op, const pd_weights *w, T tau,
+                        int K, int C, const T *f0, T *f_out)
+{
+    char *ws = c.ws;
+    const hipStream_t st = c.st;
+    const int64_t NC = c.N() * c.sh->channels;
+    const size_t plane = align_up(sizeof(T) * (size_t)NC);
+    T *zA = (T *)(ws + L.zc), *zB = (T *)(ws + L.zp);
+    auto ck = [&](int sidx, int k) { return (T *)(ws + L.ck + plane * (2 * (size_t)sidx + k)); };
+    int rc;
+    if ((rc = analysis_plain<T>(c, f0, zA)) != PD_OK) return rc;
+    PD_TRY_HIP(launch_copy<T>(zA, zB, NC, st));
+    T *zc = zA, *zp = zB;
+    for (int sidx = 0; sidx < L.nseg; ++sidx) {
+        PD_TRY_HIP(launch_copy<T>(zc, ck(sidx, 0), NC, st));
+        PD_TRY_HIP(launch_copy<T>(zp, ck(sidx, 1), NC, st));
+        const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
+        if (sidx == L.nseg - 1 && !f_out) break;
+        if ((rc = iterate<T>(c, op, w, tau, f0, zc, zp, i0, cnt, nullptr, nullptr)) != PD_OK) return rc;
+    }
+    if (f_out) return synth_chain<T>(c, zc, zc, T(0), f_out);  // zc = z(K)
+    return PD_OK;
+}
+
+template <typename T>
+int forward_ck_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
+                    const pd_params *prm, const T *f0, T *f_out, int C, void *workspace, size_t ws_bytes,
+                    hipStream_t st)
+{
+    const BwdLayout L = bwd_layout(sh, sizeof(T), prm->iters, C);
+    if (ws_bytes < L.total) return PD_ERR_WORKSPACE;
+    Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, 0);
+    return forward_checkpoints<T>(c, L, op, w, (T)prm->tau, prm->iters, C, f0, f_out);
+}
+
 template <typename T>
 int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav, const pd_weights *w,
                   const pd_params *prm, const T *f0, const T *gf, T *gf0, T *gw, int C, void *workspace,
-                  size_t ws_bytes, hipStream_t st)
+                  size_t ws_bytes, hipStream_t st, bool have_checkpoints)
 {
     const int K = prm->iters;
     BwdLayout L = bwd_layout(sh, sizeof(T), K, C);
@@ -1474,19 +1515,9 @@ int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *w
     const T tau = (T)prm->tau;
     int rc;
 
-    // forward with checkpoints
-    if ((rc = analysis_plain<T>(c, f0, zA)) != PD_OK) return rc;
-    PD_TRY_HIP(launch_copy<T>(zA, zB, NC, st));
-    {
-        T *zc = zA, *zp = zB;
-        for (int sidx = 0; sidx < L.nseg; ++sidx) {
-            PD_TRY_HIP(launch_copy<T>(zc, ck(sidx, 0), NC, st));
-            PD_TRY_HIP(launch_copy<T>(zp, ck(sidx, 1), NC, st));
-            const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
-            if (sidx == L.nseg - 1) break;  // the last segment is recomputed first anyway
-            if ((rc = iterate<T>(c, op, w, tau, f0, zc, zp, i0, cnt, nullptr, nullptr)) != PD_OK) return rc;
-        }
-    }
+    // forward with checkpoints (unless pd_solve_checkpointed left them in this workspace)
+    if (!have_checkpoints && (rc = forward_checkpoints<T>(c, L, op, w, tau, K, C, f0, nullptr)) != PD_OK)
+        return rc;
     // seeds
     if ((rc = analysis_plain<T>(c, gf, zbar)) != PD_OK) return rc;  // zbar(K) = Psi^* fbar
     PD_TRY_HIP(launch_fill<T>(zbarm, T(0), NC, st));
@@ -1543,16 +1574,19 @@ int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *w
             (void)hipGetLastError();
         }
     }
+    // every segment recomputes from a copy of its checkpoint in the working
+    // planes (the recursion runs in place), so the checkpoints stay intact for
+    // another reverse sweep (pd_backward_checkpointed)
     for (int sidx = L.nseg - 1; sidx >= 0; --sidx) {
         const int i0 = sidx * C + 1, cnt = std::min(C, K - sidx * C);
+        PD_TRY_HIP(launch_copy<T>(ck(sidx, 0), zA, NC, st));
+        PD_TRY_HIP(launch_copy<T>(ck(sidx, 1), zB, NC, st));
         if (seg_graph && sidx < L.nseg - 1) {
-            PD_TRY_HIP(launch_copy<T>(ck(sidx, 0), zA, NC, st));
-            PD_TRY_HIP(launch_copy<T>(ck(sidx, 1), zB, NC, st));
             PD_TRY_HIP(launch_set_int(c.it_dev(), i0, st));
             PD_TRY_HIP(hipGraphLaunch(seg_graph, st));
             continue;
         }
-        if ((rc = segment(c, ck(sidx, 0), ck(sidx, 1), i0, cnt, false)) != PD_OK) return rc;
+        if ((rc = segment(c, zA, zB, i0, cnt, false)) != PD_OK) return rc;
     }
     if (seg_graph) {  // retired: destroyed once its last launch has run
         hipEvent_t ev = nullptr;
@@ -1583,23 +1617,73 @@ extern "C" size_t pd_backward_workspace_size(const pd_shape *shape, int32_t dtyp
     return bwd_layout(shape, dtype == PD_F64 ? 8 : 4, iters, checkpoint_every).total;
 }
 
-extern "C" int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
-                           const pd_weights *w, const pd_params *prm, const void *f0, const void *grad_f,
-                           void *grad_f0, void *grad_w, int32_t checkpoint_every, void *workspace,
-                           size_t ws_bytes, void *stream)
+namespace {
+
+int check_backward(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                   const pd_weights *w, const pd_params *prm, const void *f0, int32_t checkpoint_every,
+                   void *workspace)
 {
     int rc;
     if ((rc = check_shape(shape)) || (rc = check_dtype(dtype)) || (rc = check_op(op, shape)) ||
         (rc = check_wavelet(wav)) || (rc = check_weights(w, shape)) || (rc = check_params(prm)))
         return rc;
-    if (!f0 || !grad_f || !workspace || checkpoint_every < 1) return PD_ERR_ARG;
+    if (!f0 || !workspace || checkpoint_every < 1) return PD_ERR_ARG;
     if (w->joint || prm->iter_offset != 0 || op->kind == PD_OP_PC) return PD_ERR_UNSUPPORTED;
+    return PD_OK;
+}
+
+int backward_checked(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                     const pd_weights *w, const pd_params *prm, const void *f0, const void *grad_f, void *grad_f0,
+                     void *grad_w, int32_t checkpoint_every, void *workspace, size_t ws_bytes, void *stream,
+                     bool have_checkpoints)
+{
+    int rc;
+    if ((rc = check_backward(shape, dtype, op, wav, w, prm, f0, checkpoint_every, workspace))) return rc;
+    if (!grad_f) return PD_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == PD_F32)
         return backward_impl<float>(shape, op, wav, w, prm, (const float *)f0, (const float *)grad_f,
-                                    (float *)grad_f0, (float *)grad_w, checkpoint_every, workspace, ws_bytes, st);
+                                    (float *)grad_f0, (float *)grad_w, checkpoint_every, workspace, ws_bytes, st,
+                                    have_checkpoints);
     return backward_impl<double>(shape, op, wav, w, prm, (const double *)f0, (const double *)grad_f,
-                                 (double *)grad_f0, (double *)grad_w, checkpoint_every, workspace, ws_bytes, st);
+                                 (double *)grad_f0, (double *)grad_w, checkpoint_every, workspace, ws_bytes, st,
+                                 have_checkpoints);
+}
+
+}  // namespace
+
+extern "C" int pd_backward(const pd_shape *shape, int32_t dtype, const pd_operator *op, const pd_wavelet *wav,
+                           const pd_weights *w, const pd_params *prm, const void *f0, const void *grad_f,
+                           void *grad_f0, void *grad_w, int32_t checkpoint_every, void *workspace,
+                           size_t ws_bytes, void *stream)
+{
+    return backward_checked(shape, dtype, op, wav, w, prm, f0, grad_f, grad_f0, grad_w, checkpoint_every, workspace,
+                            ws_bytes, stream, false);
+}
+
+extern "C" int pd_solve_checkpointed(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                                     const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                                     const void *f0, void *f_out, int32_t checkpoint_every, void *workspace,
+                                     size_t ws_bytes, void *stream)
+{
+    int rc;
+    if ((rc = check_backward(shape, dtype, op, wav, w, prm, f0, checkpoint_every, workspace))) return rc;
+    if (!f_out || f_out == f0) return PD_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == PD_F32)
+        return forward_ck_impl<float>(shape, op, wav, w, prm, (const float *)f0, (float *)f_out, checkpoint_every,
+                                      workspace, ws_bytes, st);
+    return forward_ck_impl<double>(shape, op, wav, w, prm, (const double *)f0, (double *)f_out, checkpoint_every,
+                                   workspace, ws_bytes, st);
+}
+
+extern "C" int pd_backward_checkpointed(const pd_shape *shape, int32_t dtype, const pd_operator *op,
+                                        const pd_wavelet *wav, const pd_weights *w, const pd_params *prm,
+                                        const void *f0, const void *grad_f, void *grad_f0, void *grad_w,
+                                        int32_t checkpoint_every, void *workspace, size_t ws_bytes, void *stream)
+{
+    return backward_checked(shape, dtype, op, wav, w, prm, f0, grad_f, grad_f0, grad_w, checkpoint_every, workspace,
+                            ws_bytes, stream, true);
 }
 
 // ------------------------------------------------------------------ ADMM-PC --

@@ -775,8 +775,10 @@ struct CLayout {
     }
 };
 
-// NCH: channels handled by the workgroup (the joint colour prox couples them).
-template <typename T, int NCH>
+// NCH: channels handled by the workgroup (the joint colour prox couples them);
+// JOINT: the prox is the joint (group) one -- a compile-time choice, so the
+// scalar kernel carries no code of the other.
+template <typename T, int NCH, bool JOINT>
 __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T> &lv, int bz)
 {
     using G = CGeom<T>;
@@ -794,7 +796,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     const int tid = threadIdx.x;
     const bool ana = (a.ops & COARSE_ANA) != 0, prox = (a.ops & COARSE_PROX) != 0;
     const bool need_z = !ana || prox;
-    const bool routed = NCH == 1 && ana && prox && (a.ops & COARSE_SYN) && a.kw > 0;
+    const bool routed = NCH == 1 && !JOINT && ana && prox && (a.ops & COARSE_SYN) && a.kw > 0;
     auto home = [&](int cc) { return lds + L.a + cc * m2 * G::PA; };
 
     // 1. every global load at once (clamped indices, no data-dependent branch):
@@ -828,8 +830,14 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
 #pragma unroll
     for (int k = 0; k < CPT; ++k) wr[k] = ld(p.wmap, use_w, (int64_t)ch0 * p.plane + gi[k]);
     __shared__ T wtab[PD_MAXL + 1];  // band weights, read per coefficient by the prox
-    if (tid <= PD_MAXL) wtab[tid] = p.wlev[tid];
+    if (tid <= PD_MAXL) {  // selects between scalar argument values: no per-lane argument load
+        T wv = uniform(p.wlev[0]);
+#pragma unroll
+        for (int k = 1; k <= PD_MAXL; ++k) wv = tid == k ? uniform(p.wlev[k]) : wv;
+        wtab[tid] = wv;
+    }
     constexpr int MPT = 2 * PD_TAIL_MAX * PD_TAIL_MAX / NTC;
+    static_assert(MPT * NTC == 2 * PD_TAIL_MAX * PD_TAIL_MAX, "tail matrix slots: every thread stores MPT");
     T mv[MPT];
     const int nm = a.tail ? 2 * tn * tn : 0;
 #pragma unroll
@@ -838,10 +846,8 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         mv[k] = ld(a.tail, nm > 0, e < nm ? e : 0);
     }
 #pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        const int e = tid + k * NTC;
-        if (e < nm) Mat[e] = mv[k];
-    }
+    for (int k = 0; k < MPT; ++k)  // unconditional (slots past 2 tn^2 are unused), so that no
+        Mat[tid + k * NTC] = mv[k];  // load is deferred into a branch behind a full wait
     // one channel with pass-by-pass levels: the analysis input goes straight
     // into C with its wrapped columns
     const bool in_c = NCH == 1 && ana && a.kw > 0;
@@ -882,16 +888,16 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         for (int k = 0; k < CPT; ++k) {
             if (tid + k * NTC >= cnt) continue;
             const int r = rr[k], c = cr[k];
-            // band weight: finest level of the block whose detail region holds (r, c)
-            int band = 0;
-            for (int lev = 0; lev < a.nlev; ++lev)
-                if (r >= (m2 >> (lev + 1)) || c >= (m1 >> (lev + 1))) {
-                    band = a.band_top - lev;
-                    break;
-                }
+            // band weight: the levels whose approximation region holds (r, c) are
+            // counted (branch-free); all of them -> the approximation band (k = 0),
+            // else the detail band of the first level that does not
+            int inside = 0;
+            for (int lev = 0; lev < a.nlev; ++lev)  // uniform trip count
+                inside += (r < (m2 >> (lev + 1))) & (c < (m1 >> (lev + 1)));
+            const int band = inside == a.nlev ? 0 : a.band_top - inside;
             const T wband = wtab[band];
             const int li = r * G::PA + c;
-            if (NCH == 1 && !p.joint) {
+            if (!JOINT) {
                 T *A = home(0);
                 T w = p.wmap ? wr[k] : wband;
                 T y = zcr[0][k] + lv.beta * (zcr[0][k] - zpr[0][k]);
@@ -1419,10 +1425,16 @@ __global__ __launch_bounds__(NT) void k_analysis(AnalysisArgs<T> a)
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTC) void k_coarse(CoarseArgs<T> a) { coarse_body<T, 1>(a, live_of<T>(a.p, a.beta_next), blockIdx.x); }
+__global__ __launch_bounds__(NTC) void k_coarse(CoarseArgs<T> a)
+{
+    coarse_body<T, 1, false>(a, live_of<T>(a.p, a.beta_next), blockIdx.x);
+}
 // joint colour: all NCH channels in one workgroup
 template <typename T, int NCH>
-__global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a) { coarse_body<T, NCH>(a, live_of<T>(a.p, a.beta_next), 0); }
+__global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a)
+{
+    coarse_body<T, NCH, true>(a, live_of<T>(a.p, a.beta_next), 0);
+}
 
 template <typename T>
 __global__ __launch_bounds__(NTB) void k_blur(BlurArgs<T> a)
@@ -1519,7 +1531,7 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
     } else {
         lv = live_of<T>(a.p, T(0));
     }
-    coarse_body<T, NCH>(a, lv, JOINT ? 0 : blockIdx.x - start[img]);
+    coarse_body<T, NCH, JOINT>(a, lv, JOINT ? 0 : blockIdx.x - start[img]);
 }
 
 template <typename T>

@@ -320,12 +320,7 @@ def pd_timing_read() -> list[dict]:
 
 
 # ---------------------------------------------------------------- backward ---
-def pd_backward(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
-                grad_f: torch.Tensor, level_w=None, coeff_w: torch.Tensor | None = None,
-                checkpoint_every: int = 20, want_f0: bool = True, want_w: bool = True):
-    """Reverse mode of pd_solve (init = Psi^* f0): returns (dL/df0, dL/dw) for
-    dL/df = grad_f.  dL/dw is per coefficient (Mallat layout)."""
-    _check_dev(f0, grad_f, coeff_w)
+def _bwd_args(f0, op, h, levels, tau, iters, level_w, coeff_w, checkpoint_every):
     dt = _dtype_code(f0.dtype)
     shape = _shape(f0, levels)
     wav, hh = _wavelet(h)
@@ -333,31 +328,70 @@ def pd_backward(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iter
     w = C.pd_weights(_dptr(lw) if lw is not None else None,
                      None if coeff_w is None else coeff_w.data_ptr(), 0)
     prm = C.pd_params(float(tau), int(iters), 0, 0)
-    gf0 = torch.empty_like(f0) if want_f0 else None
-    gw = torch.empty_like(f0) if want_w else None
-    L = C.load()
-    need = L.pd_backward_workspace_size(ctypes.byref(shape), dt, int(iters), int(checkpoint_every))
+    need = C.load().pd_backward_workspace_size(ctypes.byref(shape), dt, int(iters), int(checkpoint_every))
     if need == 0:
         raise C.PDError(C.PD_ERR_ARG, "pd_backward_workspace_size")
-    ws = workspace(need, f0.device)
+    return dt, shape, wav, (hh, lw), w, prm, need
+
+
+def pd_backward(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
+                grad_f: torch.Tensor, level_w=None, coeff_w: torch.Tensor | None = None,
+                checkpoint_every: int = 20, want_f0: bool = True, want_w: bool = True,
+                ws: torch.Tensor | None = None):
+    """Reverse mode of pd_solve (init = Psi^* f0): returns (dL/df0, dL/dw) for
+    dL/df = grad_f.  dL/dw is per coefficient (Mallat layout).  With ws from
+    pd_solve_checkpointed (same arguments), the stored checkpoints are used
+    (pd_backward_checkpointed) instead of a forward pass."""
+    _check_dev(f0, grad_f, coeff_w, ws)
+    dt, shape, wav, keep, w, prm, need = _bwd_args(f0, op, h, levels, tau, iters, level_w, coeff_w,
+                                                   checkpoint_every)
+    gf0 = torch.empty_like(f0) if want_f0 else None
+    gw = torch.empty_like(f0) if want_w else None
+    have = ws is not None
+    if ws is None:
+        ws = workspace(need, f0.device)
+    elif ws.numel() < need:
+        raise ValueError("workspace smaller than pd_backward_workspace_size")
     opc = op.c()
-    rc = L.pd_backward(ctypes.byref(shape), dt, ctypes.byref(opc), ctypes.byref(wav), ctypes.byref(w),
-                       ctypes.byref(prm), _ptr(f0), _ptr(grad_f.contiguous()), _ptr(gf0), _ptr(gw),
-                       int(checkpoint_every), _ptr(ws), ws.numel(), _stream(f0.device))
-    C.check(rc, "pd_backward")
+    fn = C.load().pd_backward_checkpointed if have else C.load().pd_backward
+    rc = fn(ctypes.byref(shape), dt, ctypes.byref(opc), ctypes.byref(wav), ctypes.byref(w),
+            ctypes.byref(prm), _ptr(f0), _ptr(grad_f.contiguous()), _ptr(gf0), _ptr(gw),
+            int(checkpoint_every), _ptr(ws), ws.numel(), _stream(f0.device))
+    C.check(rc, "pd_backward_checkpointed" if have else "pd_backward")
     return gf0, gw
+
+
+def pd_solve_checkpointed(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
+                          level_w=None, coeff_w: torch.Tensor | None = None, checkpoint_every: int = 20):
+    """Forward solve from Psi^* f0 keeping the reverse mode's checkpoints:
+    returns (f = Psi z(K), ws), ws to be passed to pd_backward."""
+    _check_dev(f0, coeff_w)
+    dt, shape, wav, keep, w, prm, need = _bwd_args(f0, op, h, levels, tau, iters, level_w, coeff_w,
+                                                   checkpoint_every)
+    ws = workspace(need, f0.device)
+    f = torch.empty_like(f0)
+    opc = op.c()
+    rc = C.load().pd_solve_checkpointed(ctypes.byref(shape), dt, ctypes.byref(opc), ctypes.byref(wav),
+                                        ctypes.byref(w), ctypes.byref(prm), _ptr(f0), _ptr(f),
+                                        int(checkpoint_every), _ptr(ws), ws.numel(), _stream(f0.device))
+    C.check(rc, "pd_solve_checkpointed")
+    return f, ws
 
 
 class FistaSolve(torch.autograd.Function):
     """f = Psi z(K) of pd_solve as a differentiable function of the observation
-    f0 and the per-coefficient weights w; the backward pass is pd_backward."""
+    f0 and the per-coefficient weights w.  The forward pass keeps the reverse
+    mode's checkpoints (pd_solve_checkpointed); the backward pass runs
+    pd_backward_checkpointed on them."""
 
     @staticmethod
     def forward(ctx, f0, w, op, h, levels, tau, iters, checkpoint_every):
         f0 = f0.contiguous()
         w = w.contiguous()
-        out = pd_solve(f0, op, h, levels, tau, iters, coeff_w=w)["f"]
+        out, ws = pd_solve_checkpointed(f0, op, h, levels, tau, iters, coeff_w=w,
+                                        checkpoint_every=checkpoint_every)
         ctx.save_for_backward(f0, w)
+        ctx.ws = ws
         ctx.cfg = (op, h, levels, tau, iters, checkpoint_every)
         return out
 
@@ -367,7 +401,7 @@ class FistaSolve(torch.autograd.Function):
         op, h, levels, tau, iters, ce = ctx.cfg
         gf0, gw = pd_backward(f0, op, h, levels, tau, iters, grad_f.contiguous(), coeff_w=w,
                               checkpoint_every=ce, want_f0=ctx.needs_input_grad[0],
-                              want_w=ctx.needs_input_grad[1])
+                              want_w=ctx.needs_input_grad[1], ws=ctx.ws)
         return gf0, gw, None, None, None, None, None, None
 
 

@@ -130,3 +130,23 @@ def test_autograd_function_matches_oracle():
     loss.backward()
     assert _rel(_np(f0t.grad), g0) < 1e-9
     assert _rel(_np(th.grad), gtheta) < 1e-9
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("K,ce", [(25, 7), (40, 20), (3, 5)])
+def test_checkpointed_forward_and_backward_are_bitwise(dtype, K, ce):
+    """pd_solve_checkpointed writes the f of pd_solve bit for bit and leaves
+    checkpoints from which pd_backward_checkpointed returns pd_backward's
+    gradients bit for bit (twice, for two seeds on one workspace)."""
+    pb, f0, c, h, kt, R = _case(n=48, seed=33)
+    tau = O.step_size(pb)
+    op = P.Operator.from_taps(kt, R, dtype=dtype)
+    f0t, wt = _t(f0, dtype), _t(pb.w, dtype)
+    f_ref = P.pd_solve(f0t, op, h, pb.levels, tau, K, coeff_w=wt)["f"]
+    f, ws = P.pd_solve_checkpointed(f0t, op, h, pb.levels, tau, K, coeff_w=wt, checkpoint_every=ce)
+    assert torch.equal(f, f_ref)
+    for seed in (0, 1):
+        fbar = _t(np.random.default_rng(seed).standard_normal(f0.shape), dtype)
+        a0, aw = P.pd_backward(f0t, op, h, pb.levels, tau, K, fbar, coeff_w=wt, checkpoint_every=ce)
+        b0, bw = P.pd_backward(f0t, op, h, pb.levels, tau, K, fbar, coeff_w=wt, checkpoint_every=ce, ws=ws)
+        assert torch.equal(a0, b0) and torch.equal(aw, bw), seed

@@ -372,3 +372,16 @@ def test_batched_weight_maps_and_joint_prox():
         f0m = [f0s[0], f0s[1][:1].contiguous()]
         P.pd_solve_batched(f0m, ops[:2], lws[:2], taus[:2], _h(), levels[:2], 5, joint=True)
     assert e.value.code == -7
+
+
+@pytest.mark.parametrize("n,levels", [(64, 6), (96, 5)])
+def test_joint_prox_single_channel(n, levels):
+    """The joint (group) prox with one channel, whose coarse block is done level
+    by level before the tail (the joint workgroup keeps the block in its home
+    array for the synthesis): against the oracle's joint prox."""
+    pb, f0, case = _problem(n, n, C=1, levels=levels, seed=95, joint=True)
+    tau = O.step_size(pb)
+    ref = O.fista(pb, f0, tau, 30)
+    out = _gpu_solve(pb, f0, case, tau, 30, torch.float64)
+    assert np.abs(_np(out["f"]) - ref["f"]).max() < 1e-10
+    assert np.abs(_np(out["z_cur"]) - ref["z"]).max() < 1e-10
