@@ -266,6 +266,21 @@ int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wav,
 int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operator *op,
                 int32_t transpose, const void *in, void *out, void *stream);
 
+/* Autotuning of the tile shape.  Times the tile-height variants of the fused
+ * blur (32 and 48 output rows per workgroup) for this size and operator on
+ * the caller's stream and records the fastest in a process-wide cache keyed
+ * by (n1, n2, channels, radius, dtype), which pd_solve, pd_solve_noalloc,
+ * pd_solve_checkpointed and pd_backward use from then on (32 rows for sizes
+ * never tuned).  Every variant computes each output by the same sums in the
+ * same order, so results do not depend on the choice.  workspace: at least
+ * pd_workspace_size bytes, used as scratch.  chosen (host, nullable): if it
+ * holds one of the variants on entry (32 or 48), that variant is recorded
+ * without timing; on return it holds the recorded height (0 for operators
+ * with no tile variants).  Synchronises the host with `stream` when timing.  Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_WORKSPACE,
+ * PD_ERR_UNSUPPORTED, PD_ERR_HIP. */
+int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *op, void *workspace,
+            size_t ws_bytes, int32_t *chosen, void *stream);
+
 /* Host: low-pass filter of the orthogonal wavelet with `moments` vanishing
  * moments and minimal support 2*moments whose phase is closest to linear
  * (the Symmlet family; Section 2.1 filter bank, Section 4.2 "Symmlet of order

@@ -26,6 +26,7 @@ from .solver import (  # noqa: F401
     pd_solve_batched,
     pd_solve_noalloc,
     pd_symmlet,
+    pd_tune,
     pd_workspace_size,
     pd_csr_transpose,
     pd_spmv,

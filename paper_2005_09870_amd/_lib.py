@@ -61,7 +61,7 @@ class pd_image_desc(ctypes.Structure):
 # every symbol include/pd.h declares
 EXPORTS = [
     "pd_workspace_size", "pd_solve", "pd_solve_noalloc", "pd_batched_workspace_size", "pd_solve_batched",
-    "pd_backward_workspace_size", "pd_backward", "pd_solve_checkpointed", "pd_backward_checkpointed", "pd_fwt", "pd_apply_op", "pd_symmlet",
+    "pd_backward_workspace_size", "pd_backward", "pd_solve_checkpointed", "pd_backward_checkpointed", "pd_fwt", "pd_apply_op", "pd_tune", "pd_symmlet",
     "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
     "pd_wsolve_workspace_size", "pd_wsolve", "pd_admm_workspace_size", "pd_admm_solve",
@@ -120,6 +120,8 @@ def load() -> ctypes.CDLL:
     L.pd_fwt.restype = ctypes.c_int
     L.pd_apply_op.argtypes = [P(pd_shape), i32, P(pd_operator), i32, vp, vp, vp]
     L.pd_apply_op.restype = ctypes.c_int
+    L.pd_tune.argtypes = [P(pd_shape), i32, P(pd_operator), vp, sz, P(i32), vp]
+    L.pd_tune.restype = ctypes.c_int
     L.pd_symmlet.argtypes = [i32, dp]
     L.pd_symmlet.restype = ctypes.c_int
     L.pd_op1_taps.argtypes = [i32, d, d, P(i32), dp]

@@ -971,7 +971,7 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         ba.slots = slots;
         ba.racc = nullptr;
         ba.rscale = T(0);
-        tiles_blur(n1, n2, &ba.tx, &ba.ty);
+        tiles_blur(n1, n2, &ba.tx, &ba.ty, 32);  // the batched blur runs the 32-row tile
         t_blur.add(ba, ba.tx * ba.ty * C);
         if (coarse) {
             CoarseArgs<T> ca;
@@ -1348,6 +1348,80 @@ extern "C" int pd_solve_noalloc(const pd_shape *shape, int32_t dtype, const pd_o
     if ((rc = scratch_address(&ws)) != PD_OK) return rc;
     return solve_checked(shape, dtype, op, wav, w, prm, f0, z_cur, z_prev, init_from_f0, f_out, stats, ws,
                          NOALLOC_BYTES, stream, true);
+}
+
+extern "C" int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *op, void *workspace,
+                       size_t ws_bytes, int32_t *chosen, void *stream)
+{
+    int rc;
+    if ((rc = check_shape(shape)) || (rc = check_dtype(dtype)) || (rc = check_op(op, shape))) return rc;
+    if (!workspace) return PD_ERR_ARG;
+    const size_t es = dtype == PD_F64 ? 8 : 4;
+    const Layout lay = layout(shape, es);
+    if (ws_bytes < lay.total) return PD_ERR_WORKSPACE;
+    const int pin = chosen ? *chosen : 0;
+    if (chosen) *chosen = 0;
+    if (op->kind != PD_OP_ROWBLUR) return PD_OK;  // nothing tunable for the other operators
+    for (int bt2 : BLUR_ROWS)
+        if (pin == bt2) {  // a variant named by the caller: recorded without timing
+            set_blur_rows(shape->n1, shape->n2, shape->channels, op->radius, (int)es, bt2);
+            *chosen = bt2;
+            return PD_OK;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    const int n1 = shape->n1, n2 = shape->n2, C = shape->channels, R = op->radius;
+    const int64_t NC = (int64_t)n1 * n2 * C;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct Events {
+        hipEvent_t &a, &b;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    PD_TRY_HIP(hipEventCreate(&e0));
+    PD_TRY_HIP(hipEventCreate(&e1));
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        // the blur of a zero plane into the solver's s plane (no statistics): timing only
+        T *x = (T *)(ws + lay.x), *sp = (T *)(ws + lay.s);
+        PD_TRY_HIP(launch_fill<T>(x, T(0), NC, st));
+        BlurArgs<T> a{};
+        a.x = x;
+        a.f0 = nullptr;
+        a.s = sp;
+        a.taps = (const T *)op->taps;
+        a.n1 = n1;
+        a.n2 = n2;
+        a.C = C;
+        a.R = R;
+        a.plane = (int64_t)n1 * n2;
+        a.slots = nullptr;
+        a.racc = nullptr;
+        a.rscale = T(0);
+        float best_ms = 0.0f;
+        int best = BLUR_ROWS[0];
+        for (int bt2 : BLUR_ROWS) {
+            set_blur_rows(n1, n2, C, R, (int)es, bt2);
+            for (int k = 0; k < 3; ++k) PD_TRY_HIP(launch_blur<T>(a, false, st));
+            PD_TRY_HIP(hipEventRecord(e0, st));
+            for (int k = 0; k < 10; ++k) PD_TRY_HIP(launch_blur<T>(a, false, st));
+            PD_TRY_HIP(hipEventRecord(e1, st));
+            PD_TRY_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            PD_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (bt2 == BLUR_ROWS[0] || ms < best_ms) {
+                best_ms = ms;
+                best = bt2;
+            }
+        }
+        set_blur_rows(n1, n2, C, R, (int)es, best);
+        if (chosen) *chosen = best;
+        return PD_OK;
+    };
+    return dtype == PD_F32 ? run(float(0)) : run(double(0));
 }
 
 extern "C" int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wav, int32_t inverse,

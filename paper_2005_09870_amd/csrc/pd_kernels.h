@@ -174,7 +174,12 @@ hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, in
                                    const int *it_dev, hipStream_t s);  // it_dev: it0 += *it_dev
 void tiles_synth(int M1c, int M2c, int *tx, int *ty);
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty);
-void tiles_blur(int n1, int n2, int *tx, int *ty);
+void tiles_blur(int n1, int n2, int *tx, int *ty, int bt2 = 32);
+// Blur tile height (rows of output per workgroup): BLUR_ROWS variants; the
+// launcher of the fused blur takes the tuned one for the size (32 untuned).
+constexpr int BLUR_ROWS[] = {32, 48};
+int blur_rows(int n1, int n2, int C, int R, int es);
+void set_blur_rows(int n1, int n2, int C, int R, int es, int bt2);
 hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s);
 // same with it0 = *it_dev - sub (graph replay)
 hipError_t launch_stats_finalize_dev(double *ring, double *stats, const int *it_dev, int sub, int count, hipStream_t s);

@@ -18,6 +18,10 @@
 // length <= 12 runs the same code.
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <map>
+#include <mutex>
+
 #include <cstdint>
 
 #include "pd_kernels.h"
@@ -1024,7 +1028,7 @@ __global__ void k_fill(T *dst, T v, int64_t n)
 //   r = Hx - f0
 //   u(x1,y2)  = sum_d k_{y2}[d] r(x1, y2+d)             (H^T: columns)
 //   s(y1,y2)  = sum_d k_{y2}[d] u(y1+d, y2)             (H^T: rows)
-// A workgroup produces a 32-row x 46-column tile of s, so the column passes
+// A workgroup produces a BT2-row x 46-column tile of s, so the column passes
 // work on exactly 64 columns: one wave64 per block of rows with lane = column,
 // which makes the row profiles wave-uniform (scalar loads).  Profiles narrower
 // than RM = 9 are zero-padded.
@@ -1032,31 +1036,42 @@ __global__ void k_fill(T *dst, T v, int64_t n)
 constexpr int RM = PD_MAX_RADIUS;
 constexpr int BW = 64;                 // columns of t, r, u
 constexpr int BT1 = BW - 2 * RM;       // 46 output columns
-constexpr int BT2 = 32;                // output rows
 constexpr int BX1 = BT1 + 4 * RM;      // 82 x columns
-constexpr int BX2 = BT2 + 4 * RM;      // 68 x / t rows
-constexpr int BR2 = BT2 + 2 * RM;      // 50 r rows
 constexpr int XP = 84;                 // LDS pitch of x (multiple of 4)
 constexpr int TP = 68;                 // LDS pitch of t, r, u (multiple of 4)
 constexpr int NTB = 512;               // blur workgroup: 8 waves (two per SIMD hide LDS latency)
 static_assert(BX1 <= 128 && BX1 > 64, "blur load columns");
-constexpr int RVH = 5;                 // rows per column task in the r pass (50 = 10 x 5)
-constexpr int UVH = 4;                 // rows per column task in the u pass (32 = 8 x 4)
-constexpr int RB_PER_WAVE = (BR2 / RVH + NTB / 64 - 1) / (NTB / 64);  // r-pass row blocks per wave
+constexpr int UVH = 4;                 // rows per column task in the u pass
 
-template <typename T>
+// Tile height variants (the tuned parameter; every output pixel is computed by
+// the same sums in the same order whatever the variant): BT2 output rows,
+// BX2 rows of x and t, BR2 rows of r, RVH rows per column task of the r pass.
+template <int BT2_>
+struct BlurGeom {
+    static constexpr int BT2 = BT2_;
+    static constexpr int BX2 = BT2 + 4 * RM;
+    static constexpr int BR2 = BT2 + 2 * RM;
+    static constexpr int RVH = BT2 == 32 ? 5 : 6;  // divides BR2 (50 = 10 x 5, 66 = 11 x 6)
+    static constexpr int RB_PER_WAVE = (BR2 / RVH + NTB / 64 - 1) / (NTB / 64);  // r-pass row blocks per wave
+    static_assert(BR2 % RVH == 0 && BT2 % UVH == 0, "blur pass blocking");
+};
+
+template <typename T, int BT2>
 struct BlurLds {
-    alignas(16) T sA[BX2 * XP];         // x, later r (BR2 x TP)
-    alignas(16) T sB[BX2 * TP];         // t, later u (BT2 x TP)
-    alignas(16) T sK[BX2][2 * RM + 2];  // profiles of the rows of x / t
-    alignas(16) T sKT[BR2][2 * RM + 2]; // by output row of H: sKT[q][RM+d] = profile of source row q+RM-d at d
+    using G = BlurGeom<BT2>;
+    alignas(16) T sA[G::BX2 * XP];         // x, later r (BR2 x TP)
+    alignas(16) T sB[G::BX2 * TP];         // t, later u (BT2 x TP)
+    alignas(16) T sK[G::BX2][2 * RM + 2];  // profiles of the rows of x / t
+    alignas(16) T sKT[G::BR2][2 * RM + 2]; // by output row of H: sKT[q][RM+d] = profile of source row q+RM-d at d
 };
 
 // The four passes on a staged tile (profiles zero-padded to RM).
-template <typename T>
-__device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, int bz, BlurLds<T> &lds,
-                                          const T (&f0pre)[RB_PER_WAVE][RVH])
+template <typename T, int BT2>
+__device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, int bz, BlurLds<T, BT2> &lds,
+                                          const T (&f0pre)[BlurGeom<BT2>::RB_PER_WAVE][BlurGeom<BT2>::RVH])
 {
+    using G = BlurGeom<BT2>;
+    constexpr int BX2 = G::BX2, BR2 = G::BR2, RVH = G::RVH, RB_PER_WAVE = G::RB_PER_WAVE;
     T *__restrict__ sA = lds.sA;
     T *__restrict__ sB = lds.sB;
     T(*__restrict__ sK)[2 * RM + 2] = lds.sK;
@@ -1177,10 +1192,12 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 
 // Stages the x tile and the row profiles in LDS (with f0 prefetched for the
 // r pass), then runs the passes.
-template <typename T>
+template <typename T, int BT2>
 __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, int bz)
 {
-    __shared__ BlurLds<T> lds;
+    using G = BlurGeom<BT2>;
+    constexpr int BX2 = G::BX2, BR2 = G::BR2, RVH = G::RVH, RB_PER_WAVE = G::RB_PER_WAVE;
+    __shared__ BlurLds<T, BT2> lds;
     T *__restrict__ sA = lds.sA;
     T(*__restrict__ sK)[2 * RM + 2] = lds.sK;
     const int n1 = a.n1, n2 = a.n2, R = a.R, W = 2 * R + 1;
@@ -1243,7 +1260,7 @@ __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, 
         }
     }
     __syncthreads();
-    blur_body<T>(a, bx, by, bz, lds, f0pre);
+    blur_body<T, BT2>(a, bx, by, bz, lds, f0pre);
 }
 
 // H = Id: s = r = x - f0.
@@ -1436,12 +1453,12 @@ __global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a)
     coarse_body<T, NCH, true>(a, live_of<T>(a.p, a.beta_next), 0);
 }
 
-template <typename T>
+template <typename T, int BT2>
 __global__ __launch_bounds__(NTB) void k_blur(BlurArgs<T> a)
 {
     const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
     if (t < 0) return;
-    blur_tile<T>(a, t % a.tx, t / a.tx, blockIdx.y);
+    blur_tile<T, BT2>(a, t % a.tx, t / a.tx, blockIdx.y);
 }
 
 __device__ __forceinline__ int locate(const int *__restrict__ start, int n, int blk)
@@ -1546,7 +1563,7 @@ __global__ __launch_bounds__(NTB) void k_blur_b(const BlurArgs<T> *__restrict__ 
     int loc = g - start[img];
     const int bx = loc % a.tx;
     loc /= a.tx;
-    blur_tile<T>(a, bx, loc % a.ty, loc / a.ty);
+    blur_tile<T, 32>(a, bx, loc % a.ty, loc / a.ty);
 }
 
 // ------------------------------------------------------------ launchers ---
@@ -1614,8 +1631,12 @@ hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s)
         hipLaunchKernelGGL(k_identity<T>, dim3(blocks), dim3(NT), 0, s, a);
     } else {
         BlurArgs<T> b = a;
-        tiles_blur(a.n1, a.n2, &b.tx, &b.ty);
-        hipLaunchKernelGGL(k_blur<T>, dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
+        const int bt2 = blur_rows(a.n1, a.n2, a.C, a.R, (int)sizeof(T));
+        tiles_blur(a.n1, a.n2, &b.tx, &b.ty, bt2);
+        if (bt2 == 48)
+            hipLaunchKernelGGL((k_blur<T, 48>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
+        else
+            hipLaunchKernelGGL((k_blur<T, 32>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
     }
     return hipGetLastError();
 }
@@ -1748,7 +1769,31 @@ PD_INST_REV(double)
 
 void tiles_synth(int M1c, int M2c, int *tx, int *ty) { *tx = (M1c + SP - 1) / SP; *ty = (M2c + SP - 1) / SP; }
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty) { *tx = (M1c + TC - 1) / TC; *ty = (M2c + TC - 1) / TC; }
-void tiles_blur(int n1, int n2, int *tx, int *ty) { *tx = (n1 + BT1 - 1) / BT1; *ty = (n2 + BT2 - 1) / BT2; }
+// The autotuning cache: the blur tile height chosen by pd_tune per
+// (n1, n2, channels, radius, element size); 32 rows where nothing was tuned.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int, 5>, int> g_blur_rows;
+}  // namespace
+
+int blur_rows(int n1, int n2, int C, int R, int es)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_blur_rows.find({n1, n2, C, R, es});
+    return it == g_blur_rows.end() ? 32 : it->second;
+}
+
+void set_blur_rows(int n1, int n2, int C, int R, int es, int bt2)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_blur_rows[{n1, n2, C, R, es}] = bt2;
+}
+
+void tiles_blur(int n1, int n2, int *tx, int *ty, int bt2)
+{
+    *tx = (n1 + BT1 - 1) / BT1;
+    *ty = (n2 + bt2 - 1) / bt2;
+}
 
 hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s)
 {

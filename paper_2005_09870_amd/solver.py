@@ -215,6 +215,21 @@ def step_size(op: Operator, n1: int, n2: int, device="cuda") -> float:
     return 1.0 / (lipschitz(op, n1, n2, device=device) * (1.0 + 1e-6))
 
 
+def pd_tune(f0: torch.Tensor, op: Operator, levels: int, pin: int = 0) -> int:
+    """Autotune the blur tile for f0's size and this operator (cached in the
+    library for later solves of the same size); returns the chosen tile height
+    (0: nothing to tune).  pin = 32 or 48 records that variant untimed."""
+    _check_dev(f0)
+    shape = _shape(f0, levels)
+    ws = workspace(pd_workspace_size(shape, f0.dtype), f0.device)
+    ch = ctypes.c_int32(int(pin))
+    opc = op.c()
+    rc = C.load().pd_tune(ctypes.byref(shape), _dtype_code(f0.dtype), ctypes.byref(opc), _ptr(ws), ws.numel(),
+                          ctypes.byref(ch), _stream(f0.device))
+    C.check(rc, "pd_tune")
+    return int(ch.value)
+
+
 def pd_solve_noalloc(f0: torch.Tensor, op: Operator, h, levels: int, tau: float, iters: int,
                      level_w=None, coeff_w: torch.Tensor | None = None, joint: bool = False,
                      z_cur: torch.Tensor | None = None, z_prev: torch.Tensor | None = None,

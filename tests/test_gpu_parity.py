@@ -385,3 +385,25 @@ def test_joint_prox_single_channel(n, levels):
     out = _gpu_solve(pb, f0, case, tau, 30, torch.float64)
     assert np.abs(_np(out["f"]) - ref["f"]).max() < 1e-10
     assert np.abs(_np(out["z_cur"]) - ref["z"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("n1,n2,C", [(512, 512, 1), (160, 96, 3)])
+def test_blur_tile_variants_are_bitwise(n1, n2, C):
+    """Every tile-height variant of the fused blur gives the same iterates bit
+    for bit (the autotuner's choice never changes results); pd_tune records
+    a variant and reports it."""
+    pb, f0, case = _problem(n1, n2, C=C, seed=97)
+    f0t = _t(f0, torch.float32)
+    op = _op(pb, torch.float32)
+    outs = {}
+    for bt2 in (32, 48):
+        assert P.pd_tune(f0t, op, pb.levels, pin=bt2) == bt2
+        outs[bt2] = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w, stats=True)
+    for k in ("f", "z_cur", "z_prev"):
+        assert torch.equal(outs[32][k], outs[48][k]), k
+    np.testing.assert_allclose(_np(outs[32]["stats"]), _np(outs[48]["stats"]), rtol=1e-12)
+    chosen = P.pd_tune(f0t, op, pb.levels)
+    assert chosen in (32, 48)
+    again = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w)
+    assert torch.equal(again["f"], outs[32]["f"])
+    P.pd_tune(f0t, op, pb.levels, pin=32)
