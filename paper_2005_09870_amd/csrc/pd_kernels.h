@@ -115,6 +115,16 @@ struct CoarseArgs {
     ProxArgs<T> p;          // in PLAIN analysis (ops == ANA) zn receives coefficients
 };
 
+// The joint prox on a coarse block (m1 x m2 at the top left of each channel's
+// Mallat plane) from the coefficients g that a per-channel coarse analysis
+// wrote at their Mallat positions of a scratch plane.
+template <typename T>
+struct CoarseJProxArgs {
+    const T *g;             // [C][n2][n1] scratch plane (block positions only)
+    int m1, m2, nlev, band_top;
+    ProxArgs<T> p;          // zc, zp, zn, beta, tau, weights, slots, flag, di
+};
+
 // Fused r = H x - f0, s = H^T r (or a single pass for the building block).
 template <typename T>
 struct BlurArgs {
@@ -152,6 +162,7 @@ struct Dyn {
 template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s);
 template <typename T> hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s);
+template <typename T> hipError_t launch_coarse_jprox(const CoarseJProxArgs<T> &a, int nch, hipStream_t s);
 template <typename T> size_t coarse_lds_bytes(int m1, int m2, int chans);
 template <typename T> hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s);
 template <typename T> hipError_t launch_blur_single(const BlurArgs<T> &a, int transpose, hipStream_t s);

@@ -122,6 +122,28 @@ __device__ void block_slot_add(double (&v)[NV], double *slots)
     }
 }
 
+// y = a + beta (a - b), the momentum step, as one explicit fused multiply-add, so
+// that every kernel forming a y from the same two iterates gets the same bits.
+template <typename T>
+__device__ __forceinline__ T momentum(T a, T b, T beta)
+{
+    return fma(beta, a - b, a);
+}
+
+// A product rounded on its own (never fused into a later add): the joint prox's
+// z feeds both its store and, in the coarse kernel, the next y, which must be
+// formed from the stored (rounded) z as a later launch would form it.
+__device__ __forceinline__ float mul_rn(float a, float b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double mul_rn(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+
 // Soft threshold S_t(v) = sign(v) max(|v| - t, 0), zero on |v| <= t.
 template <typename T>
 __device__ __forceinline__ T soft(T v, T t)
@@ -200,7 +222,7 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, const Live<T> 
         const int R = wv + i * (NT / 64);
         const bool bottom = R >= SR;
         const int r = bottom ? R - SR : R;
-        if (lok) sB[(hi1 ? 1 : 0) + (bottom ? 2 : 0)][r][lc_] = va[i] + lv.beta * (va[i] - vb[i]);
+        if (lok) sB[(hi1 ? 1 : 0) + (bottom ? 2 : 0)][r][lc_] = momentum(va[i], vb[i], lv.beta);
     }
     __syncthreads();
 
@@ -417,7 +439,7 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
         const T wband = b == 0 ? uniform(p.wlev[0]) : uniform(p.wlev[a.band_detail]);
         if (!JOINT) {
             T w = p.wmap ? wr[o] : wband;
-            T y = zcr[0][o] + lv.beta * (zcr[0][o] - zpr[0][o]);
+            T y = momentum(zcr[0][o], zpr[0][o], lv.beta);
             lv.zn[(int64_t)ch0 * p.plane + idx] = prox1(y, res[0][2 * q + hx2], p.tau, w, st, bad);
         } else {
             T yv[NC], vv[NC];
@@ -425,7 +447,7 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
             double ny = 0.0;
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
-                yv[cc] = zcr[cc][o] + lv.beta * (zcr[cc][o] - zpr[cc][o]);
+                yv[cc] = momentum(zcr[cc][o], zpr[cc][o], lv.beta);
                 vv[cc] = yv[cc] - p.tau * res[cc][2 * q + hx2];
                 nv = fma(vv[cc], vv[cc], nv);
                 ny += (double)yv[cc] * (double)yv[cc];
@@ -438,7 +460,7 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
             st[0] += (double)w * sqrt(ny);
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
-                T z = vv[cc] * sc;
+                T z = mul_rn(vv[cc], sc);
                 lv.zn[(int64_t)cc * p.plane + idx] = z;
                 st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
             }
@@ -865,7 +887,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                     copies(cr[k] + G::HA, m1, 0, m1 + 2 * G::HA + 2, [&](int q) { Cb[rr[k] * G::PC + q] = x; });
                 } else {
                     home(cc)[rr[k] * G::PA + cr[k]] =
-                        ana ? v[cc][k] : zcr[cc][k] + lv.beta * (zcr[cc][k] - zpr[cc][k]);
+                        ana ? v[cc][k] : momentum(zcr[cc][k], zpr[cc][k], lv.beta);
                 }
             }
     __syncthreads();
@@ -904,10 +926,10 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
             if (!JOINT) {
                 T *A = home(0);
                 T w = p.wmap ? wr[k] : wband;
-                T y = zcr[0][k] + lv.beta * (zcr[0][k] - zpr[0][k]);
+                T y = momentum(zcr[0][k], zpr[0][k], lv.beta);
                 T z = prox1(y, A[li], p.tau, w, st, bad);
                 lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
-                const T yn = z + lv.beta_next * (z - zcr[0][k]);
+                const T yn = momentum(z, zcr[0][k], lv.beta_next);
                 if (!routed || (a.kw < a.nlev && r < a.tM2 && c < a.tM1)) {
                     A[li] = yn;  // the tail's input (or the whole block)
                 } else {  // straight into the synthesis input of the level that reads it
@@ -925,7 +947,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 double ny = 0.0;
 #pragma unroll
                 for (int cc = 0; cc < NCH; ++cc) {
-                    yv[cc] = zcr[cc][k] + lv.beta * (zcr[cc][k] - zpr[cc][k]);
+                    yv[cc] = momentum(zcr[cc][k], zpr[cc][k], lv.beta);
                     vv[cc] = yv[cc] - p.tau * home(cc)[li];
                     nv = fma(vv[cc], vv[cc], nv);
                     ny += (double)yv[cc] * (double)yv[cc];
@@ -938,10 +960,10 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 st[0] += (double)w * sqrt(ny);
 #pragma unroll
                 for (int cc = 0; cc < NCH; ++cc) {
-                    T z = vv[cc] * sc;
+                    T z = mul_rn(vv[cc], sc);
                     lv.zn[(int64_t)cc * p.plane + gi[k]] = z;
                     st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
-                    home(cc)[li] = z + lv.beta_next * (z - zcr[cc][k]);
+                    home(cc)[li] = momentum(z, zcr[cc][k], lv.beta_next);
                 }
             }
         }
@@ -1453,6 +1475,57 @@ __global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a)
     coarse_body<T, NCH, true>(a, live_of<T>(a.p, a.beta_next), 0);
 }
 
+// The joint (group) prox on the coarse block as its own element-wise launch,
+// between a per-channel coarse analysis (coefficients g in a scratch plane at
+// their Mallat positions) and a per-channel coarse synthesis of y(i+1): the
+// same formulas as the joint branch of coarse_body, over many workgroups.
+template <typename T, int NCH>
+__global__ __launch_bounds__(NT) void k_coarse_jprox(CoarseJProxArgs<T> a)
+{
+    const ProxArgs<T> &p = a.p;
+    const Live<T> lv = live_of<T>(p, T(0));
+    const int cnt = a.m1 * a.m2;
+    double st[2] = {0.0, 0.0};
+    bool bad = false;
+    const int e = blockIdx.x * NT + threadIdx.x;
+    if (e < cnt) {
+        int r, c;
+        split(e, a.m1, r, c);
+        int inside = 0;
+        for (int lev = 0; lev < a.nlev; ++lev)  // uniform trip count
+            inside += (r < (a.m2 >> (lev + 1))) & (c < (a.m1 >> (lev + 1)));
+        const int band = inside == a.nlev ? 0 : a.band_top - inside;
+        T w = p.wlev[0];
+#pragma unroll
+        for (int k = 1; k <= PD_MAXL; ++k) w = band == k ? p.wlev[k] : w;  // selects, no per-lane argument load
+        const int64_t gi = (int64_t)r * p.pitch + c;
+        T yv[NCH], vv[NCH];
+        T nv = T(0);
+        double ny = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc) {
+            const T zc = lv.zc[(int64_t)cc * p.plane + gi], zp = lv.zp[(int64_t)cc * p.plane + gi];
+            yv[cc] = momentum(zc, zp, lv.beta);
+            vv[cc] = yv[cc] - p.tau * a.g[(int64_t)cc * p.plane + gi];
+            nv = fma(vv[cc], vv[cc], nv);
+            ny += (double)yv[cc] * (double)yv[cc];
+        }
+        T nrm = sqrt(nv);
+        T sc = nrm > T(0) ? T(1) - p.tau * w / nrm : T(0);
+        sc = sc > T(0) ? sc : T(0);
+        bad |= !isfinite(nrm);
+        st[0] += (double)w * sqrt(ny);
+#pragma unroll
+        for (int cc = 0; cc < NCH; ++cc) {
+            T z = mul_rn(vv[cc], sc);
+            lv.zn[(int64_t)cc * p.plane + gi] = z;
+            st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
+        }
+    }
+    if (bad) atomicOr(p.flag, 1);
+    if (lv.slots) block_slot_add<2, NT>(st, lv.slots + PD_NSLOT);
+}
+
 template <typename T, int BT2>
 __global__ __launch_bounds__(NTB) void k_blur(BlurArgs<T> a)
 {
@@ -1601,6 +1674,20 @@ size_t coarse_lds_bytes(int m1, int m2, int chans)
 {
     if (m1 > CGeom<T>::CM || m2 > CGeom<T>::CM) return SIZE_MAX;
     return sizeof(T) * (size_t)CLayout<T>(m1, m2, chans).total;
+}
+
+template <typename T>
+hipError_t launch_coarse_jprox(const CoarseJProxArgs<T> &a, int nch, hipStream_t s)
+{
+    const dim3 grid((a.m1 * a.m2 + NT - 1) / NT);
+    switch (nch) {
+    case 1: hipLaunchKernelGGL((k_coarse_jprox<T, 1>), grid, dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_coarse_jprox<T, 2>), grid, dim3(NT), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_coarse_jprox<T, 3>), grid, dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_coarse_jprox<T, 4>), grid, dim3(NT), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -1817,6 +1904,7 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
     template hipError_t launch_synth<T>(const SynthArgs<T> &, int, hipStream_t);           \
     template hipError_t launch_analysis<T>(const AnalysisArgs<T> &, hipStream_t);          \
     template hipError_t launch_coarse<T>(const CoarseArgs<T> &, int, hipStream_t);         \
+    template hipError_t launch_coarse_jprox<T>(const CoarseJProxArgs<T> &, int, hipStream_t); \
     template size_t coarse_lds_bytes<T>(int, int, int);                                    \
     template hipError_t launch_blur<T>(const BlurArgs<T> &, bool, hipStream_t);            \
     template hipError_t launch_blur_single<T>(const BlurArgs<T> &, int, hipStream_t);      \

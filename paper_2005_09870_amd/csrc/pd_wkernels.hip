@@ -229,7 +229,7 @@ __global__ __launch_bounds__(NTW) void k_wprox(WProxArgs<T> a)
                 st[0] += (double)w * fabs((double)y[j]);
                 st[1] += ((double)z - (double)y[j]) * ((double)z - (double)y[j]);
                 a.zn[r[j]] = z;
-                a.y[r[j]] = z + a.beta_next * (z - zc[j]);
+                a.y[r[j]] = fma(a.beta_next, z - zc[j], z);  // y(i+1), one explicit fma
             }
         }
     } else {
@@ -265,7 +265,7 @@ template <typename T>
 __global__ void k_wform_y(const T *zc, const T *zp, T beta, T *y, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = zc[i] + beta * (zc[i] - zp[i]);
+    if (i < n) y[i] = fma(beta, zc[i] - zp[i], zc[i]);  // as the fused product
 }
 
 // ---------------------------------------------------------------- transpose --
