@@ -480,8 +480,9 @@ typedef enum {
                            forward rows/columns, 2/3 inverse rows/columns)     */
     PD_K_ADMM = 9,      /* ADMM-PC element-wise steps (level 1 spectral, 2 f and
                            multipliers, 3 zeta and z)                          */
-    PD_K_DECOMP = 10    /* Algorithm 1: level 0 probe convolutions, 1 multiplier,
+    PD_K_DECOMP = 10,   /* Algorithm 1: level 0 probe convolutions, 1 multiplier,
                            2 spreading of B_k columns over A~_k, 3 count, 4 fill */
+    PD_K_SYNTH2 = 11    /* two synthesis levels in one launch (level = the finer) */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */
@@ -504,6 +505,11 @@ int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *l
  * launch has completed).  Off while timing is enabled and in pd_backward's
  * recomputation.  Process-wide; not thread-safe. */
 int pd_graphs_enable(int32_t enable);
+
+/* Fusion of the two coarsest fine synthesis levels into one launch (default
+ * on; results are bitwise the same either way).  Process-wide; not
+ * thread-safe. */
+int pd_fuse_enable(int32_t enable);
 
 /* Short description of a pd_status code. */
 const char *pd_strerror(int32_t status);

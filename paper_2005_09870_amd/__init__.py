@@ -21,6 +21,7 @@ from .solver import (  # noqa: F401
     pd_fft2,
     pd_fwt,
     pd_graphs_enable,
+    pd_fuse_enable,
     pd_op1_taps,
     pd_solve,
     pd_solve_batched,

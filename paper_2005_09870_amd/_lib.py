@@ -62,7 +62,7 @@ class pd_image_desc(ctypes.Structure):
 EXPORTS = [
     "pd_workspace_size", "pd_solve", "pd_solve_noalloc", "pd_batched_workspace_size", "pd_solve_batched",
     "pd_backward_workspace_size", "pd_backward", "pd_solve_checkpointed", "pd_backward_checkpointed", "pd_fwt", "pd_apply_op", "pd_tune", "pd_symmlet",
-    "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable",
+    "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable", "pd_fuse_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
     "pd_wsolve_workspace_size", "pd_wsolve", "pd_admm_workspace_size", "pd_admm_solve",
     "pd_fft2_workspace_size", "pd_fft2", "pd_decompose_workspace_size", "pd_decompose",
@@ -70,9 +70,9 @@ EXPORTS = [
 
 PD_K_BLUR, PD_K_SYNTH, PD_K_ANALYSIS, PD_K_COARSE, PD_K_OTHER = 1, 2, 3, 4, 5
 PD_K_WRES, PD_K_WPROX = 6, 7
-PD_K_FFT, PD_K_ADMM, PD_K_DECOMP = 8, 9, 10
+PD_K_FFT, PD_K_ADMM, PD_K_DECOMP, PD_K_SYNTH2 = 8, 9, 10, 11
 KCLASS_NAMES = {1: "blur", 2: "synthesis", 3: "analysis", 4: "coarse", 5: "other",
-                6: "wres", 7: "wprox", 8: "fft", 9: "admm", 10: "decomp"}
+                6: "wres", 7: "wprox", 8: "fft", 9: "admm", 10: "decomp", 11: "synthesis2"}
 
 _lib = None
 
@@ -128,6 +128,8 @@ def load() -> ctypes.CDLL:
     L.pd_op1_taps.restype = ctypes.c_int
     L.pd_timing_enable.argtypes = [i32]
     L.pd_timing_enable.restype = ctypes.c_int
+    L.pd_fuse_enable.argtypes = [i32]
+    L.pd_fuse_enable.restype = ctypes.c_int
     L.pd_graphs_enable.argtypes = [i32]
     L.pd_graphs_enable.restype = ctypes.c_int
     L.pd_timing_read.argtypes = [i32, P(i32), P(i32), P(ctypes.c_int64), dp, P(i32)]

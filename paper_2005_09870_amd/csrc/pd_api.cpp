@@ -24,6 +24,8 @@ using namespace pd;
 
 namespace {
 
+bool g_synth2 = true;  // the two coarsest fine synthesis levels in one launch (pd_fuse_enable)
+
 bool is_pow2_divisible(int n, int L) { return L >= 0 && L < 31 && (n % (1 << L)) == 0; }
 
 int check_shape(const pd_shape *s)
@@ -314,7 +316,7 @@ template <typename T>
 int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIter di = DevIter{nullptr, 0})
 {
     const int L = c.sh->levels, n1 = c.sh->n1, n2 = c.sh->n2;
-    for (int lev = c.lc - 1; lev >= 1; --lev) {
+    auto args = [&](int lev) {
         SynthArgs<T> a;
         a.f = c.f;
         a.zc = zc;
@@ -330,6 +332,16 @@ int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIte
         a.out_plane = lev == 1 ? c.N() : (int64_t)(n1 >> (lev - 1)) * (n2 >> (lev - 1));
         a.M1c = n1 >> lev;
         a.M2c = n2 >> lev;
+        return a;
+    };
+    int lev = c.lc - 1;
+    if (lev >= 2 && g_synth2) {  // the two coarsest fine levels in one launch
+        const SynthArgs<T> u = args(lev), d = args(lev - 1);
+        PD_TRY_HIP(timed(PD_K_SYNTH2, lev - 1, c.st, [&] { return launch_synth2<T>(d, u, c.sh->channels, c.st); }));
+        lev -= 2;
+    }
+    for (; lev >= 1; --lev) {
+        const SynthArgs<T> a = args(lev);
         PD_TRY_HIP(timed(PD_K_SYNTH, lev, c.st, [&] { return launch_synth<T>(a, c.sh->channels, c.st); }));
     }
     return PD_OK;
@@ -1246,6 +1258,12 @@ extern "C" int pd_solve_batched(int32_t batch, const pd_image_desc *descs, int32
                                       (double *)f_out_packed, stats, workspace, ws_bytes, st);
 }
 
+
+extern "C" int pd_fuse_enable(int32_t enable)
+{
+    g_synth2 = enable != 0;
+    return PD_OK;
+}
 
 extern "C" int pd_graphs_enable(int32_t enable)
 {

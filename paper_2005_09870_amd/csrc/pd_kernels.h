@@ -160,6 +160,10 @@ struct Dyn {
 };
 
 template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s);
+// two synthesis levels in one launch: d = the finer level, u = the next coarser
+// (its output, d's approximation band, stays in LDS; u.out is not written)
+template <typename T>
+hipError_t launch_synth2(const SynthArgs<T> &d, const SynthArgs<T> &u, int C, hipStream_t s);
 template <typename T> hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s);
 template <typename T> hipError_t launch_coarse_jprox(const CoarseJProxArgs<T> &a, int nch, hipStream_t s);

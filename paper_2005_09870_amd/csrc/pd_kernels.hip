@@ -282,6 +282,175 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, const Live<T> 
 }
 
 // ===========================================================================
+// Two synthesis levels in one launch: the coarser level U = D + 1 and the finer
+// level D.  A workgroup produces the same 32 x 32 tile of level D's output as
+// synth_body, computing the 26 x 26 part of level D's approximation band it
+// reads (the output of level U) from a 24 x 24 region of level U's bands in
+// LDS instead of reading it from memory.  Every output is formed by the same
+// sums in the same order as the two single-level launches, so the results are
+// the same bits; the saving is one launch and one round trip to memory.
+// ===========================================================================
+constexpr int UQ = SP / 2 + 6;   // level-U output pairs per axis (14): outputs [p0 - 6, p0 + 22)
+constexpr int UR = UQ + 10;      // level-U band positions per axis (24)
+constexpr int UO = 2 * UQ;       // level-U outputs per axis (28)
+
+template <typename T>
+__device__ __forceinline__ void synth2_body(const SynthArgs<T> &d, const SynthArgs<T> &u, const Live<T> &lv, int bx,
+                                            int by, int bz)
+{
+    __shared__ T sU[4][UR][UR + 1];   // level U: LL, HL, LH, HH
+    __shared__ T sUL[2][UO][UR + 1];  // level U after x2: low / high along x1
+    __shared__ T sB[4][SR][SR + 1];   // level D: LL (= level U's output), HL, LH, HH
+    __shared__ T sLH[2][SF][SR + 1];  // level D after x2
+    const int64_t ch = bz;
+    const int p01 = bx * SP, p02 = by * SP;  // level-D coarse tile origin
+    const int P01 = p01 / 2 - 3, P02 = p02 / 2 - 3;  // level-U output pair origin
+    const T *zc = lv.zc + ch * d.plane;
+    const T *zp = lv.zp + ch * d.plane;
+    const T *apx = u.apx ? u.apx + ch * u.apx_plane : nullptr;
+    const int tid = threadIdx.x;
+    const int M1u = u.M1c, M2u = u.M2c, M1d = d.M1c, M2d = d.M2c;
+
+    // every load up front: the four level-U bands (24 x 24 from position P0 - 5) and the three
+    // level-D detail bands (26 x 26 from position p0 - 5); y = z(i-1) + beta (z(i-1) - z(i-2))
+    constexpr int NU = 4 * UR * UR, ND = 3 * SR * SR, NL = (NU + ND + NT - 1) / NT;
+    T va[NL], vb[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        int e = tid + k * NT;
+        e = e < NU + ND ? e : 0;  // past the end: an in-range duplicate, unused
+        int64_t idx;
+        bool from_apx = false;
+        if (e < NU) {
+            const int b = e / (UR * UR), rem = e - b * (UR * UR), r = rem / UR, c = rem - r * UR;
+            const int q2 = wrap(P02 - 5 + r, M2u), q1 = wrap(P01 - 5 + c, M1u);
+            from_apx = b == 0 && apx;
+            idx = from_apx ? (int64_t)q2 * M1u + q1
+                           : (int64_t)(q2 + (b >= 2 ? M2u : 0)) * d.pitch + q1 + ((b & 1) ? M1u : 0);
+        } else {
+            const int e2 = e - NU, b = 1 + e2 / (SR * SR), rem = e2 - (b - 1) * (SR * SR), r = rem / SR,
+                      c = rem - r * SR;
+            const int q2 = wrap(p02 - 5 + r, M2d), q1 = wrap(p01 - 5 + c, M1d);
+            idx = (int64_t)(q2 + (b >= 2 ? M2d : 0)) * d.pitch + q1 + ((b & 1) ? M1d : 0);
+        }
+        va[k] = (from_apx ? apx : zc)[idx];
+        vb[k] = (from_apx ? apx : zp)[idx];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int e = tid + k * NT;
+        if (e >= NU + ND) continue;
+        const T y = momentum(va[k], vb[k], lv.beta);
+        if (e < NU) {
+            const int b = e / (UR * UR), rem = e - b * (UR * UR), r = rem / UR, c = rem - r * UR;
+            sU[b][r][c] = y;
+        } else {
+            const int e2 = e - NU, b = 1 + e2 / (SR * SR), rem = e2 - (b - 1) * (SR * SR), r = rem / SR,
+                      c = rem - r * SR;
+            sB[b][r][c] = y;
+        }
+    }
+    __syncthreads();
+
+    // level U along x2: task = (band pair, column c, output pair q)
+    for (int t = tid; t < 2 * UR * UQ; t += NT) {
+        const int band = t / (UR * UQ), rem = t - band * (UR * UQ), q = rem / UR, c = rem - q * UR;
+        T lo[6], hi[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            lo[j] = sU[band][q + j][c];
+            hi[j] = sU[band + 2][q + 5 + j][c];
+        }
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                acc = fma(u.f.h[par + 10 - 2 * j], lo[j], acc);
+                acc = fma(u.f.g[par - 2 * j + 10], hi[j], acc);
+            }
+            sUL[band][2 * q + par][c] = acc;
+        }
+    }
+    __syncthreads();
+    // level U along x1, into the approximation band of level D (output n <-> sB row / column n - (p0 - 5))
+    for (int t = tid; t < UO * UQ; t += NT) {
+        const int f = t / UQ, q = t - f * UQ;
+        T lo[6], hi[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            lo[j] = sUL[0][f][q + j];
+            hi[j] = sUL[1][f][q + 5 + j];
+        }
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                acc = fma(u.f.h[par + 10 - 2 * j], lo[j], acc);
+                acc = fma(u.f.g[par - 2 * j + 10], hi[j], acc);
+            }
+            const int r = f - 1, c = 2 * q + par - 1;
+            if (r >= 0 && r < SR && c >= 0 && c < SR) sB[0][r][c] = acc;
+        }
+    }
+    __syncthreads();
+
+    // level D: the passes of synth_body
+    for (int t = tid; t < 2 * SR * (SP / 4); t += NT) {
+        int band = t / (SR * (SP / 4)), rem = t - band * SR * (SP / 4);
+        int blk = rem / SR, c = rem - blk * SR;
+        const int bl = band, bh = band + 2;
+        T lo[9], hi[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            lo[j] = sB[bl][4 * blk + j][c];
+            hi[j] = sB[bh][4 * blk + 5 + j][c];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    acc = fma(d.f.h[par + 10 - 2 * j], lo[q + j], acc);
+                    acc = fma(d.f.g[par - 2 * j + 10], hi[q + j], acc);
+                }
+                sLH[band][8 * blk + 2 * q + par][c] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    T *out = d.out + ch * d.out_plane;
+    const int M1 = 2 * M1d, M2 = 2 * M2d;
+    for (int t = tid; t < SF * (SP / 2); t += NT) {
+        int f = t / (SP / 2), blk = t - f * (SP / 2);
+        T lo[7], hi[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            lo[j] = sLH[0][f][2 * blk + j];
+            hi[j] = sLH[1][f][2 * blk + 5 + j];
+        }
+        const int o2 = 2 * p02 + f;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    acc = fma(d.f.h[par + 10 - 2 * j], lo[q + j], acc);
+                    acc = fma(d.f.g[par - 2 * j + 10], hi[q + j], acc);
+                }
+                const int o1 = 2 * p01 + 4 * blk + 2 * q + par;
+                if (o2 < M2 && o1 < M1) out[(int64_t)o2 * d.out_pitch + o1] = acc;
+            }
+        }
+    }
+}
+
+// ===========================================================================
 // Analysis of one fine level (Section 2.1):
 //   lo[l] = sum_{k=0}^{11} h[k] in[2l+k],  hi[l] = sum_{k=-10}^{1} g[k] in[2l+k]
 // along x1 then x2.  A workgroup produces a 16 x 16 tile of each band from a
@@ -1446,6 +1615,16 @@ __global__ __launch_bounds__(NT) void k_synth(SynthArgs<T> a)
 }
 
 template <typename T>
+__global__ __launch_bounds__(NT) void k_synth2(SynthArgs<T> d, SynthArgs<T> u)
+{
+    const T beta = d.di.it_dev ? beta_at<T>(*d.di.it_dev + d.di.it_off) : d.beta;
+    const Live<T> lv{d.zc, d.zp, nullptr, beta, T(0), nullptr};
+    const int t = xcd_tile(d.tx * d.ty);  // channel = blockIdx.y
+    if (t < 0) return;
+    synth2_body<T>(d, u, lv, t % d.tx, t / d.tx, blockIdx.y);
+}
+
+template <typename T>
 __device__ __forceinline__ Live<T> live_of(const ProxArgs<T> &p, T beta_next)
 {
     if (p.di.it_dev) {
@@ -1640,6 +1819,15 @@ __global__ __launch_bounds__(NTB) void k_blur_b(const BlurArgs<T> *__restrict__ 
 }
 
 // ------------------------------------------------------------ launchers ---
+template <typename T>
+hipError_t launch_synth2(const SynthArgs<T> &d, const SynthArgs<T> &u, int C, hipStream_t s)
+{
+    SynthArgs<T> b = d;
+    tiles_synth(d.M1c, d.M2c, &b.tx, &b.ty);
+    hipLaunchKernelGGL(k_synth2<T>, dim3(xcd_grid(b.tx * b.ty), C), dim3(NT), 0, s, b, u);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s)
 {
@@ -1903,6 +2091,7 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
 #define PD_INST(T)                                                                          \
     template hipError_t launch_synth<T>(const SynthArgs<T> &, int, hipStream_t);           \
     template hipError_t launch_analysis<T>(const AnalysisArgs<T> &, hipStream_t);          \
+    template hipError_t launch_synth2<T>(const SynthArgs<T> &, const SynthArgs<T> &, int, hipStream_t); \
     template hipError_t launch_coarse<T>(const CoarseArgs<T> &, int, hipStream_t);         \
     template hipError_t launch_coarse_jprox<T>(const CoarseJProxArgs<T> &, int, hipStream_t); \
     template size_t coarse_lds_bytes<T>(int, int, int);                                    \

@@ -308,6 +308,11 @@ def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, tau
 
 
 # ------------------------------------------------------------- diagnostics ---
+def pd_fuse_enable(enable: bool = True) -> None:
+    """Fusion of the two coarsest fine synthesis levels into one launch (bitwise-identical results)."""
+    C.check(C.load().pd_fuse_enable(1 if enable else 0), "pd_fuse_enable")
+
+
 def pd_graphs_enable(enable: bool = True) -> None:
     """Graph replay of pd_solve's middle iterations (bitwise-identical results)."""
     C.check(C.load().pd_graphs_enable(1 if enable else 0), "pd_graphs_enable")

@@ -407,3 +407,28 @@ def test_blur_tile_variants_are_bitwise(n1, n2, C):
     again = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w)
     assert torch.equal(again["f"], outs[32]["f"])
     P.pd_tune(f0t, op, pb.levels, pin=32)
+
+
+@pytest.mark.parametrize("n1,n2,C,levels", [(512, 512, 1, 9), (160, 96, 2, 5), (256, 128, 1, 3), (1024, 64, 1, 6),
+                                             (512, 256, 1, 2)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_fused_synthesis_levels_are_bitwise(n1, n2, C, levels, dtype):
+    """The two coarsest fine synthesis levels in one launch give the same
+    iterates, statistics aside, bit for bit as two launches (and pd_fwt's
+    inverse transform the same output)."""
+    pb, f0, case = _problem(n1, n2, C=C, levels=levels, seed=99)
+    f0t = _t(f0, dtype)
+    op = _op(pb, dtype)
+    outs = {}
+    try:
+        for fuse in (True, False):
+            P.pd_fuse_enable(fuse)
+            outs[fuse] = (P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 30, level_w=case.level_w),
+                          P.pd_fwt(f0t, _h(), pb.levels, inverse=True))
+    finally:
+        P.pd_fuse_enable(True)
+    for k in ("f", "z_cur", "z_prev"):
+        assert torch.equal(outs[True][0][k], outs[False][0][k]), k
+    assert torch.equal(outs[True][1], outs[False][1])
+    ref = O.fista(pb, f0, 0.85, 30)
+    assert np.abs(_np(outs[True][0]["f"]) - ref["f"]).max() < (1e-10 if dtype == torch.float64 else 1e-5)
