@@ -369,7 +369,7 @@ def colour_case(torch, P, SI, h, iters, n=2048):
     tau = P.step_size(op, n, n, device=dev)
     shape = P.solver._shape(f0, c.levels)
     ws = P.solver.workspace(P.pd_workspace_size(shape, f0.dtype), f0.device)
-    blur_rows = P.pd_tune(f0, op, c.levels)
+    blur_variant = P.pd_tune(f0, op, c.levels)
 
     def run(k):
         return P.pd_solve(f0, op, h, c.levels, tau, k, level_w=c.level_w, joint=True, ws=ws, stats=True)
@@ -391,7 +391,7 @@ def colour_case(torch, P, SI, h, iters, n=2048):
     ach = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
     return {"workload": f"{n}x{n}x3 FP32 joint shrinkage, {iters} iterations",
             "mpx_it_s": round(3 * n * n * iters / dt / 1e6, 1), "ms_per_iter": round(1e3 * dt / iters, 4),
-            "tuned_blur_rows": blur_rows,
+            "tuned_blur": blur_variant,
             "alg_frac_20B": round(3 * n * n * iters / dt * 20 / (HBM_PEAK_GBS * 1e9), 5),
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom["kernel"] +
@@ -678,7 +678,7 @@ def main():
     h = P.pd_symmlet(6)
     case, op, f0, tau = make_problem(torch, P, SI)
     n = case.n1
-    blur_rows = P.pd_tune(f0, op, case.levels)  # the autotuner's blur tile for this size
+    blur_variant = P.pd_tune(f0, op, case.levels)  # the autotuner's blur variant for this size
     log(f"[bench] 512x512 FP32, {args.iters} iterations, tau={tau:.6f}, steps={args.steps}, warmup={args.warmup}")
     wall, ev_ms, r, step = time_forward(torch, P, case, op, f0, tau, args.iters, args.steps,
                                         args.warmup, h)
@@ -709,7 +709,7 @@ def main():
                                    "2000 FISTA iterations per step, FP64 energy reductions",
                        "iters": args.iters, "n1": n, "n2": n, "levels": case.levels},
             "roofline": roofline,
-            "tuned_blur_rows": blur_rows,
+            "tuned_blur": blur_variant,
             # the method's compulsory traffic in (y, z_prev) form -- read y, z_prev and f0, write z
             # and y+, 4 B each: 20 B per pixel-iteration -- at this rate, as a fraction of HBM peak
             "alg_frac_20B": round(value * 1e6 * 20 / (HBM_PEAK_GBS * 1e9), 5)}

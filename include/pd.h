@@ -266,18 +266,26 @@ int pd_fwt(const pd_shape *shape, int32_t dtype, const pd_wavelet *wav,
 int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operator *op,
                 int32_t transpose, const void *in, void *out, void *stream);
 
-/* Autotuning of the tile shape.  Times the tile-height variants of the fused
- * blur (32 and 48 output rows per workgroup) for this size and operator on
+/* Autotuning of the blur.  Times its variants for this size and operator on
  * the caller's stream and records the fastest in a process-wide cache keyed
  * by (n1, n2, channels, radius, dtype), which pd_solve, pd_solve_noalloc,
- * pd_solve_checkpointed and pd_backward use from then on (32 rows for sizes
- * never tuned).  Every variant computes each output by the same sums in the
- * same order, so results do not depend on the choice.  workspace: at least
- * pd_workspace_size bytes, used as scratch.  chosen (host, nullable): if it
- * holds one of the variants on entry (32 or 48), that variant is recorded
- * without timing; on return it holds the recorded height (0 for operators
- * with no tile variants).  Synchronises the host with `stream` when timing.  Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_WORKSPACE,
+ * pd_solve_checkpointed and pd_backward use from then on (variant 32 for
+ * sizes never tuned).  Variants (PD_BLUR_* codes): 32 and 48 = one fused
+ * kernel with that many output rows per workgroup; 1016, 1032 and 1064 = two
+ * kernels (r = H x - f0, then s = H^T r) whose waves walk down strips of
+ * 128 columns in blocks of 16, 32 or 64 rows.  Every variant computes each
+ * output by the same sums in the same order, so results do not depend on the
+ * choice.  workspace: at least pd_workspace_size bytes, used as scratch.
+ * chosen (host, nullable): if it holds one of the codes on entry, that
+ * variant is recorded without timing; on return it holds the recorded code
+ * (0 for operators with no variants).  Synchronises the host with `stream`
+ * when timing.  Errors: PD_ERR_ARG, PD_ERR_SHAPE, PD_ERR_WORKSPACE,
  * PD_ERR_UNSUPPORTED, PD_ERR_HIP. */
+#define PD_BLUR_TILE32 32
+#define PD_BLUR_TILE48 48
+#define PD_BLUR_SPLIT16 1016
+#define PD_BLUR_SPLIT32 1032
+#define PD_BLUR_SPLIT64 1064
 int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *op, void *workspace,
             size_t ws_bytes, int32_t *chosen, void *stream);
 

@@ -6,6 +6,7 @@ include/pd.h); this package only marshals torch device tensors into it.
 """
 from ._lib import PDError, load  # noqa: F401
 from .solver import (  # noqa: F401
+    BLUR_VARIANTS,
     Csr,
     FistaSolve,
     Operator,

@@ -95,10 +95,12 @@ Filt<T> make_filt(const pd_wavelet *w)
     return f;
 }
 
-// Workspace: approximation pyramid (levels 1..L-1), x, s, flag.
+// Workspace: approximation pyramid (levels 1..L-1), x, s, r (the two-kernel
+// blur's intermediate), the blur's profile tables, flag, statistics ring,
+// tail matrices, graph iteration number.
 struct Layout {
     size_t apx[PD_MAXL + 1];
-    size_t x, s, flag, slots, tail, it, total;
+    size_t x, s, r, btab, flag, slots, tail, it, total;
 };
 
 Layout layout(const pd_shape *s, size_t es)
@@ -116,6 +118,10 @@ Layout layout(const pd_shape *s, size_t es)
     off = align_up(off + plane);
     l.s = off;
     off = align_up(off + plane);
+    l.r = off;
+    off = align_up(off + plane);
+    l.btab = off;
+    off = align_up(off + 2 * (size_t)s->n2 * BLUR_TAB_PITCH * es);
     l.flag = off;
     off = align_up(off + 256);
     l.slots = off;
@@ -160,6 +166,7 @@ struct Ctx {
     bool eager = false;  // no graph replay (the allocation-free entry point)
     TailShape ts;
     const T *tail;  // device copy of the tail matrices (nullptr: none)
+    const T *btab = nullptr;  // the blur's profile tables once filled (prep_blur)
     int64_t N() const { return (int64_t)sh->n1 * sh->n2; }
     T *apx(int j) const { return (T *)(ws + lay.apx[j]); }
     T *x() const { return (T *)(ws + lay.x); }
@@ -413,6 +420,9 @@ int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T
     a.slots = slots;
     a.racc = racc;
     a.rscale = rscale;
+    a.r = c.btab ? (T *)(c.ws + c.lay.r) : nullptr;
+    a.tabs = c.btab;
+    a.rows = 0;
     if (op->kind == PD_OP_PC) {  // product-convolution expansion (no reverse-mode accumulation)
         if (racc) return PD_ERR_UNSUPPORTED;
         PcArgs<T> p{x, f0, s, (const T *)op->taps, (const T *)op->mult, c.sh->n1, c.sh->n2, c.sh->channels,
@@ -421,6 +431,18 @@ int blur_step(const Ctx<T> &c, const pd_operator *op, const T *x, const T *f0, T
         return PD_OK;
     }
     PD_TRY_HIP(timed(PD_K_BLUR, 0, c.st, [&] { return launch_blur<T>(a, op->kind == PD_OP_IDENTITY, c.st); }));
+    return PD_OK;
+}
+
+// Fills the per-row profile tables of the two-kernel blur (row blur only);
+// stream-ordered before the iterations that read them.
+template <typename T>
+int prep_blur(Ctx<T> &c, const pd_operator *op)
+{
+    if (op->kind != PD_OP_ROWBLUR) return PD_OK;
+    T *tab = (T *)(c.ws + c.lay.btab);
+    PD_TRY_HIP(launch_blur_tables<T>((const T *)op->taps, c.sh->n2, op->radius, tab, c.st));
+    c.btab = tab;
     return PD_OK;
 }
 
@@ -738,6 +760,7 @@ int solve_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *wav,
     c.eager = eager;
     const int64_t NC = c.N() * sh->channels;
     int rc;
+    if ((rc = prep_blur<T>(c, op)) != PD_OK) return rc;
     if (init) {
         if ((rc = analysis_plain<T>(c, f0, z_cur)) != PD_OK) return rc;
         PD_TRY_HIP(timed(PD_K_OTHER, 0, st, [&] { return launch_copy<T>(z_cur, z_prev, NC, st); }));
@@ -1401,10 +1424,10 @@ extern "C" int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *
     const int pin = chosen ? *chosen : 0;
     if (chosen) *chosen = 0;
     if (op->kind != PD_OP_ROWBLUR) return PD_OK;  // nothing tunable for the other operators
-    for (int bt2 : BLUR_ROWS)
-        if (pin == bt2) {  // a variant named by the caller: recorded without timing
-            set_blur_rows(shape->n1, shape->n2, shape->channels, op->radius, (int)es, bt2);
-            *chosen = bt2;
+    for (int v : BLUR_VARIANTS)
+        if (pin == v) {  // a variant named by the caller: recorded without timing
+            set_blur_variant(shape->n1, shape->n2, shape->channels, op->radius, (int)es, v);
+            *chosen = v;
             return PD_OK;
         }
     hipStream_t st = (hipStream_t)stream;
@@ -1440,10 +1463,14 @@ extern "C" int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *
         a.slots = nullptr;
         a.racc = nullptr;
         a.rscale = T(0);
+        a.r = (T *)(ws + lay.r);
+        a.tabs = (T *)(ws + lay.btab);
+        a.rows = 0;
+        PD_TRY_HIP(launch_blur_tables<T>((const T *)op->taps, n2, R, (T *)(ws + lay.btab), st));
         float best_ms = 0.0f;
-        int best = BLUR_ROWS[0];
-        for (int bt2 : BLUR_ROWS) {
-            set_blur_rows(n1, n2, C, R, (int)es, bt2);
+        int best = BLUR_VARIANTS[0];
+        for (int v : BLUR_VARIANTS) {
+            set_blur_variant(n1, n2, C, R, (int)es, v);
             for (int k = 0; k < 3; ++k) PD_TRY_HIP(launch_blur<T>(a, false, st));
             PD_TRY_HIP(hipEventRecord(e0, st));
             for (int k = 0; k < 10; ++k) PD_TRY_HIP(launch_blur<T>(a, false, st));
@@ -1451,12 +1478,12 @@ extern "C" int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *
             PD_TRY_HIP(hipEventSynchronize(e1));
             float ms = 0.0f;
             PD_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (bt2 == BLUR_ROWS[0] || ms < best_ms) {
+            if (v == BLUR_VARIANTS[0] || ms < best_ms) {
                 best_ms = ms;
-                best = bt2;
+                best = v;
             }
         }
-        set_blur_rows(n1, n2, C, R, (int)es, best);
+        set_blur_variant(n1, n2, C, R, (int)es, best);
         if (chosen) *chosen = best;
         return PD_OK;
     };
@@ -1605,6 +1632,8 @@ int forward_ck_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet 
     const BwdLayout L = bwd_layout(sh, sizeof(T), prm->iters, C);
     if (ws_bytes < L.total) return PD_ERR_WORKSPACE;
     Ctx<T> c = make_ctx<T>(sh, wav, workspace, st, 0);
+    int rc;
+    if ((rc = prep_blur<T>(c, op)) != PD_OK) return rc;
     return forward_checkpoints<T>(c, L, op, w, (T)prm->tau, prm->iters, C, f0, f_out);
 }
 
@@ -1627,6 +1656,7 @@ int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *w
     T *seg = (T *)(ws + L.seg);
     const T tau = (T)prm->tau;
     int rc;
+    if ((rc = prep_blur<T>(c, op)) != PD_OK) return rc;
 
     // forward with checkpoints (unless pd_solve_checkpointed left them in this workspace)
     if (!have_checkpoints && (rc = forward_checkpoints<T>(c, L, op, w, tau, K, C, f0, nullptr)) != PD_OK)

@@ -137,6 +137,9 @@ struct BlurArgs {
     int tx, ty;             // tiles along x1, x2 (batched launches)
     T *racc;                // reverse mode: racc += rscale * r (nullptr: off); f0 may be nullptr
     T rscale;
+    T *r;                   // plane for r = Hx - f0 of the two-kernel variant (nullptr: fused only)
+    const T *tabs;          // [2][n2][2 PD_MAX_RADIUS + 2] profile tables of that variant
+    int rows;               // rows per wave of that variant (set by the launcher)
 };
 
 // Values that change from iteration to iteration, passed by value so that the
@@ -190,11 +193,18 @@ hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, in
 void tiles_synth(int M1c, int M2c, int *tx, int *ty);
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty);
 void tiles_blur(int n1, int n2, int *tx, int *ty, int bt2 = 32);
-// Blur tile height (rows of output per workgroup): BLUR_ROWS variants; the
-// launcher of the fused blur takes the tuned one for the size (32 untuned).
-constexpr int BLUR_ROWS[] = {32, 48};
-int blur_rows(int n1, int n2, int C, int R, int es);
-void set_blur_rows(int n1, int n2, int C, int R, int es, int bt2);
+// Blur variants (the tuned choice per size; 32 where nothing was tuned):
+// 32, 48 = the fused tile kernel with that many output rows per workgroup;
+// BLUR_SPLIT + w = the two marching kernels with w rows per wave (needs
+// BlurArgs::r and ::tabs, else the fused 32-row kernel runs).  All variants
+// give the same results bit for bit.
+constexpr int BLUR_SPLIT = 1000;
+constexpr int BLUR_VARIANTS[] = {32, 48, BLUR_SPLIT + 16, BLUR_SPLIT + 32, BLUR_SPLIT + 64};
+int blur_variant(int n1, int n2, int C, int R, int es);
+void set_blur_variant(int n1, int n2, int C, int R, int es, int v);
+// per-row profile tables of the two-kernel variant: tab = [2][n2][2 PD_MAX_RADIUS + 2]
+template <typename T> hipError_t launch_blur_tables(const T *taps, int n2, int R, T *tab, hipStream_t s);
+constexpr int BLUR_TAB_PITCH = 2 * PD_MAX_RADIUS + 2;
 hipError_t launch_stats_finalize(double *ring, double *stats, int it0, int count, hipStream_t s);
 // same with it0 = *it_dev - sub (graph replay)
 hipError_t launch_stats_finalize_dev(double *ring, double *stats, const int *it_dev, int sub, int count, hipStream_t s);

@@ -23,6 +23,8 @@
 #include <mutex>
 
 #include <cstdint>
+#include <type_traits>
+#include <utility>
 
 #include "pd_kernels.h"
 
@@ -1713,6 +1715,408 @@ __global__ __launch_bounds__(NTB) void k_blur(BlurArgs<T> a)
     blur_tile<T, BT2>(a, t % a.tx, t / a.tx, blockIdx.y);
 }
 
+// ===========================================================================
+// The blur as two marching kernels (large planes).  The same four passes as
+// the tile kernel, every output the same sum in the same order, so results
+// agree with it bit for bit and the autotuner may pick either:
+//   k_blur_h : t = rows of x with the row's own profile, r = columns of t with
+//              the source rows' profiles, minus f0           x, f0 -> r
+//   k_blur_ht: u = columns of r with the output row's profile, s = rows of u
+//              with the same profile                         r -> s
+// A wave owns a strip of 128 columns (two neighbouring columns per lane) and
+// walks down a block of rows.  Each column pass keeps the last 2R+1 rows of
+// its input in registers (a sliding window: nothing is recomputed along x2
+// but the first 2R rows of t, and the columns need no LDS); each row pass
+// trades one row through a wave-private LDS row.  Profiles are wave-uniform:
+// they come from two per-row tables (the own profile, and the profiles
+// gathered by output row) through scalar loads.  Waves are independent; the
+// workgroup only shares the statistics reduction.
+// ===========================================================================
+constexpr int TABP = 2 * RM + 2;            // table pitch (taps d = -RM..RM, one pad)
+constexpr int SWS = 128;                    // strip width: columns of t, r, u
+constexpr int SOT = SWS - 2 * RM - 2;       // s columns per k_blur_ht strip (108, even)
+constexpr int NWS = 4;                      // waves per workgroup
+constexpr int WIN = 2 * RM + 1;             // window rows
+constexpr int SPF = 4;                      // rows loaded ahead of use
+constexpr int SRW = SWS + 2 * RM + 6;       // LDS row: columns c0-RM-1 .. c0+SWS+RM (+ pad to 16 bytes)
+static_assert(TABP % 4 == 0 && SRW % 4 == 0, "16-byte LDS rows");
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+    T v[4];
+};
+
+// Orders a wave's LDS writes before the reads of other lanes.  LDS
+// operations of one wave execute in order, so only the compiler has to be
+// kept from moving memory operations across this point (a plain load may be
+// moved across a fence, not across a memory clobber).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("" ::: "memory");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// tab[0][p][i]: profile of row p at d = i - RM; tab[1][p][i]: profile of row
+// p - d at d (the taps output row p of H gathers); zero where |d| > R.
+template <typename T>
+__global__ void k_blur_tables(const T *__restrict__ taps, int n2, int R, T *__restrict__ tab)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n2 * TABP) return;
+    const int p = e / TABP, i = e - p * TABP, d = i - RM;
+    const int W = 2 * R + 1;
+    const bool ok = i < WIN && d >= -R && d <= R;
+    T own = T(0), gat = T(0);
+    if (ok) {
+        own = taps[(int64_t)p * W + d + R];
+        gat = taps[(int64_t)wrap(p - d, n2) * W + d + R];
+    }
+    tab[e] = own;
+    tab[(int64_t)n2 * TABP + e] = gat;
+}
+
+// (strip, row block) of this wave, strips of `width` columns and blocks of
+// `rows` rows; workgroups in XCD-aware order (tx workgroups of items).
+__device__ __forceinline__ bool march_item(int width, int n1, int n2, int rows, int tx, int &c0, int &p0, int &np)
+{
+    const int t = xcd_tile(tx);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nblk = (n2 + rows - 1) / rows, items = ((n1 + width - 1) / width) * nblk;
+    const int item = t * NWS + wv;
+    if (t < 0 || item >= items) return false;
+    const int strip = item / nblk, blk = item - strip * nblk;
+    c0 = strip * width;
+    p0 = blk * rows;
+    np = n2 - p0 < rows ? n2 - p0 : rows;
+    return true;
+}
+
+// Copies table rows into the wave's LDS: local row q < na is row
+// wrap(pa + q) of table A, local row na + q (q < nb) is row pb + q of table B.
+template <typename T>
+__device__ __forceinline__ void stage_taps(const T *A, int pa, int na, const T *B, int pb, int nb, int n2, T *dst,
+                                           int lane)
+{
+    constexpr int CPR = TABP / 4;  // 16-byte chunks per row
+    const int total = (na + nb) * CPR;
+    for (int e0 = 0; e0 < total; e0 += 4 * 64) {
+        Quad<T> v[4];
+        int at[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {  // four loads in flight per lane
+            const int e = e0 + u * 64 + lane;
+            const int ee = e < total ? e : 0;
+            const int q = ee / CPR, c = ee - q * CPR;
+            const T *src = q < na ? A + (int64_t)wrap(pa + q, n2) * TABP : B + (int64_t)(pb + q - na) * TABP;
+            v[u] = reinterpret_cast<const Quad<T> *>(src)[c];
+            at[u] = e < total ? q * TABP + 4 * c : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (at[u] >= 0) *reinterpret_cast<Quad<T> *>(dst + at[u]) = v[u];
+    }
+}
+
+// The 2 RM + 1 taps of one LDS table row (wave-uniform address: broadcast reads).
+template <typename T>
+__device__ __forceinline__ void read_taps(const T *row, T (&k)[TABP])
+{
+#pragma unroll
+    for (int c = 0; c < TABP / 4; ++c) {
+        const Quad<T> q = reinterpret_cast<const Quad<T> *>(row)[c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k[4 * c + u] = q.v[u];
+    }
+}
+
+// 2 RM + 4 values lrow[2 lane .. 2 lane + 2 RM + 3] as aligned pairs (one
+// 2-element vector read each: consecutive lanes read consecutive pairs).
+template <typename T>
+__device__ __forceinline__ void read_row(const T *lrow, int lane, T (&v)[2 * RM + 4])
+{
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const V2 *p = reinterpret_cast<const V2 *>(__builtin_assume_aligned(lrow, 2 * sizeof(T)));
+#pragma unroll
+    for (int i = 0; i < RM + 2; ++i) {
+        const V2 q = p[lane + i];
+        v[2 * i] = q.x;
+        v[2 * i + 1] = q.y;
+    }
+}
+
+// LDS elements per wave: k_blur_h row (+ for LDS taps: own taps of the steps
+// padded to whole blocks of WIN plus one, gathered taps of the rows); k_blur_ht
+// row + own taps of the output rows.
+__host__ __device__ constexpr int pad_steps(int rows) { return (rows + 2 * RM + WIN - 1) / WIN * WIN; }
+template <typename T>
+__host__ __device__ constexpr int blur_h_lds(int rows)
+{
+    return SRW + (sizeof(T) == 4 ? 0 : (pad_steps(rows) + 1 + rows) * TABP);
+}
+__host__ __device__ constexpr int blur_ht_lds(int rows) { return SRW + rows * TABP; }
+
+// f(integral_constant<int, K>) for K = 0 .. N-1, in order (compile-time slots).
+template <typename F, int... K>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
+{
+    (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Row counter that walks down the periodic plane one row per step.
+__device__ __forceinline__ int next_row(int r, int n) { return r + 1 == n ? 0 : r + 1; }
+
+// Taps of one table row: FP32 rows come through scalar loads (wave-uniform
+// addresses; the values stay in scalar registers), FP64 rows from the
+// wave's LDS copy.
+template <typename T>
+using CT = const __attribute__((address_space(4))) T;
+template <typename T>
+constexpr bool scalar_taps() { return sizeof(T) == 4; }
+
+template <typename T>
+__device__ __forceinline__ void load_taps(const T *gtab, const T *ltab, int grow, int lrow_, T (&k)[TABP])
+{
+    if constexpr (scalar_taps<T>()) {
+        CT<T> *row = (CT<T> *)(gtab + (int64_t)grow * TABP);
+#pragma unroll
+        for (int i = 0; i < TABP; ++i) k[i] = row[i];
+    } else {
+        read_taps<T>(ltab + lrow_ * TABP, k);
+    }
+}
+
+// Steps run in unconditional blocks of WIN (the window slot of step j is
+// j mod WIN, and prefetched rows rotate without control flow, so no load in
+// flight is ever copied); steps past the block's last row compute values
+// that are not stored.  The first block (the warm-up of the column pass) is
+// peeled so that its conditions are static.  The next step's taps are
+// requested once this step's LDS data has arrived.
+template <typename T>
+__global__ __launch_bounds__(64 * NWS) void k_blur_h(BlurArgs<T> a)
+{
+    if (xcd_tile(a.tx) < 0) return;  // padding workgroup (uniform)
+    extern __shared__ __align__(16) unsigned char blur_lds[];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n1 = a.n1, n2 = a.n2;
+    double st[1] = {0.0};
+    int c0, p0, np;
+    if (march_item(SWS, n1, n2, a.rows, a.tx, c0, p0, np)) {
+        const int64_t ch = blockIdx.y;
+        const T *x = a.x + ch * a.plane;
+        const T *f0 = a.f0 ? a.f0 + ch * a.plane : x;
+        T *r = a.r + ch * a.plane;
+        T *racc = a.racc ? a.racc + ch * a.plane : nullptr;
+        const T *gown = a.tabs, *ggat = a.tabs + (int64_t)n2 * TABP;
+        T *lrow = reinterpret_cast<T *>(blur_lds) + wv * blur_h_lds<T>(a.rows);
+        const int nsteps = np + 2 * RM;  // t rows p0-RM .. p0+np-1+RM
+        const int nblk = (nsteps + WIN - 1) / WIN;
+        T *ltown = lrow + SRW;                 // (LDS taps) own profile of t row p0-RM+j at ltown[j]
+        T *ltgat = ltown + (nblk * WIN + 1) * TABP;  // gathered taps of r row p0+q at ltgat[q]
+        if constexpr (!scalar_taps<T>())
+            stage_taps<T>(gown, p0 - RM, nblk * WIN + 1, ggat, p0, np, n2, ltown, lane);
+        // LDS slot q holds x column c0-RM-1+q: lanes store slots 2 lane, 2 lane+1
+        // and (10 lanes) SWS + 2 lane, +1.  Columns come in even-aligned pairs.
+        const int qa = wrap(c0 - RM - 1 + 2 * lane, n1);
+        const bool hb = lane < (2 * RM + 2) / 2;
+        const int qb = wrap(c0 - RM - 1 + SWS + (hb ? 2 * lane : 0), n1);
+        const int cr = c0 + 2 * lane;  // this lane's r columns cr, cr + 1
+        const bool own = cr < n1;      // n1 is even: both or neither
+        const int crl = own ? cr : 0;
+        int xrow = wrap(p0 - RM, n2), frow = wrap(p0 - 2 * RM, n2);  // rows of the next loads
+        int trow = xrow;                                              // own-profile row of the next taps
+        Pair<T> xa[SPF], xb[SPF], fq[SPF];
+        auto load_next = [&](Pair<T> &va, Pair<T> &vb, Pair<T> &vf) {
+            const T *rowp = x + (int64_t)xrow * n1;
+            va = *reinterpret_cast<const Pair<T> *>(rowp + qa);
+            vb = *reinterpret_cast<const Pair<T> *>(rowp + qb);
+            vf = *reinterpret_cast<const Pair<T> *>(f0 + (int64_t)frow * n1 + crl);
+            xrow = next_row(xrow, n2);
+            frow = next_row(frow, n2);
+        };
+#pragma unroll
+        for (int q = 0; q < SPF; ++q) load_next(xa[q], xb[q], fq[q]);
+        T kt[TABP], kg[TABP];  // taps of the current step (t pass, r pass)
+        load_taps<T>(gown, ltown, trow, 0, kt);
+        trow = next_row(trow, n2);
+        // gathered taps of r row p0+q into kg (scalar taps; padded steps repeat
+        // the block's last row)
+        auto load_gat = [&](int q) {
+            q = q < np - 1 ? q : np - 1;
+            load_taps<T>(ggat, ltgat, p0 + q, q, kg);
+        };
+        T win[WIN][2];
+        if constexpr (!scalar_taps<T>()) wave_lds_sync();  // the staged taps
+        const int pend = p0 + np;
+        // step j in window slot k: t of row p0-RM+j; with_r: r of row p0+j-2RM
+        auto step = [&](int j, auto kc, auto rc, auto nc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr bool with_r = decltype(rc)::value, next_r = decltype(nc)::value;
+            const Pair<T> cx = xa[0], cxb = xb[0], cf = fq[0];
+#pragma unroll
+            for (int q = 0; q + 1 < SPF; ++q) {
+                xa[q] = xa[q + 1];
+                xb[q] = xb[q + 1];
+                fq[q] = fq[q + 1];
+            }
+            load_next(xa[SPF - 1], xb[SPF - 1], fq[SPF - 1]);
+            *reinterpret_cast<Pair<T> *>(lrow + 2 * lane) = cx;
+            if (hb) *reinterpret_cast<Pair<T> *>(lrow + SWS + 2 * lane) = cxb;
+            wave_lds_sync();
+            T xs[2 * RM + 4];
+            read_row<T>(lrow, lane, xs);  // xs[i] = x column cr - RM - 1 + i
+            wave_lds_sync();
+            // t of row p0-RM+j: rows pass with the row's own profile
+            T t0 = T(0), t1 = T(0);
+#pragma unroll
+            for (int m = 0; m <= 2 * RM; ++m) {
+                const T kk = kt[2 * RM - m];  // d = RM - m: t(c) = sum k[d] x(c - d)
+                t0 = fma(kk, xs[m + 1], t0);
+                t1 = fma(kk, xs[m + 2], t1);
+            }
+            // computed here, not sunk towards the (later) column pass: bounded lifetimes
+            __asm__ __volatile__("" : "+v"(t0), "+v"(t1));
+            win[k][0] = t0;
+            win[k][1] = t1;
+            load_taps<T>(gown, ltown, trow, j + 1, kt);  // the next step's own profile
+            trow = next_row(trow, n2);
+            T kr[TABP];  // this step's gathered taps
+            if constexpr (scalar_taps<T>()) {
+#pragma unroll
+                for (int i = 0; i < TABP; ++i) kr[i] = kg[i];
+                if (next_r) load_gat(j + 1 - 2 * RM);  // the next step's, requested early
+            } else if (with_r) {
+                const int q = j - 2 * RM < np - 1 ? j - 2 * RM : np - 1;
+                read_taps<T>(ltgat + q * TABP, kr);
+            }
+            if (with_r) {
+                // columns of t with the source rows' profiles, d = -RM..RM
+                // (t row p-d sits in slot (k + d - RM) mod WIN)
+                T r0 = T(0), r1 = T(0);
+#pragma unroll
+                for (int i = 0; i <= 2 * RM; ++i) {
+                    const int sl = (k - i + 2 * WIN) % WIN;
+                    r0 = fma(kr[i], win[sl][0], r0);
+                    r1 = fma(kr[i], win[sl][1], r1);
+                }
+                r0 = r0 - (a.f0 ? cf.a : T(0));
+                r1 = r1 - (a.f0 ? cf.b : T(0));
+                const int pr = p0 + j - 2 * RM;
+                if (own && pr < pend) {
+                    const int64_t o = (int64_t)pr * n1 + cr;
+                    *reinterpret_cast<Pair<T> *>(r + o) = Pair<T>{r0, r1};
+                    st[0] += 0.5 * (double)r0 * (double)r0;
+                    st[0] += 0.5 * (double)r1 * (double)r1;
+                    if (racc) {
+                        racc[o] = fma(a.rscale, r0, racc[o]);
+                        racc[o + 1] = fma(a.rscale, r1, racc[o + 1]);
+                    }
+                }
+            }
+        };
+        static_for<WIN>([&](auto kc) {  // warm-up block
+            constexpr int k = decltype(kc)::value;
+            step(k, kc, std::integral_constant<bool, (k >= 2 * RM)>{}, std::integral_constant<bool, (k + 1 >= 2 * RM)>{});
+        });
+        for (int base = WIN; base < nsteps; base += WIN)
+            static_for<WIN>([&](auto kc) {
+                step(base + decltype(kc)::value, kc, std::true_type{}, std::true_type{});
+            });
+    }
+    if (a.slots) block_slot_add<1, 64 * NWS>(st, a.slots);
+}
+
+// The H^T kernel reads its taps from the wave's LDS copy (one profile per
+// step, needed at the start of the step).
+template <typename T>
+__global__ __launch_bounds__(64 * NWS) void k_blur_ht(BlurArgs<T> a)
+{
+    if (xcd_tile(a.tx) < 0) return;
+    extern __shared__ __align__(16) unsigned char blur_lds[];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n1 = a.n1, n2 = a.n2;
+    int c0, p0, np;
+    if (!march_item(SOT, n1, n2, a.rows, a.tx, c0, p0, np)) return;
+    const int64_t ch = blockIdx.y;
+    const T *rin = a.r + ch * a.plane;
+    T *s = a.s + ch * a.plane;
+    T *lrow = reinterpret_cast<T *>(blur_lds) + wv * blur_ht_lds(a.rows);
+    T *ltown = lrow + SRW;  // own profile of output row p0+q at ltown[q]
+    stage_taps<T>(a.tabs, p0, np, a.tabs, 0, 0, n2, ltown, lane);
+    // u columns (LDS slots 2 lane, 2 lane+1) = r columns c0-RM-1+2 lane, +1;
+    // s columns c0 + 2 lane, +1 for the first SOT/2 lanes
+    const int qu = wrap(c0 - RM - 1 + 2 * lane, n1);
+    const int cs = c0 + 2 * lane;
+    const bool own = lane < SOT / 2 && cs < n1;
+    const int nsteps = np + 2 * RM;  // r rows p0-RM .. p0+np-1+RM enter the window
+    int rrow = wrap(p0 - RM, n2);
+    Pair<T> rq[SPF];
+    auto load_next = [&](Pair<T> &v) {
+        v = *reinterpret_cast<const Pair<T> *>(rin + (int64_t)rrow * n1 + qu);
+        rrow = next_row(rrow, n2);
+    };
+#pragma unroll
+    for (int q = 0; q < SPF; ++q) load_next(rq[q]);
+    T win[WIN][2];
+    wave_lds_sync();  // the staged taps
+    const int pend = p0 + np;
+    auto step = [&](int j, auto kc, auto uc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr bool with_u = decltype(uc)::value;
+        win[k][0] = rq[0].a;
+        win[k][1] = rq[0].b;
+#pragma unroll
+        for (int q = 0; q + 1 < SPF; ++q) rq[q] = rq[q + 1];
+        load_next(rq[SPF - 1]);
+        if (with_u) {
+            // the output row's profile (padded steps repeat the block's last row)
+            const int q = j - 2 * RM < np - 1 ? j - 2 * RM : np - 1;
+            T kp[TABP];
+            read_taps<T>(ltown + q * TABP, kp);
+            // u of row p: r rows p+d (d = -RM..RM) sit in slots (k + 1 + i) mod WIN, i = d + RM
+            T u0 = T(0), u1 = T(0);
+#pragma unroll
+            for (int i = 0; i <= 2 * RM; ++i) {
+                const int sl = (k + 1 + i) % WIN;
+                u0 = fma(kp[i], win[sl][0], u0);
+                u1 = fma(kp[i], win[sl][1], u1);
+            }
+            *reinterpret_cast<Pair<T> *>(lrow + 2 * lane) = Pair<T>{u0, u1};
+            wave_lds_sync();
+            T us[2 * RM + 4];
+            read_row<T>(lrow, lane, us);  // us[i] = u column cs - RM - 1 + i
+            wave_lds_sync();
+            // s(c) = sum_{m} k[m - RM] u(c - RM + m), m = 0..2RM
+            T s0 = T(0), s1 = T(0);
+#pragma unroll
+            for (int m = 0; m <= 2 * RM; ++m) {
+                s0 = fma(kp[m], us[m + 1], s0);
+                s1 = fma(kp[m], us[m + 2], s1);
+            }
+            const int pr = p0 + j - 2 * RM;
+            if (own && pr < pend) *reinterpret_cast<Pair<T> *>(s + (int64_t)pr * n1 + cs) = Pair<T>{s0, s1};
+        }
+    };
+    static_for<WIN>([&](auto kc) {  // warm-up block: the window fills
+        constexpr int k = decltype(kc)::value;
+        step(k, kc, std::integral_constant<bool, (k >= 2 * RM)>{});
+    });
+    for (int base = WIN; base < nsteps; base += WIN)
+        static_for<WIN>([&](auto kc) { step(base + decltype(kc)::value, kc, std::true_type{}); });
+}
+
 __device__ __forceinline__ int locate(const int *__restrict__ start, int n, int blk)
 {
     int lo = 0, hi = n;  // start[lo] <= blk < start[hi]
@@ -1906,7 +2310,19 @@ hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s)
         hipLaunchKernelGGL(k_identity<T>, dim3(blocks), dim3(NT), 0, s, a);
     } else {
         BlurArgs<T> b = a;
-        const int bt2 = blur_rows(a.n1, a.n2, a.C, a.R, (int)sizeof(T));
+        const int v = blur_variant(a.n1, a.n2, a.C, a.R, (int)sizeof(T));
+        if (v > BLUR_SPLIT && a.r && a.tabs) {
+            b.rows = v - BLUR_SPLIT;
+            const int nb = (a.n2 + b.rows - 1) / b.rows;
+            b.tx = ((a.n1 + SWS - 1) / SWS * nb + NWS - 1) / NWS;
+            hipLaunchKernelGGL(k_blur_h<T>, dim3(xcd_grid(b.tx), a.C), dim3(64 * NWS),
+                               NWS * blur_h_lds<T>(b.rows) * sizeof(T), s, b);
+            b.tx = ((a.n1 + SOT - 1) / SOT * nb + NWS - 1) / NWS;
+            hipLaunchKernelGGL(k_blur_ht<T>, dim3(xcd_grid(b.tx), a.C), dim3(64 * NWS),
+                               NWS * blur_ht_lds(b.rows) * sizeof(T), s, b);
+            return hipGetLastError();
+        }
+        const int bt2 = v == 48 ? 48 : 32;
         tiles_blur(a.n1, a.n2, &b.tx, &b.ty, bt2);
         if (bt2 == 48)
             hipLaunchKernelGGL((k_blur<T, 48>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
@@ -2044,25 +2460,37 @@ PD_INST_REV(double)
 
 void tiles_synth(int M1c, int M2c, int *tx, int *ty) { *tx = (M1c + SP - 1) / SP; *ty = (M2c + SP - 1) / SP; }
 void tiles_analysis(int M1c, int M2c, int *tx, int *ty) { *tx = (M1c + TC - 1) / TC; *ty = (M2c + TC - 1) / TC; }
-// The autotuning cache: the blur tile height chosen by pd_tune per
-// (n1, n2, channels, radius, element size); 32 rows where nothing was tuned.
+// The autotuning cache: the blur variant chosen by pd_tune per
+// (n1, n2, channels, radius, element size); the 32-row tile kernel where
+// nothing was tuned.
 namespace {
 std::mutex g_tune_mu;
-std::map<std::array<int, 5>, int> g_blur_rows;
+std::map<std::array<int, 5>, int> g_blur_variant;
 }  // namespace
 
-int blur_rows(int n1, int n2, int C, int R, int es)
+int blur_variant(int n1, int n2, int C, int R, int es)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_blur_rows.find({n1, n2, C, R, es});
-    return it == g_blur_rows.end() ? 32 : it->second;
+    auto it = g_blur_variant.find({n1, n2, C, R, es});
+    return it == g_blur_variant.end() ? 32 : it->second;
 }
 
-void set_blur_rows(int n1, int n2, int C, int R, int es, int bt2)
+void set_blur_variant(int n1, int n2, int C, int R, int es, int v)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_blur_rows[{n1, n2, C, R, es}] = bt2;
+    g_blur_variant[{n1, n2, C, R, es}] = v;
 }
+
+template <typename T>
+hipError_t launch_blur_tables(const T *taps, int n2, int R, T *tab, hipStream_t s)
+{
+    const int n = n2 * TABP;
+    hipLaunchKernelGGL(k_blur_tables<T>, dim3((n + 255) / 256), dim3(256), 0, s, taps, n2, R, tab);
+    return hipGetLastError();
+}
+template hipError_t launch_blur_tables<float>(const float *, int, int, float *, hipStream_t);
+template hipError_t launch_blur_tables<double>(const double *, int, int, double *, hipStream_t);
+static_assert(TABP == BLUR_TAB_PITCH, "table pitch");
 
 void tiles_blur(int n1, int n2, int *tx, int *ty, int bt2)
 {

@@ -387,26 +387,59 @@ def test_joint_prox_single_channel(n, levels):
     assert np.abs(_np(out["z_cur"]) - ref["z"]).max() < 1e-10
 
 
-@pytest.mark.parametrize("n1,n2,C", [(512, 512, 1), (160, 96, 3)])
-def test_blur_tile_variants_are_bitwise(n1, n2, C):
-    """Every tile-height variant of the fused blur gives the same iterates bit
-    for bit (the autotuner's choice never changes results); pd_tune records
-    a variant and reports it."""
-    pb, f0, case = _problem(n1, n2, C=C, seed=97)
+@pytest.mark.parametrize("n1,n2,C,dtype", [(512, 512, 1, torch.float32), (160, 96, 3, torch.float32),
+                                            (384, 200, 1, torch.float32), (8, 8, 1, torch.float32),
+                                            (256, 136, 2, torch.float64)])
+def test_blur_variants_are_bitwise(n1, n2, C, dtype):
+    """Every blur variant (fused tile heights 32 and 48, and the two marching
+    kernels with 16, 32 and 64 rows per wave) gives the same iterates bit for
+    bit (the autotuner's choice never changes results), on widths that are not
+    a multiple of any strip and heights shorter than the profile window;
+    pd_tune records a variant and reports it."""
+    pb, f0, case = _problem(n1, n2, C=C, levels=3 if n1 == 8 else None, seed=97)
+    f0t = _t(f0, dtype)
+    op = _op(pb, dtype)
+    outs = {}
+    try:
+        for v in P.BLUR_VARIANTS:
+            assert P.pd_tune(f0t, op, pb.levels, pin=v) == v
+            outs[v] = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w, stats=True)
+        for v in P.BLUR_VARIANTS[1:]:
+            for k in ("f", "z_cur", "z_prev"):
+                assert torch.equal(outs[32][k], outs[v][k]), (v, k)
+            np.testing.assert_allclose(_np(outs[32]["stats"]), _np(outs[v]["stats"]), rtol=1e-12)
+        chosen = P.pd_tune(f0t, op, pb.levels)
+        assert chosen in P.BLUR_VARIANTS
+        again = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w)
+        assert torch.equal(again["f"], outs[32]["f"])
+    finally:
+        P.pd_tune(f0t, op, pb.levels, pin=32)
+    ref = O.fista(pb, f0, 0.85, 40)
+    assert np.abs(_np(outs[1032]["f"]) - ref["f"]).max() < (1e-10 if dtype == torch.float64 else 1e-5)
+
+
+@pytest.mark.parametrize("n1,n2", [(96, 64), (256, 160)])
+def test_blur_variants_reverse_mode_is_bitwise(n1, n2):
+    """The reverse mode's accumulation of H Psi v through the blur (the
+    marching r kernel's racc path) gives the same gradients bit for bit under
+    every variant."""
+    pb, f0, case = _problem(n1, n2, seed=98)
     f0t = _t(f0, torch.float32)
     op = _op(pb, torch.float32)
+    rng = np.random.default_rng(5)
+    gf = torch.tensor(rng.normal(size=f0.shape), dtype=torch.float32, device="cuda")
     outs = {}
-    for bt2 in (32, 48):
-        assert P.pd_tune(f0t, op, pb.levels, pin=bt2) == bt2
-        outs[bt2] = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w, stats=True)
-    for k in ("f", "z_cur", "z_prev"):
-        assert torch.equal(outs[32][k], outs[48][k]), k
-    np.testing.assert_allclose(_np(outs[32]["stats"]), _np(outs[48]["stats"]), rtol=1e-12)
-    chosen = P.pd_tune(f0t, op, pb.levels)
-    assert chosen in (32, 48)
-    again = P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 40, level_w=case.level_w)
-    assert torch.equal(again["f"], outs[32]["f"])
-    P.pd_tune(f0t, op, pb.levels, pin=32)
+    try:
+        for v in P.BLUR_VARIANTS:
+            P.pd_tune(f0t, op, pb.levels, pin=v)
+            outs[v] = P.pd_backward(f0t, op, _h(), pb.levels, 0.85, 25, gf, level_w=case.level_w,
+                                    checkpoint_every=10)
+    finally:
+        P.pd_tune(f0t, op, pb.levels, pin=32)
+    for v in P.BLUR_VARIANTS[1:]:
+        for a, b in zip(outs[32], outs[v]):
+            if a is not None:
+                assert torch.equal(a, b), v
 
 
 @pytest.mark.parametrize("n1,n2,C,levels", [(512, 512, 1, 9), (160, 96, 2, 5), (256, 128, 1, 3), (1024, 64, 1, 6),
