@@ -271,9 +271,9 @@ int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operator *op,
  * by (n1, n2, channels, radius, dtype), which pd_solve, pd_solve_noalloc,
  * pd_solve_checkpointed and pd_backward use from then on (variant 32 for
  * sizes never tuned).  Variants (PD_BLUR_* codes): 32 and 48 = one fused
- * kernel with that many output rows per workgroup; 1016, 1032 and 1064 = two
+ * kernel with that many output rows per workgroup; 1020, 1039 and 1058 = two
  * kernels (r = H x - f0, then s = H^T r) whose waves walk down strips of
- * 128 columns in blocks of 16, 32 or 64 rows.  Every variant computes each
+ * 128 columns in blocks of 20, 39 or 58 rows.  Every variant computes each
  * output by the same sums in the same order, so results do not depend on the
  * choice.  workspace: at least pd_workspace_size bytes, used as scratch.
  * chosen (host, nullable): if it holds one of the codes on entry, that
@@ -283,9 +283,9 @@ int pd_apply_op(const pd_shape *shape, int32_t dtype, const pd_operator *op,
  * PD_ERR_UNSUPPORTED, PD_ERR_HIP. */
 #define PD_BLUR_TILE32 32
 #define PD_BLUR_TILE48 48
-#define PD_BLUR_SPLIT16 1016
-#define PD_BLUR_SPLIT32 1032
-#define PD_BLUR_SPLIT64 1064
+#define PD_BLUR_SPLIT20 1020
+#define PD_BLUR_SPLIT39 1039
+#define PD_BLUR_SPLIT58 1058
 int pd_tune(const pd_shape *shape, int32_t dtype, const pd_operator *op, void *workspace,
             size_t ws_bytes, int32_t *chosen, void *stream);
 

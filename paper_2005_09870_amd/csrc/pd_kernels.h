@@ -199,7 +199,8 @@ void tiles_blur(int n1, int n2, int *tx, int *ty, int bt2 = 32);
 // BlurArgs::r and ::tabs, else the fused 32-row kernel runs).  All variants
 // give the same results bit for bit.
 constexpr int BLUR_SPLIT = 1000;
-constexpr int BLUR_VARIANTS[] = {32, 48, BLUR_SPLIT + 16, BLUR_SPLIT + 32, BLUR_SPLIT + 64};
+// (rows + 2 PD_MAX_RADIUS a multiple of 2 PD_MAX_RADIUS + 1: no padded steps)
+constexpr int BLUR_VARIANTS[] = {32, 48, BLUR_SPLIT + 20, BLUR_SPLIT + 39, BLUR_SPLIT + 58};
 int blur_variant(int n1, int n2, int C, int R, int es);
 void set_blur_variant(int n1, int n2, int C, int R, int es, int v);
 // per-row profile tables of the two-kernel variant: tab = [2][n2][2 PD_MAX_RADIUS + 2]

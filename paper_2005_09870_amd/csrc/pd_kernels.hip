@@ -1996,6 +1996,7 @@ __global__ __launch_bounds__(64 * NWS) void k_blur_h(BlurArgs<T> a)
 #pragma unroll
                 for (int i = 0; i < TABP; ++i) kr[i] = kg[i];
                 if (next_r) load_gat(j + 1 - 2 * RM);  // the next step's, requested early
+                __builtin_amdgcn_sched_barrier(0);     // (not sunk into the next step)
             } else if (with_r) {
                 const int q = j - 2 * RM < np - 1 ? j - 2 * RM : np - 1;
                 read_taps<T>(ltgat + q * TABP, kr);

@@ -215,15 +215,15 @@ def step_size(op: Operator, n1: int, n2: int, device="cuda") -> float:
     return 1.0 / (lipschitz(op, n1, n2, device=device) * (1.0 + 1e-6))
 
 
-BLUR_VARIANTS = (32, 48, 1016, 1032, 1064)
+BLUR_VARIANTS = (32, 48, 1020, 1039, 1058)
 
 
 def pd_tune(f0: torch.Tensor, op: Operator, levels: int, pin: int = 0) -> int:
     """Autotune the blur for f0's size and this operator (cached in the
     library for later solves of the same size); returns the chosen variant
     code (0: nothing to tune): 32 / 48 = one fused kernel with that many
-    output rows per workgroup, 1016 / 1032 / 1064 = two marching kernels with
-    16 / 32 / 64 rows per wave.  pin = one of BLUR_VARIANTS records that
+    output rows per workgroup, 1020 / 1039 / 1058 = two marching kernels with
+    20 / 39 / 58 rows per wave.  pin = one of BLUR_VARIANTS records that
     variant untimed.  Results never depend on the variant."""
     _check_dev(f0)
     shape = _shape(f0, levels)
