@@ -40,7 +40,8 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_w: bool) -> float:
+def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_w: bool,
+              plain: bool = False) -> float:
     """Algorithmic (compulsory) HBM bytes of one launch of a kernel class.
 
     blur      : read x, f0; write s                         -> 3 planes
@@ -52,9 +53,15 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
                 approximation                                -> 3.5 x input
                 (+0.75 x input with a per-coefficient weight map)
     coarse    : all levels from l on, one workgroup          -> 5 x input
+    analysis, plain (the joint prox's split form): reads its input, writes
+                the coefficients and the coarser approximation -> 2 x input
+    jprox     : joint prox over the whole plane: reads g, z(i-1), z(i-2),
+                writes z(i)                                  -> 4 planes
     """
     if kernel == "blur":
         return 3.0 * es * n1 * n2 * C
+    if kernel == "jprox":
+        return 4.0 * es * n1 * n2 * C
     if level < 1:
         return 0.0
     m = (n1 >> (level - 1)) * (n2 >> (level - 1)) * C
@@ -67,7 +74,7 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
     if kernel == "synthesis2":  # levels `level` and level + 1 in one launch
         return 2.75 * es * m + 2.75 * es * m / 4
     if kernel == "analysis":
-        return (3.5 + (0.75 if coeff_w else 0.0)) * es * m
+        return (2.0 if plain else 3.5 + (0.75 if coeff_w else 0.0)) * es * m
     return 0.0
 
 
@@ -386,7 +393,7 @@ def colour_case(torch, P, SI, h, iters, n=2048):
     rows = P.solver.pd_timing_read()
     P.solver.pd_timing_enable(False)
     for rw in rows:
-        rw["alg_bytes_per_launch"] = alg_bytes(rw["kernel"], rw["level"], n, n, 3, 4, False)
+        rw["alg_bytes_per_launch"] = alg_bytes(rw["kernel"], rw["level"], n, n, 3, 4, False, plain=True)
     dom = max(rows, key=lambda rw: rw["total_ms"])
     ach = dom["alg_bytes_per_launch"] / (dom["avg_us"] * 1e-6) / 1e9
     return {"workload": f"{n}x{n}x3 FP32 joint shrinkage, {iters} iterations",

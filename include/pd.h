@@ -477,10 +477,11 @@ int pd_decompose(const pd_shape *shape, const pd_operator *op, const pd_wavelet 
  * two HIP events recorded on its launch stream, keyed by kernel class and
  * decomposition level.  Adds one event pair per launch; not thread-safe.   */
 typedef enum {
-    PD_K_BLUR = 1,      /* fused r = H x - f0, s = H^T r                       */
+    PD_K_BLUR = 1,      /* r = H x - f0, s = H^T r (one or two launches)        */
     PD_K_SYNTH = 2,     /* one synthesis level (level = decomposition level)   */
     PD_K_ANALYSIS = 3,  /* one analysis level with the fused prox              */
-    PD_K_COARSE = 4,    /* all coarse levels of an iteration in one workgroup  */
+    PD_K_COARSE = 4,    /* all coarse levels of an iteration in one workgroup
+                           per channel (or per image)                          */
     PD_K_OTHER = 5,     /* copies and set-up                                   */
     PD_K_WRES = 6,      /* wavelet domain: u = Theta_L y - z0                  */
     PD_K_WPROX = 7,     /* wavelet domain: Theta_L^T u, prox and momentum      */
@@ -490,7 +491,8 @@ typedef enum {
                            multipliers, 3 zeta and z)                          */
     PD_K_DECOMP = 10,   /* Algorithm 1: level 0 probe convolutions, 1 multiplier,
                            2 spreading of B_k columns over A~_k, 3 count, 4 fill */
-    PD_K_SYNTH2 = 11    /* two synthesis levels in one launch (level = the finer) */
+    PD_K_SYNTH2 = 11,   /* two synthesis levels in one launch (level = the finer) */
+    PD_K_JPROX = 12     /* joint colour prox over the whole coefficient plane  */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */

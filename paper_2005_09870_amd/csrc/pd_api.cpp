@@ -498,31 +498,34 @@ int one_iteration(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T
     // z(i) overwrites z(i-2) in place (each coefficient is read, then written, by one thread)
     ProxArgs<T> p = prox_args<T>(c, zc, zp, zp, beta, tau, w, sti);
     p.di = di;
-    if ((rc = analysis_fine<T>(c, c.s(), MODE_PROX, p)) != PD_OK) return rc;
-    if (coarse && p.joint && sh->channels > 1) {
-        // joint prox over several channels: per-channel coarse analysis (one workgroup each) into the
-        // block positions of the x plane (free after the blur), the joint prox over many workgroups,
-        // then per-channel synthesis of y(i+1) from (z(i), z(i-1)) -- the fused kernel's formulas
+    if (p.joint && sh->channels > 1) {
+        // joint prox over several channels: per-channel plain analysis (fine levels, then the coarse
+        // block) into the x plane (free after the blur), the joint prox over the whole plane, then
+        // per-channel coarse synthesis of y(i+1) from (z(i), z(i-1)) -- the fused kernels' formulas
         ProxArgs<T> pa = prox_args<T>(c, nullptr, nullptr, c.x(), T(0), T(0), nullptr, nullptr);
-        if ((rc = coarse_step<T>(c, COARSE_ANA, c.s(), nullptr, pa, T(0))) != PD_OK) return rc;
-        CoarseJProxArgs<T> ja;
+        if ((rc = analysis_fine<T>(c, c.s(), MODE_PLAIN, pa)) != PD_OK) return rc;
+        if (coarse && (rc = coarse_step<T>(c, COARSE_ANA, c.s(), nullptr, pa, T(0))) != PD_OK) return rc;
+        JProxArgs<T> ja;
         ja.g = c.x();
-        ja.m1 = sh->n1 >> (c.lc - 1);
-        ja.m2 = sh->n2 >> (c.lc - 1);
-        ja.nlev = sh->levels - c.lc + 1;
-        ja.band_top = sh->levels + 1 - c.lc;
+        ja.m1 = sh->n1;
+        ja.m2 = sh->n2;
+        ja.nlev = sh->levels;
+        ja.band_top = sh->levels;
         ja.p = p;
-        PD_TRY_HIP(timed(PD_K_COARSE, c.lc, st, [&] { return launch_coarse_jprox<T>(ja, sh->channels, st); }));
-        if (!last) {
+        PD_TRY_HIP(timed(PD_K_JPROX, 0, st, [&] { return launch_jprox<T>(ja, sh->channels, st); }));
+        if (coarse && !last) {
             // y(i+1) = z(i) + b_i (z(i) - z(i-1)): z(i) is in zp (in place of z(i-2)), z(i-1) in zc
             ProxArgs<T> ps = prox_args<T>(c, zp, zc, nullptr, (T)beta_y(i + 1), T(0), nullptr, nullptr);
             ps.di = di;
             if (di.it_dev) ps.di.it_off = di.it_off + 1;  // the device iteration's beta of i + 1
             if ((rc = coarse_step<T>(c, COARSE_SYN, nullptr, c.x(), ps, T(0))) != PD_OK) return rc;
         }
-    } else if (coarse) {
-        const int ops = COARSE_ANA | COARSE_PROX | (last ? 0 : COARSE_SYN);
-        if ((rc = coarse_step<T>(c, ops, c.s(), c.x(), p, (T)beta_y(i + 1))) != PD_OK) return rc;
+    } else {
+        if ((rc = analysis_fine<T>(c, c.s(), MODE_PROX, p)) != PD_OK) return rc;
+        if (coarse) {
+            const int ops = COARSE_ANA | COARSE_PROX | (last ? 0 : COARSE_SYN);
+            if ((rc = coarse_step<T>(c, ops, c.s(), c.x(), p, (T)beta_y(i + 1))) != PD_OK) return rc;
+        }
     }
     if (stats && ((it + 1) % PD_RING == 0 || last)) {  // fold the ring into stats
         const int cnt = (it % PD_RING) + 1, it0 = it + 1 - cnt;

@@ -119,9 +119,10 @@ struct CoarseArgs {
 // Mallat plane) from the coefficients g that a per-channel coarse analysis
 // wrote at their Mallat positions of a scratch plane.
 template <typename T>
-struct CoarseJProxArgs {
-    const T *g;             // [C][n2][n1] scratch plane (block positions only)
-    int m1, m2, nlev, band_top;
+struct JProxArgs {
+    const T *g;             // [C][n2][n1] coefficients of the transformed gradient (read in the region)
+    int m1, m2, nlev, band_top;  // region = top-left m2 x m1 of the Mallat plane, its levels,
+                                 // band index of its finest detail level
     ProxArgs<T> p;          // zc, zp, zn, beta, tau, weights, slots, flag, di
 };
 
@@ -169,7 +170,7 @@ template <typename T>
 hipError_t launch_synth2(const SynthArgs<T> &d, const SynthArgs<T> &u, int C, hipStream_t s);
 template <typename T> hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s);
-template <typename T> hipError_t launch_coarse_jprox(const CoarseJProxArgs<T> &a, int nch, hipStream_t s);
+template <typename T> hipError_t launch_jprox(const JProxArgs<T> &a, int nch, hipStream_t s);
 template <typename T> size_t coarse_lds_bytes(int m1, int m2, int chans);
 template <typename T> hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s);
 template <typename T> hipError_t launch_blur_single(const BlurArgs<T> &a, int transpose, hipStream_t s);

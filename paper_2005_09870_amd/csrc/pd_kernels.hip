@@ -156,10 +156,19 @@ __device__ __forceinline__ T soft(T v, T t)
 
 // Gradient step + prox + momentum bookkeeping for one coefficient of one
 // channel (scalar weights).  Returns z; accumulates w|y| and (z-y)^2.
+// v = y - tau g as one explicit fused multiply-add (every prox of every
+// kernel forms it the same way, so the fused and the split paths agree bit
+// for bit).
+template <typename T>
+__device__ __forceinline__ T grad_step(T y, T g, T tau)
+{
+    return fma(-tau, g, y);
+}
+
 template <typename T>
 __device__ __forceinline__ T prox1(T y, T g, T tau, T w, double (&st)[2], bool &bad)
 {
-    T v = y - tau * g;
+    T v = grad_step(y, g, tau);
     T z = soft(v, tau * w);
     bad |= !isfinite(v);
     st[0] += (double)w * fabs((double)y);
@@ -619,7 +628,7 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
 #pragma unroll
             for (int cc = 0; cc < NC; ++cc) {
                 yv[cc] = momentum(zcr[cc][o], zpr[cc][o], lv.beta);
-                vv[cc] = yv[cc] - p.tau * res[cc][2 * q + hx2];
+                vv[cc] = grad_step(yv[cc], res[cc][2 * q + hx2], p.tau);
                 nv = fma(vv[cc], vv[cc], nv);
                 ny += (double)yv[cc] * (double)yv[cc];
             }
@@ -1119,7 +1128,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
 #pragma unroll
                 for (int cc = 0; cc < NCH; ++cc) {
                     yv[cc] = momentum(zcr[cc][k], zpr[cc][k], lv.beta);
-                    vv[cc] = yv[cc] - p.tau * home(cc)[li];
+                    vv[cc] = grad_step(yv[cc], home(cc)[li], p.tau);
                     nv = fma(vv[cc], vv[cc], nv);
                     ny += (double)yv[cc] * (double)yv[cc];
                 }
@@ -1656,51 +1665,72 @@ __global__ __launch_bounds__(NTC) void k_coarse_joint(CoarseArgs<T> a)
     coarse_body<T, NCH, true>(a, live_of<T>(a.p, a.beta_next), 0);
 }
 
-// The joint (group) prox on the coarse block as its own element-wise launch,
-// between a per-channel coarse analysis (coefficients g in a scratch plane at
-// their Mallat positions) and a per-channel coarse synthesis of y(i+1): the
-// same formulas as the joint branch of coarse_body, over many workgroups.
+// The joint (group) prox as its own element-wise launch over an m2 x m1
+// region of the Mallat plane (the whole plane, or the coarse block), between a
+// per-channel plain analysis (coefficients g in a scratch plane at their
+// Mallat positions) and the per-channel synthesis of y(i+1): the same formulas
+// as the joint branches of the fused kernels.  A grid of at most JP_GROUPS
+// workgroups strides over the positions, JP_UNROLL per thread at a time with
+// all their loads in flight, so that the statistics need few atomics.
+constexpr int JP_UNROLL = 4;
+constexpr int JP_GROUPS = 2048;
+
 template <typename T, int NCH>
-__global__ __launch_bounds__(NT) void k_coarse_jprox(CoarseJProxArgs<T> a)
+__global__ __launch_bounds__(NT) void k_jprox(JProxArgs<T> a)
 {
     const ProxArgs<T> &p = a.p;
     const Live<T> lv = live_of<T>(p, T(0));
-    const int cnt = a.m1 * a.m2;
+    const int64_t cnt = (int64_t)a.m1 * a.m2;
     double st[2] = {0.0, 0.0};
     bool bad = false;
-    const int e = blockIdx.x * NT + threadIdx.x;
-    if (e < cnt) {
-        int r, c;
-        split(e, a.m1, r, c);
-        int inside = 0;
-        for (int lev = 0; lev < a.nlev; ++lev)  // uniform trip count
-            inside += (r < (a.m2 >> (lev + 1))) & (c < (a.m1 >> (lev + 1)));
-        const int band = inside == a.nlev ? 0 : a.band_top - inside;
-        T w = p.wlev[0];
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t e0 = (int64_t)blockIdx.x * NT + threadIdx.x; e0 < cnt; e0 += JP_UNROLL * stride) {
+        T zc[JP_UNROLL][NCH], zp[JP_UNROLL][NCH], g[JP_UNROLL][NCH];
+        int64_t gi[JP_UNROLL];
+        int band[JP_UNROLL];
 #pragma unroll
-        for (int k = 1; k <= PD_MAXL; ++k) w = band == k ? p.wlev[k] : w;  // selects, no per-lane argument load
-        const int64_t gi = (int64_t)r * p.pitch + c;
-        T yv[NCH], vv[NCH];
-        T nv = T(0);
-        double ny = 0.0;
+        for (int u = 0; u < JP_UNROLL; ++u) {
+            const int64_t e = e0 + u * stride < cnt ? e0 + u * stride : e0;  // past the end: a repeat, not stored
+            const int r = (int)(e / a.m1), c = (int)(e - (int64_t)r * a.m1);
+            int inside = 0;
+            for (int lev = 0; lev < a.nlev; ++lev)  // uniform trip count
+                inside += (r < (a.m2 >> (lev + 1))) & (c < (a.m1 >> (lev + 1)));
+            band[u] = inside == a.nlev ? 0 : a.band_top - inside;
+            gi[u] = (int64_t)r * p.pitch + c;
 #pragma unroll
-        for (int cc = 0; cc < NCH; ++cc) {
-            const T zc = lv.zc[(int64_t)cc * p.plane + gi], zp = lv.zp[(int64_t)cc * p.plane + gi];
-            yv[cc] = momentum(zc, zp, lv.beta);
-            vv[cc] = yv[cc] - p.tau * a.g[(int64_t)cc * p.plane + gi];
-            nv = fma(vv[cc], vv[cc], nv);
-            ny += (double)yv[cc] * (double)yv[cc];
+            for (int cc = 0; cc < NCH; ++cc) {
+                zc[u][cc] = lv.zc[(int64_t)cc * p.plane + gi[u]];
+                zp[u][cc] = lv.zp[(int64_t)cc * p.plane + gi[u]];
+                g[u][cc] = a.g[(int64_t)cc * p.plane + gi[u]];
+            }
         }
-        T nrm = sqrt(nv);
-        T sc = nrm > T(0) ? T(1) - p.tau * w / nrm : T(0);
-        sc = sc > T(0) ? sc : T(0);
-        bad |= !isfinite(nrm);
-        st[0] += (double)w * sqrt(ny);
 #pragma unroll
-        for (int cc = 0; cc < NCH; ++cc) {
-            T z = mul_rn(vv[cc], sc);
-            lv.zn[(int64_t)cc * p.plane + gi] = z;
-            st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
+        for (int u = 0; u < JP_UNROLL; ++u) {
+            if (e0 + u * stride >= cnt) continue;
+            T w = p.wlev[0];
+#pragma unroll
+            for (int k = 1; k <= PD_MAXL; ++k) w = band[u] == k ? p.wlev[k] : w;  // selects, no per-lane argument load
+            T yv[NCH], vv[NCH];
+            T nv = T(0);
+            double ny = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < NCH; ++cc) {
+                yv[cc] = momentum(zc[u][cc], zp[u][cc], lv.beta);
+                vv[cc] = grad_step(yv[cc], g[u][cc], p.tau);
+                nv = fma(vv[cc], vv[cc], nv);
+                ny += (double)yv[cc] * (double)yv[cc];
+            }
+            T nrm = sqrt(nv);
+            T sc = nrm > T(0) ? T(1) - p.tau * w / nrm : T(0);
+            sc = sc > T(0) ? sc : T(0);
+            bad |= !isfinite(nrm);
+            st[0] += (double)w * sqrt(ny);
+#pragma unroll
+            for (int cc = 0; cc < NCH; ++cc) {
+                T z = mul_rn(vv[cc], sc);
+                lv.zn[(int64_t)cc * p.plane + gi[u]] = z;
+                st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
+            }
         }
     }
     if (bad) atomicOr(p.flag, 1);
@@ -2251,14 +2281,10 @@ hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s)
     dim3 grid(xcd_grid(b.tx * b.ty), groups);
     if (!a.p.joint)
         hipLaunchKernelGGL((k_analysis<T, 0>), grid, dim3(NT), 0, s, b);
-    else if (a.p.C == 1)
+    else if (a.p.C == 1)  // (several channels: plain analysis + k_jprox)
         hipLaunchKernelGGL((k_analysis<T, 1>), grid, dim3(NT), 0, s, b);
-    else if (a.p.C == 2)
-        hipLaunchKernelGGL((k_analysis<T, 2>), grid, dim3(NT), 0, s, b);
-    else if (a.p.C == 3)
-        hipLaunchKernelGGL((k_analysis<T, 3>), grid, dim3(NT), 0, s, b);
     else
-        hipLaunchKernelGGL((k_analysis<T, 4>), grid, dim3(NT), 0, s, b);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -2270,14 +2296,17 @@ size_t coarse_lds_bytes(int m1, int m2, int chans)
 }
 
 template <typename T>
-hipError_t launch_coarse_jprox(const CoarseJProxArgs<T> &a, int nch, hipStream_t s)
+hipError_t launch_jprox(const JProxArgs<T> &a, int nch, hipStream_t s)
 {
-    const dim3 grid((a.m1 * a.m2 + NT - 1) / NT);
+    const int64_t cnt = (int64_t)a.m1 * a.m2;
+    const int64_t want = (cnt + JP_UNROLL * NT - 1) / (JP_UNROLL * NT);
+    const int groups = want < JP_GROUPS ? (int)want : JP_GROUPS;
+    const dim3 grid(groups > 0 ? groups : 1);
     switch (nch) {
-    case 1: hipLaunchKernelGGL((k_coarse_jprox<T, 1>), grid, dim3(NT), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_coarse_jprox<T, 2>), grid, dim3(NT), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_coarse_jprox<T, 3>), grid, dim3(NT), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_coarse_jprox<T, 4>), grid, dim3(NT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_jprox<T, 1>), grid, dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_jprox<T, 2>), grid, dim3(NT), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_jprox<T, 3>), grid, dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_jprox<T, 4>), grid, dim3(NT), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2290,14 +2319,10 @@ hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s)
     size_t lds = coarse_lds_bytes<T>(a.m1, a.m2, chans);
     if (!a.p.joint)
         hipLaunchKernelGGL(k_coarse<T>, dim3(groups), dim3(NTC), lds, s, a);
-    else if (chans == 1)
+    else if (chans == 1)  // (several channels: per-channel analysis/synthesis + k_jprox)
         hipLaunchKernelGGL((k_coarse_joint<T, 1>), dim3(groups), dim3(NTC), lds, s, a);
-    else if (chans == 2)
-        hipLaunchKernelGGL((k_coarse_joint<T, 2>), dim3(groups), dim3(NTC), lds, s, a);
-    else if (chans == 3)
-        hipLaunchKernelGGL((k_coarse_joint<T, 3>), dim3(groups), dim3(NTC), lds, s, a);
     else
-        hipLaunchKernelGGL((k_coarse_joint<T, 4>), dim3(groups), dim3(NTC), lds, s, a);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -2522,7 +2547,7 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
     template hipError_t launch_analysis<T>(const AnalysisArgs<T> &, hipStream_t);          \
     template hipError_t launch_synth2<T>(const SynthArgs<T> &, const SynthArgs<T> &, int, hipStream_t); \
     template hipError_t launch_coarse<T>(const CoarseArgs<T> &, int, hipStream_t);         \
-    template hipError_t launch_coarse_jprox<T>(const CoarseJProxArgs<T> &, int, hipStream_t); \
+    template hipError_t launch_jprox<T>(const JProxArgs<T> &, int, hipStream_t); \
     template size_t coarse_lds_bytes<T>(int, int, int);                                    \
     template hipError_t launch_blur<T>(const BlurArgs<T> &, bool, hipStream_t);            \
     template hipError_t launch_blur_single<T>(const BlurArgs<T> &, int, hipStream_t);      \
