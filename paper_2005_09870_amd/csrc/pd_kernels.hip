@@ -983,26 +983,31 @@ struct CLayout {
 
 // NCH: channels handled by the workgroup (the joint colour prox couples them);
 // JOINT: the prox is the joint (group) one -- a compile-time choice, so the
-// scalar kernel carries no code of the other.
-template <typename T, int NCH, bool JOINT>
+// scalar kernel carries no code of the other.  SM, SKW, STM: when nonzero,
+// the block side (square), the number of pass-by-pass levels and the tail
+// side as compile-time constants (the arguments then hold the same values):
+// the common geometry gets its index arithmetic folded at compile time.
+template <typename T, int NCH, bool JOINT, int SM = 0, int SKW = 0, int STM = 0>
 __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T> &lv, int bz)
 {
     using G = CGeom<T>;
     extern __shared__ unsigned char lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
     const ProxArgs<T> &p = a.p;
-    const int m1 = a.m1, m2 = a.m2;
+    const int m1 = SM ? SM : a.m1, m2 = SM ? SM : a.m2;
+    const int kw = SKW ? SKW : a.kw;
+    const int tM1 = STM ? STM : a.tM1, tM2 = STM ? STM : a.tM2;
     const int ch0 = NCH > 1 ? 0 : bz;
     const CLayout<T> L(m1, m2, NCH);
     T *Cb = lds + L.c;
     T *B = lds + L.b;
     T *Mat = lds + L.mat;  // [2][tn][tn] tail matrices
-    const int tn = a.tM1 * a.tM2;
+    const int tn = tM1 * tM2;
     const int cnt = m1 * m2;  // <= CPT * NTC
     const int tid = threadIdx.x;
     const bool ana = (a.ops & COARSE_ANA) != 0, prox = (a.ops & COARSE_PROX) != 0;
     const bool need_z = !ana || prox;
-    const bool routed = NCH == 1 && !JOINT && ana && prox && (a.ops & COARSE_SYN) && a.kw > 0;
+    const bool routed = NCH == 1 && !JOINT && ana && prox && (a.ops & COARSE_SYN) && kw > 0;
     auto home = [&](int cc) { return lds + L.a + cc * m2 * G::PA; };
 
     // 1. every global load at once (clamped indices, no data-dependent branch):
@@ -1056,7 +1061,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         Mat[tid + k * NTC] = mv[k];  // load is deferred into a branch behind a full wait
     // one channel with pass-by-pass levels: the analysis input goes straight
     // into C with its wrapped columns
-    const bool in_c = NCH == 1 && ana && a.kw > 0;
+    const bool in_c = NCH == 1 && ana && kw > 0;
 #pragma unroll
     for (int cc = 0; cc < NCH; ++cc)
 #pragma unroll
@@ -1075,7 +1080,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     if (ana) {
 #pragma unroll
         for (int cc = 0; cc < NCH; ++cc)
-            coarse_analysis<T>(home(cc), B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat, in_c);
+            coarse_analysis<T>(home(cc), B, Cb, m1, m2, a.nlev, a.f, kw, tM1, tM2, Mat, in_c);
         if (!prox) {  // plain forward transform
 #pragma unroll
             for (int cc = 0; cc < NCH; ++cc)
@@ -1110,11 +1115,11 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 T z = prox1(y, A[li], p.tau, w, st, bad);
                 lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
                 const T yn = momentum(z, zcr[0][k], lv.beta_next);
-                if (!routed || (a.kw < a.nlev && r < a.tM2 && c < a.tM1)) {
+                if (!routed || (kw < a.nlev && r < tM2 && c < tM1)) {
                     A[li] = yn;  // the tail's input (or the whole block)
                 } else {  // straight into the synthesis input of the level that reads it
-                    int lev = a.kw - 1;
-                    for (int j = 0; j < a.kw - 1; ++j)
+                    int lev = kw - 1;
+                    for (int j = 0; j < kw - 1; ++j)
                         if (r >= (m2 >> (j + 1)) || c >= (m1 >> (j + 1))) {
                             lev = j;
                             break;
@@ -1156,7 +1161,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
 #pragma unroll
     for (int cc = 0; cc < NCH; ++cc) {
         T *A = home(cc);
-        coarse_synthesis<T>(A, B, Cb, m1, m2, a.nlev, a.f, a.kw, a.tM1, a.tM2, Mat + tn * tn, routed);
+        coarse_synthesis<T>(A, B, Cb, m1, m2, a.nlev, a.f, kw, tM1, tM2, Mat + tn * tn, routed);
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int e = tid + k * NTC;
@@ -1653,10 +1658,25 @@ __global__ __launch_bounds__(NT) void k_analysis(AnalysisArgs<T> a)
     analysis_body<T, NCH>(a, live_of<T>(a.p, T(0)), t % a.tx, t / a.tx, blockIdx.y);
 }
 
+// The scalar coarse body, specialised for the geometry every large
+// power-of-two plane reaches (a CM x CM block, levels down to an 8 x 8 tail):
+// 64 x 64 with 3 pass-by-pass levels in FP32, 32 x 32 with 2 in FP64.
+template <typename T>
+__device__ __forceinline__ void coarse_scalar(const CoarseArgs<T> &a, const Live<T> &lv, int bz)
+{
+    constexpr int CM = CGeom<T>::CM, KW = sizeof(T) == 4 ? 3 : 2;
+    static_assert((CM >> KW) * (CM >> KW) <= PD_TAIL_MAX && (CM >> (KW - 1)) * (CM >> (KW - 1)) > PD_TAIL_MAX,
+                  "specialised geometry");
+    if (a.m1 == CM && a.m2 == CM && a.kw == KW && a.tM1 == (CM >> KW) && a.tM2 == (CM >> KW))
+        coarse_body<T, 1, false, CM, KW, (CM >> KW)>(a, lv, bz);
+    else
+        coarse_body<T, 1, false>(a, lv, bz);
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTC) void k_coarse(CoarseArgs<T> a)
 {
-    coarse_body<T, 1, false>(a, live_of<T>(a.p, a.beta_next), blockIdx.x);
+    coarse_scalar<T>(a, live_of<T>(a.p, a.beta_next), blockIdx.x);
 }
 // joint colour: all NCH channels in one workgroup
 template <typename T, int NCH>
@@ -2235,7 +2255,10 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
     } else {
         lv = live_of<T>(a.p, T(0));
     }
-    coarse_body<T, NCH, JOINT>(a, lv, JOINT ? 0 : blockIdx.x - start[img]);
+    if constexpr (!JOINT && NCH == 1)
+        coarse_scalar<T>(a, lv, blockIdx.x - start[img]);
+    else
+        coarse_body<T, NCH, JOINT>(a, lv, JOINT ? 0 : blockIdx.x - start[img]);
 }
 
 template <typename T>
