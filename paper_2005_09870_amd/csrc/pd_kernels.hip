@@ -983,11 +983,12 @@ struct CLayout {
 
 // NCH: channels handled by the workgroup (the joint colour prox couples them);
 // JOINT: the prox is the joint (group) one -- a compile-time choice, so the
-// scalar kernel carries no code of the other.  SM, SKW, STM: when nonzero,
-// the block side (square), the number of pass-by-pass levels and the tail
-// side as compile-time constants (the arguments then hold the same values):
-// the common geometry gets its index arithmetic folded at compile time.
-template <typename T, int NCH, bool JOINT, int SM = 0, int SKW = 0, int STM = 0>
+// scalar kernel carries no code of the other.  SM, SKW, STM, SNL, SOPS: when
+// nonzero, the block side (square), the number of pass-by-pass levels, the
+// tail side, the number of levels and the operations as compile-time
+// constants (the arguments then hold the same values): the common geometry
+// gets its index arithmetic folded at compile time.
+template <typename T, int NCH, bool JOINT, int SM = 0, int SKW = 0, int STM = 0, int SNL = 0, int SOPS = 0>
 __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T> &lv, int bz)
 {
     using G = CGeom<T>;
@@ -997,6 +998,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     const int m1 = SM ? SM : a.m1, m2 = SM ? SM : a.m2;
     const int kw = SKW ? SKW : a.kw;
     const int tM1 = STM ? STM : a.tM1, tM2 = STM ? STM : a.tM2;
+    const int nlev = SNL ? SNL : a.nlev, ops = SOPS ? SOPS : a.ops;
     const int ch0 = NCH > 1 ? 0 : bz;
     const CLayout<T> L(m1, m2, NCH);
     T *Cb = lds + L.c;
@@ -1005,9 +1007,9 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     const int tn = tM1 * tM2;
     const int cnt = m1 * m2;  // <= CPT * NTC
     const int tid = threadIdx.x;
-    const bool ana = (a.ops & COARSE_ANA) != 0, prox = (a.ops & COARSE_PROX) != 0;
+    const bool ana = (ops & COARSE_ANA) != 0, prox = (ops & COARSE_PROX) != 0;
     const bool need_z = !ana || prox;
-    const bool routed = NCH == 1 && !JOINT && ana && prox && (a.ops & COARSE_SYN) && kw > 0;
+    const bool routed = NCH == 1 && !JOINT && ana && prox && (ops & COARSE_SYN) && kw > 0;
     auto home = [&](int cc) { return lds + L.a + cc * m2 * G::PA; };
 
     // 1. every global load at once (clamped indices, no data-dependent branch):
@@ -1080,7 +1082,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     if (ana) {
 #pragma unroll
         for (int cc = 0; cc < NCH; ++cc)
-            coarse_analysis<T>(home(cc), B, Cb, m1, m2, a.nlev, a.f, kw, tM1, tM2, Mat, in_c);
+            coarse_analysis<T>(home(cc), B, Cb, m1, m2, nlev, a.f, kw, tM1, tM2, Mat, in_c);
         if (!prox) {  // plain forward transform
 #pragma unroll
             for (int cc = 0; cc < NCH; ++cc)
@@ -1103,9 +1105,9 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
             // counted (branch-free); all of them -> the approximation band (k = 0),
             // else the detail band of the first level that does not
             int inside = 0;
-            for (int lev = 0; lev < a.nlev; ++lev)  // uniform trip count
+            for (int lev = 0; lev < nlev; ++lev)  // uniform trip count
                 inside += (r < (m2 >> (lev + 1))) & (c < (m1 >> (lev + 1)));
-            const int band = inside == a.nlev ? 0 : a.band_top - inside;
+            const int band = inside == nlev ? 0 : a.band_top - inside;
             const T wband = wtab[band];
             const int li = r * G::PA + c;
             if (!JOINT) {
@@ -1115,7 +1117,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 T z = prox1(y, A[li], p.tau, w, st, bad);
                 lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
                 const T yn = momentum(z, zcr[0][k], lv.beta_next);
-                if (!routed || (kw < a.nlev && r < tM2 && c < tM1)) {
+                if (!routed || (kw < nlev && r < tM2 && c < tM1)) {
                     A[li] = yn;  // the tail's input (or the whole block)
                 } else {  // straight into the synthesis input of the level that reads it
                     int lev = kw - 1;
@@ -1156,12 +1158,12 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         if (lv.slots) block_slot_add<2, NTC>(st, lv.slots + PD_NSLOT);  // contains a barrier
         else __syncthreads();
     }
-    if (!(a.ops & COARSE_SYN)) return;
+    if (!(ops & COARSE_SYN)) return;
     // 3. synthesis of the block back to the level lc-1 approximation
 #pragma unroll
     for (int cc = 0; cc < NCH; ++cc) {
         T *A = home(cc);
-        coarse_synthesis<T>(A, B, Cb, m1, m2, a.nlev, a.f, kw, tM1, tM2, Mat + tn * tn, routed);
+        coarse_synthesis<T>(A, B, Cb, m1, m2, nlev, a.f, kw, tM1, tM2, Mat + tn * tn, routed);
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int e = tid + k * NTC;
@@ -1660,17 +1662,25 @@ __global__ __launch_bounds__(NT) void k_analysis(AnalysisArgs<T> a)
 
 // The scalar coarse body, specialised for the geometry every large
 // power-of-two plane reaches (a CM x CM block, levels down to an 8 x 8 tail):
-// 64 x 64 with 3 pass-by-pass levels in FP32, 32 x 32 with 2 in FP64.
+// 64 x 64 with 3 pass-by-pass levels in FP32, 32 x 32 with 2 in FP64; and
+// within it for the full depth (down to 1 x 1) with the operations of every
+// middle iteration.
 template <typename T>
 __device__ __forceinline__ void coarse_scalar(const CoarseArgs<T> &a, const Live<T> &lv, int bz)
 {
-    constexpr int CM = CGeom<T>::CM, KW = sizeof(T) == 4 ? 3 : 2;
+    constexpr int CM = CGeom<T>::CM, KW = sizeof(T) == 4 ? 3 : 2, NL = sizeof(T) == 4 ? 6 : 5;
+    constexpr int ALL = COARSE_ANA | COARSE_PROX | COARSE_SYN;
     static_assert((CM >> KW) * (CM >> KW) <= PD_TAIL_MAX && (CM >> (KW - 1)) * (CM >> (KW - 1)) > PD_TAIL_MAX,
                   "specialised geometry");
-    if (a.m1 == CM && a.m2 == CM && a.kw == KW && a.tM1 == (CM >> KW) && a.tM2 == (CM >> KW))
-        coarse_body<T, 1, false, CM, KW, (CM >> KW)>(a, lv, bz);
-    else
+    static_assert((CM >> NL) == 1, "full depth");
+    if (a.m1 == CM && a.m2 == CM && a.kw == KW && a.tM1 == (CM >> KW) && a.tM2 == (CM >> KW)) {
+        if (a.nlev == NL && a.ops == ALL)
+            coarse_body<T, 1, false, CM, KW, (CM >> KW), NL, ALL>(a, lv, bz);
+        else
+            coarse_body<T, 1, false, CM, KW, (CM >> KW)>(a, lv, bz);
+    } else {
         coarse_body<T, 1, false>(a, lv, bz);
+    }
 }
 
 template <typename T>
