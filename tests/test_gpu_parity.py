@@ -442,26 +442,34 @@ def test_blur_variants_reverse_mode_is_bitwise(n1, n2):
                 assert torch.equal(a, b), v
 
 
-@pytest.mark.parametrize("n1,n2,C,levels", [(512, 512, 1, 9), (160, 96, 2, 5), (256, 128, 1, 3), (1024, 64, 1, 6),
-                                             (512, 256, 1, 2)])
+@pytest.mark.parametrize("n1,n2,C,levels,coeff", [(512, 512, 1, 9, False), (160, 96, 2, 5, False),
+                                                   (256, 128, 1, 3, False), (1024, 64, 1, 6, False),
+                                                   (512, 256, 1, 2, False), (512, 512, 1, 9, True),
+                                                   (352, 224, 1, 5, True)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_fused_synthesis_levels_are_bitwise(n1, n2, C, levels, dtype):
+def test_fused_levels_are_bitwise(n1, n2, C, levels, coeff, dtype):
     """The two coarsest fine synthesis levels in one launch give the same
-    iterates, statistics aside, bit for bit as two launches (and pd_fwt's
-    inverse transform the same output)."""
-    pb, f0, case = _problem(n1, n2, C=C, levels=levels, seed=99)
+    iterates and, statistics aside, bit for bit as one launch per level (and
+    pd_fwt's forward and inverse transforms the same output), with level or
+    per-coefficient weights."""
+    pb, f0, case = _problem(n1, n2, C=C, levels=levels, seed=99, coeff=coeff)
     f0t = _t(f0, dtype)
     op = _op(pb, dtype)
+    cw = _t(pb.w, dtype) if coeff else None
     outs = {}
     try:
         for fuse in (True, False):
             P.pd_fuse_enable(fuse)
-            outs[fuse] = (P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 30, level_w=case.level_w),
-                          P.pd_fwt(f0t, _h(), pb.levels, inverse=True))
+            kw = dict(coeff_w=cw) if coeff else dict(level_w=case.level_w)
+            outs[fuse] = (P.pd_solve(f0t, op, _h(), pb.levels, 0.85, 30, stats=True, **kw),
+                          P.pd_fwt(f0t, _h(), pb.levels, inverse=True),
+                          P.pd_fwt(f0t, _h(), pb.levels))
     finally:
         P.pd_fuse_enable(True)
     for k in ("f", "z_cur", "z_prev"):
         assert torch.equal(outs[True][0][k], outs[False][0][k]), k
+    np.testing.assert_allclose(_np(outs[True][0]["stats"]), _np(outs[False][0]["stats"]), rtol=1e-12)
     assert torch.equal(outs[True][1], outs[False][1])
+    assert torch.equal(outs[True][2], outs[False][2])
     ref = O.fista(pb, f0, 0.85, 30)
     assert np.abs(_np(outs[True][0]["f"]) - ref["f"]).max() < (1e-10 if dtype == torch.float64 else 1e-5)
