@@ -445,7 +445,7 @@ def test_blur_variants_reverse_mode_is_bitwise(n1, n2):
 @pytest.mark.parametrize("n1,n2,C,levels,coeff", [(512, 512, 1, 9, False), (160, 96, 2, 5, False),
                                                    (256, 128, 1, 3, False), (1024, 64, 1, 6, False),
                                                    (512, 256, 1, 2, False), (512, 512, 1, 9, True),
-                                                   (352, 224, 1, 5, True)])
+                                                   (352, 224, 1, 5, True), (320, 256, 2, 6, False)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fused_levels_are_bitwise(n1, n2, C, levels, coeff, dtype):
     """The two coarsest fine synthesis levels in one launch give the same
