@@ -139,6 +139,21 @@ def time_forward(torch, P, case, op, f0, tau, iters, steps, warmup, h):
     return wall, ev_ms, r, step
 
 
+def fp64_case(torch, P, SI, h, iters):
+    """The same 512^2 workload with FP64 state and arithmetic (the paper's own
+    GPU figure is in FP64): forward Mpixel-iter/s, graph-replayed like the
+    headline."""
+    case, op32, f0_32, tau = make_problem(torch, P, SI)
+    n = case.n1
+    op = P.Operator.op1(n, dtype=torch.float64, device="cuda")
+    f0 = f0_32.double()
+    wall, ev_ms, r, _ = time_forward(torch, P, case, op, f0, tau, iters, 2, 1, h)
+    ms = ev_ms / 2
+    return {"workload": f"512x512 FP64, {iters} iterations", "mpx_it_s": round(n * n * iters / (ms / 1e3) / 1e6, 1),
+            "us_per_iter": round(1e3 * ms / iters, 2),
+            "alg_frac_40B": round(n * n * iters / (ms / 1e3) * 40 / (HBM_PEAK_GBS * 1e9), 5)}
+
+
 def kernel_table(torch, P, step):
     """One instrumented step: per-launch HIP events recorded by the library."""
     P.solver.pd_timing_enable(True)
@@ -649,6 +664,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--fp64-iters", type=int, default=500)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=1000)
     ap.add_argument("--batched-count", type=int, default=64)
@@ -720,6 +737,9 @@ def main():
             # the method's compulsory traffic in (y, z_prev) form -- read y, z_prev and f0, write z
             # and y+, 4 B each: 20 B per pixel-iteration -- at this rate, as a fraction of HBM peak
             "alg_frac_20B": round(value * 1e6 * 20 / (HBM_PEAK_GBS * 1e9), 5)}
+    if not args.no_fp64:
+        log(f"[bench] 512x512 FP64, {args.fp64_iters} iterations")
+        line["fp64_512"] = fp64_case(torch, P, SI, h, args.fp64_iters)
     if not args.no_batched:
         log(f"[bench] batched vs per-image: {args.batched_count} images, {args.batched_iters} iterations")
         line["batched"] = batched_vs_per_image(torch, P, SI, h, args.batched_iters, args.batched_count)
