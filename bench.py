@@ -376,7 +376,7 @@ def fwd_bwd_512(torch, P, SI, h, iters=200, ce=20):
             "ms_fwd_bwd": round(1e3 * res["fwd_bwd"], 2), "ms_fwd": round(1e3 * res["fwd"], 2)}
 
 
-def colour_case(torch, P, SI, h, iters, n=2048):
+def colour_case(torch, P, SI, h, iters, n=2048, pin=0):
     """2048 x 2048 x 3, joint (group) shrinkage across channels, noise 0.1 + 5%
     salt-and-pepper, lambda 0.1: forward solve Mpixel-iter/s (pixels x
     channels) and the dominant kernel's HBM roofline."""
@@ -391,7 +391,7 @@ def colour_case(torch, P, SI, h, iters, n=2048):
     tau = P.step_size(op, n, n, device=dev)
     shape = P.solver._shape(f0, c.levels)
     ws = P.solver.workspace(P.pd_workspace_size(shape, f0.dtype), f0.device)
-    blur_variant = P.pd_tune(f0, op, c.levels)
+    blur_variant = P.pd_tune(f0, op, c.levels, pin=pin)
 
     def run(k):
         return P.pd_solve(f0, op, h, c.levels, tau, k, level_w=c.level_w, joint=True, ws=ws, stats=True)
@@ -665,6 +665,8 @@ def main():
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--blur-variant-512", type=int, default=0)     # 0: tuned
+    ap.add_argument("--blur-variant-colour", type=int, default=0)  # 0: tuned
     ap.add_argument("--fp64-iters", type=int, default=500)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=1000)
@@ -702,7 +704,9 @@ def main():
     h = P.pd_symmlet(6)
     case, op, f0, tau = make_problem(torch, P, SI)
     n = case.n1
-    blur_variant = P.pd_tune(f0, op, case.levels)  # the autotuner's blur variant for this size
+    # the autotuner's blur variant for this size (or the one named: profiles pin it, since counter
+    # collection serialises launches and distorts the tuner's timing)
+    blur_variant = P.pd_tune(f0, op, case.levels, pin=args.blur_variant_512)
     log(f"[bench] 512x512 FP32, {args.iters} iterations, tau={tau:.6f}, steps={args.steps}, warmup={args.warmup}")
     wall, ev_ms, r, step = time_forward(torch, P, case, op, f0, tau, args.iters, args.steps,
                                         args.warmup, h)
@@ -750,7 +754,7 @@ def main():
         line["fwd_bwd_512"] = fwd_bwd_512(torch, P, SI, h)
     if not args.no_colour:
         log(f"[bench] colour 2048^2 x 3, {args.colour_iters} iterations")
-        line["colour_2048x3"] = colour_case(torch, P, SI, h, args.colour_iters)
+        line["colour_2048x3"] = colour_case(torch, P, SI, h, args.colour_iters, pin=args.blur_variant_colour)
     if not args.no_wavelet:
         log(f"[bench] wavelet domain 1024^2 (FISTA-W / FISTA-WP), {args.wavelet_iters} iterations")
         line["wavelet_1024"] = wavelet_case(torch, P, SI, h, args.wavelet_iters)
