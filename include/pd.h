@@ -304,6 +304,29 @@ int pd_symmlet(int32_t moments, double *h_out);
 int pd_op1_taps(int32_t n2, double sigma_max, double mass, int32_t *radius,
                 double *taps_out);
 
+/* Host: rank-`terms` product-convolution expansion H ~ sum_k u_k * (v_k . x)
+ * of Operator 1 (Section 3.3.3): a randomized SVD of its space-varying impulse
+ * response S, which has one row per window offset (d2, d1), row-major over
+ * [-R, R]^2, and one column per source row y (the response of Operator 1
+ * depends on the source row only): S[(d2, d1), y] = taps[y][d2+R] taps[y][d1+R].
+ * The range of S is sampled with terms + oversample Gaussian vectors (a
+ * SplitMix64 stream of `seed`, Box-Muller), refined by power_iters rounds of
+ * subspace iteration and the projected matrix is decomposed exactly (one-sided
+ * Jacobi); only products with S and S^T are formed.
+ *   taps        host double [n2][2R+1], e.g. from pd_op1_taps; R = radius <= 64
+ *   terms       requested rank, >= 1; oversample in [0, 64]; power_iters in [0, 16]
+ *   u_out       host double [terms][(2R+1)^2]: orthonormal kernels, each with its
+ *               entry of largest magnitude positive
+ *   v_out       host double [terms][n2]: v_k(y) = <S(., y), u_k>, the multiplier
+ *               of source row y (the same for every column of the row)
+ *   sv_out      host double [terms] singular values, descending (may be NULL)
+ *   terms_out   the rank produced: at most terms, terms + oversample, n2 and
+ *               (2R+1)^2, and only singular values above 1e-14 of the largest
+ * Returns PD_ERR_ARG for bad arguments or S = 0; never touches the GPU. */
+int pd_pc_expansion(const double *taps, int32_t n2, int32_t radius, int32_t terms,
+                    int32_t oversample, int32_t power_iters, uint64_t seed,
+                    double *u_out, double *v_out, double *sv_out, int32_t *terms_out);
+
 /* ---------------------------------------------------------------------------
  * FISTA in the wavelet domain (Section 4.3, eq. 4.3, and Appendix A.1).
  * Eq. 4.1 approximated as

@@ -24,6 +24,7 @@ from .solver import (  # noqa: F401
     pd_graphs_enable,
     pd_fuse_enable,
     pd_op1_taps,
+    pd_pc_expansion,
     pd_solve,
     pd_solve_batched,
     pd_solve_noalloc,

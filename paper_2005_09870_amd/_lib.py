@@ -62,7 +62,7 @@ class pd_image_desc(ctypes.Structure):
 EXPORTS = [
     "pd_workspace_size", "pd_solve", "pd_solve_noalloc", "pd_batched_workspace_size", "pd_solve_batched",
     "pd_backward_workspace_size", "pd_backward", "pd_solve_checkpointed", "pd_backward_checkpointed", "pd_fwt", "pd_apply_op", "pd_tune", "pd_symmlet",
-    "pd_op1_taps", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable", "pd_fuse_enable",
+    "pd_op1_taps", "pd_pc_expansion", "pd_strerror", "pd_timing_enable", "pd_timing_read", "pd_graphs_enable", "pd_fuse_enable",
     "pd_csr_transpose_workspace_size", "pd_csr_transpose", "pd_spmv", "pd_wjacobi",
     "pd_wsolve_workspace_size", "pd_wsolve", "pd_admm_workspace_size", "pd_admm_solve",
     "pd_fft2_workspace_size", "pd_fft2", "pd_decompose_workspace_size", "pd_decompose",
@@ -127,6 +127,8 @@ def load() -> ctypes.CDLL:
     L.pd_symmlet.restype = ctypes.c_int
     L.pd_op1_taps.argtypes = [i32, d, d, P(i32), dp]
     L.pd_op1_taps.restype = ctypes.c_int
+    L.pd_pc_expansion.argtypes = [dp, i32, i32, i32, i32, i32, ctypes.c_uint64, dp, dp, dp, P(i32)]
+    L.pd_pc_expansion.restype = ctypes.c_int
     L.pd_timing_enable.argtypes = [i32]
     L.pd_timing_enable.restype = ctypes.c_int
     L.pd_fuse_enable.argtypes = [i32]

@@ -1,9 +1,10 @@
-// pd_setup.cpp -- host-side set-up of a solve: the Symmlet filter bank and
-// the Operator-1 tap table (Escande & Weiss, arXiv:2005.09870, Sections 2.1,
-// 4.1, 4.2).  Plain C++, no GPU code.
+// pd_setup.cpp -- host-side set-up of a solve: the Symmlet filter bank, the
+// Operator-1 tap table and its product-convolution expansion (Escande & Weiss,
+// arXiv:2005.09870, Sections 2.1, 3.3.3, 4.1, 4.2).  Plain C++, no GPU code.
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <vector>
 
 #include "pd.h"
@@ -248,6 +249,197 @@ extern "C" int pd_op1_taps(int32_t n2, double sigma_max, double mass, int32_t *r
         for (int d = -rr[i]; d <= rr[i]; ++d) row[R + d] = (double)(p[d + rr[i]] / s);
     }
     return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Product-convolution expansion of Operator 1 by a randomized SVD of its SVIR
+// (Section 3.3.3; the range finder with subspace iteration and the direct SVD
+// of the projected matrix of Halko, Martinsson and Tropp).  S has one row per
+// offset (d2, d1) of the (2R+1)^2 window, row-major, and one column per source
+// row y (Operator 1's response depends on the source row only): S[(a, b), y] =
+// p_y[a] p_y[b], p_y the row's profile.  Only products with S and S^T are used.
+// ---------------------------------------------------------------------------
+namespace {
+
+// SplitMix64 (Steele, Lea and Flood, 2014) as a counter-based generator.
+uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+// Standard normal number i of stream `seed` (Box-Muller on two uniforms in (0, 1)).
+double gauss(uint64_t seed, uint64_t i)
+{
+    const uint64_t a = splitmix64(seed ^ splitmix64(2 * i)), b = splitmix64(seed ^ splitmix64(2 * i + 1));
+    const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53, u2 = ((double)(b >> 11) + 0.5) * 0x1.0p-53;
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586476925286766559 * u2);
+}
+
+struct Svir {
+    const double *taps;
+    int n2, W;
+    int rows() const { return W * W; }
+    // out[W W] = S x, x[n2]
+    void apply(const double *x, double *out) const
+    {
+        std::fill(out, out + rows(), 0.0);
+        for (int y = 0; y < n2; ++y) {
+            if (x[y] == 0.0) continue;
+            const double *p = taps + (size_t)y * W;
+            for (int a = 0; a < W; ++a) {
+                const double t = x[y] * p[a];
+                for (int b = 0; b < W; ++b) out[a * W + b] += t * p[b];
+            }
+        }
+    }
+    // out[n2] = S^T q, q[W W]
+    void apply_t(const double *q, double *out) const
+    {
+        for (int y = 0; y < n2; ++y) {
+            const double *p = taps + (size_t)y * W;
+            double s = 0.0;
+            for (int a = 0; a < W; ++a) {
+                double r = 0.0;
+                for (int b = 0; b < W; ++b) r += q[a * W + b] * p[b];
+                s += p[a] * r;
+            }
+            out[y] = s;
+        }
+    }
+};
+
+double dot(const double *a, const double *b, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+// Orthonormal basis of the k columns of Y (column j at Y + j n) by modified
+// Gram-Schmidt, each column orthogonalised twice; a column left with at most
+// 1e-13 of its norm (Y rank-deficient) becomes zero.  Returns the rank.
+int orthonormalise(std::vector<double> &Y, int n, int k)
+{
+    int rank = 0;
+    for (int j = 0; j < k; ++j) {
+        double *c = Y.data() + (size_t)j * n;
+        const double n0 = std::sqrt(dot(c, c, n));
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < j; ++i) {
+                const double *q = Y.data() + (size_t)i * n;
+                const double r = dot(q, c, n);
+                for (int t = 0; t < n; ++t) c[t] -= r * q[t];
+            }
+        const double nr = std::sqrt(dot(c, c, n));
+        if (n0 == 0.0 || nr <= 1e-13 * n0) {
+            std::fill(c, c + n, 0.0);
+            continue;
+        }
+        for (int t = 0; t < n; ++t) c[t] /= nr;
+        ++rank;
+    }
+    return rank;
+}
+
+// One-sided Jacobi (Hestenes): rotates the k columns of G (column j at G + j n)
+// until they are mutually orthogonal, accumulating the rotations in J (k x k,
+// column-major, starts as the identity).  Afterwards G = G0 J has orthogonal
+// columns whose norms are the singular values of G0.
+void jacobi_svd(std::vector<double> &G, int n, int k, std::vector<double> &J)
+{
+    J.assign((size_t)k * k, 0.0);
+    for (int j = 0; j < k; ++j) J[(size_t)j * k + j] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < k; ++i)
+            for (int j = i + 1; j < k; ++j) {
+                double *gi = G.data() + (size_t)i * n, *gj = G.data() + (size_t)j * n;
+                const double a = dot(gi, gi, n), b = dot(gj, gj, n), c = dot(gi, gj, n);
+                if (c == 0.0 || std::fabs(c) <= 1e-15 * std::sqrt(a * b)) continue;
+                off = std::max(off, std::fabs(c) / std::sqrt(a * b));
+                // the rotation that zeroes the (i, j) entry of the 2 x 2 Gram matrix
+                const double zeta = (b - a) / (2.0 * c);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+                for (int r = 0; r < n; ++r) {
+                    const double x = gi[r], y = gj[r];
+                    gi[r] = cs * x - sn * y;
+                    gj[r] = sn * x + cs * y;
+                }
+                double *ji = J.data() + (size_t)i * k, *jj = J.data() + (size_t)j * k;
+                for (int r = 0; r < k; ++r) {
+                    const double x = ji[r], y = jj[r];
+                    ji[r] = cs * x - sn * y;
+                    jj[r] = sn * x + cs * y;
+                }
+            }
+        if (off <= 1e-15) break;
+    }
+}
+
+}  // namespace
+
+extern "C" int pd_pc_expansion(const double *taps, int32_t n2, int32_t radius, int32_t terms, int32_t oversample,
+                               int32_t power_iters, uint64_t seed, double *u_out, double *v_out, double *sv_out,
+                               int32_t *terms_out)
+{
+    if (!taps || !u_out || !v_out || !terms_out || n2 < 1 || radius < 0 || radius > 64 || terms < 1 ||
+        oversample < 0 || oversample > 64 || power_iters < 0 || power_iters > 16)
+        return PD_ERR_ARG;
+    const int W = 2 * radius + 1, M = W * W;
+    const Svir S{taps, n2, W};
+    const int k = std::min({terms + oversample, n2, M});
+    // range finder: Y = S Omega, Omega n2 x k Gaussian; then power_iters rounds
+    // of Q <- orth(S orth(S^T Q))
+    std::vector<double> Y((size_t)M * k), Z((size_t)n2 * k), om(n2);
+    for (int j = 0; j < k; ++j) {
+        for (int y = 0; y < n2; ++y) om[y] = gauss(seed, (uint64_t)j * n2 + y);
+        S.apply(om.data(), Y.data() + (size_t)j * M);
+    }
+    int rank = orthonormalise(Y, M, k);
+    for (int it = 0; it < power_iters && rank > 0; ++it) {
+        for (int j = 0; j < k; ++j) S.apply_t(Y.data() + (size_t)j * M, Z.data() + (size_t)j * n2);
+        orthonormalise(Z, n2, k);
+        for (int j = 0; j < k; ++j) S.apply(Z.data() + (size_t)j * n2, Y.data() + (size_t)j * M);
+        rank = orthonormalise(Y, M, k);
+    }
+    // B = Q^T S (k x n2), held as its transpose G = S^T Q (column j = S^T q_j);
+    // B = J Sigma V^T from the one-sided Jacobi of G, so u = Q J
+    std::vector<double> G((size_t)n2 * k), J;
+    for (int j = 0; j < k; ++j) S.apply_t(Y.data() + (size_t)j * M, G.data() + (size_t)j * n2);
+    jacobi_svd(G, n2, k, J);
+    std::vector<double> sv(k);
+    std::vector<int> ord(k);
+    for (int j = 0; j < k; ++j) {
+        sv[j] = std::sqrt(dot(G.data() + (size_t)j * n2, G.data() + (size_t)j * n2, n2));
+        ord[j] = j;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return sv[a] > sv[b]; });
+    int m = 0;
+    while (m < std::min(terms, k) && sv[ord[m]] > 0.0 && sv[ord[m]] > 1e-14 * sv[ord[0]]) ++m;
+    std::vector<double> u(M);
+    for (int t = 0; t < m; ++t) {
+        const int j = ord[t];
+        std::fill(u.begin(), u.end(), 0.0);
+        for (int i = 0; i < k; ++i) {
+            const double c = J[(size_t)j * k + i];
+            const double *q = Y.data() + (size_t)i * M;
+            for (int r = 0; r < M; ++r) u[r] += c * q[r];
+        }
+        const double nu = std::sqrt(dot(u.data(), u.data(), M));
+        int big = 0;  // sign: the entry of largest magnitude is positive
+        for (int r = 1; r < M; ++r)
+            if (std::fabs(u[r]) > std::fabs(u[big])) big = r;
+        const double sc = (u[big] < 0.0 ? -1.0 : 1.0) / nu;
+        for (int r = 0; r < M; ++r) u_out[(size_t)t * M + r] = u[r] * sc;
+        S.apply_t(u_out + (size_t)t * M, v_out + (size_t)t * n2);  // v_t(y) = <S(., y), u_t>
+        if (sv_out) sv_out[t] = sv[j];
+    }
+    *terms_out = m;
+    return m > 0 ? PD_OK : PD_ERR_ARG;
 }
 
 extern "C" const char *pd_strerror(int32_t status)

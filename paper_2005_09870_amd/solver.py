@@ -61,6 +61,24 @@ def pd_op1_taps(n2: int, sigma_max: float = 3.0, mass: float = 0.99):
     return taps, r.value
 
 
+def pd_pc_expansion(taps, radius: int, terms: int, oversample: int = 10, power_iters: int = 2, seed: int = 0):
+    """Rank-`terms` product-convolution expansion of a row-profile operator by
+    libpd's randomized SVD of its impulse responses (Section 3.3.3).  Returns
+    (u (m, 2R+1, 2R+1), v (m, n2), singular values (m,)), m <= terms."""
+    taps = np.ascontiguousarray(taps, dtype=np.float64)
+    n2, W = taps.shape
+    if W != 2 * radius + 1:
+        raise ValueError("taps must be (n2, 2R+1)")
+    u = np.zeros((terms, W * W))
+    v = np.zeros((terms, n2))
+    sv = np.zeros(terms)
+    m = ctypes.c_int32()
+    C.check(C.load().pd_pc_expansion(_dptr(taps), n2, radius, terms, oversample, power_iters, seed, _dptr(u),
+                                     _dptr(v), _dptr(sv), ctypes.byref(m)), "pd_pc_expansion")
+    k = m.value
+    return u[:k].reshape(k, W, W).copy(), v[:k].copy(), sv[:k].copy()
+
+
 @dataclass
 class Operator:
     """Blur operator on the device: PD_OP_IDENTITY, a row-profile table

@@ -43,6 +43,86 @@ def test_op1_taps_match_oracle():
         np.testing.assert_allclose(t, kt, atol=1e-15)
 
 
+def _svir(taps):
+    """S of a row-profile operator, dense: S[(a, b), y] = taps[y, a] taps[y, b]."""
+    n2, W = taps.shape
+    return np.einsum("ya,yb->aby", taps, taps).reshape(W * W, n2)
+
+
+def test_pc_expansion_matches_exact_svd():
+    """pd_pc_expansion (randomized SVD, Section 3.3.3) against the oracle's exact
+    SVD of the same S: the singular values and the rank-m truncation
+    sum_k u_k v_k^T (unique while sigma_m > sigma_m+1), Operator 1 at several
+    heights and ranks, and the oracle's own u, v up to the sign of each term."""
+    from oracle import product_convolution as PC
+    for n2, m in ((64, 5), (256, 5), (512, 12), (128, 25), (1024, 5)):
+        taps, R = S.pd_op1_taps(n2)
+        u, v, sv = S.pd_pc_expansion(taps, R, m)
+        ue, ve, sve = PC.pc_expansion(taps, R, m)
+        k = min(m, ue.shape[0])
+        assert u.shape == (k, 2 * R + 1, 2 * R + 1) and v.shape == (k, n2)
+        np.testing.assert_allclose(sv, sve[:k], rtol=1e-10, atol=1e-12 * sve[0])
+        W2 = (2 * R + 1) ** 2
+        approx = u.reshape(k, W2).T @ v
+        exact = ue.reshape(-1, W2)[:k].T @ ve[:k]
+        np.testing.assert_allclose(approx, exact, atol=1e-10 * sve[0])
+        for t in range(k):
+            if t + 1 < k and sve[t] - sve[t + 1] < 1e-6 * sve[0]:
+                continue  # a near-degenerate pair: only the truncation is unique
+            s = np.sign(np.dot(u[t].ravel(), ue[t].ravel()))
+            np.testing.assert_allclose(u[t] * s, ue[t], atol=1e-8)
+            np.testing.assert_allclose(v[t] * s, ve[t], atol=1e-8 * sve[0])
+
+
+def test_pc_expansion_pins():
+    """Pins of pd_pc_expansion that do not use the oracle: at full rank the terms
+    rebuild S exactly and sum sigma^2 = ||S||_F^2; the kernels are orthonormal
+    with their largest entry positive; v_k = S^T u_k and ||v_k|| = sigma_k; a
+    single profile (rank-one S) gives one term whatever the request; the
+    result does not depend on the seed beyond rounding."""
+    taps, R = S.pd_op1_taps(48)
+    Sm = _svir(taps)
+    full = min(Sm.shape)
+    u, v, sv = S.pd_pc_expansion(taps, R, full, oversample=0, power_iters=1)
+    k = u.shape[0]
+    U = u.reshape(k, -1)
+    np.testing.assert_allclose(U.T @ v, Sm, atol=1e-12 * sv[0])
+    np.testing.assert_allclose(np.sum(sv ** 2), np.sum(Sm ** 2), rtol=1e-12)
+    np.testing.assert_allclose(U @ U.T, np.eye(k), atol=1e-12)
+    assert np.all(np.diff(sv) <= 0)
+    for t in range(k):
+        assert U[t, np.argmax(np.abs(U[t]))] > 0
+    np.testing.assert_allclose(v, U @ Sm, atol=1e-14)
+    np.testing.assert_allclose(np.linalg.norm(v, axis=1), sv, rtol=1e-10, atol=1e-13 * sv[0])
+    one = np.tile(np.array([[0.25, 0.5, 0.25]]), (10, 1))
+    u1, v1, s1 = S.pd_pc_expansion(one, 1, 5)
+    assert u1.shape[0] == 1
+    np.testing.assert_allclose(u1[0], np.outer(one[0], one[0]) / np.linalg.norm(np.outer(one[0], one[0])),
+                               atol=1e-15)
+    a = S.pd_pc_expansion(taps, R, 5, seed=1)
+    b = S.pd_pc_expansion(taps, R, 5, seed=12345)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, atol=1e-10)
+
+
+def test_pc_expansion_argument_errors():
+    L = C.load()
+    taps, R = S.pd_op1_taps(16)
+    u = np.zeros((5, (2 * R + 1) ** 2))
+    v = np.zeros((5, 16))
+    m = ctypes.c_int32()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    ok = (dp(taps), 16, R, 5, 10, 2, 0, dp(u), dp(v), None, ctypes.byref(m))
+    assert L.pd_pc_expansion(*ok) == C.PD_OK and m.value == 5
+    for i, bad in ((0, None), (1, 0), (2, -1), (2, 65), (3, 0), (4, -1), (5, 17), (7, None), (8, None),
+                   (10, None)):
+        args = list(ok)
+        args[i] = bad
+        assert L.pd_pc_expansion(*args) == C.PD_ERR_ARG, i
+    zero = np.zeros_like(taps)
+    assert L.pd_pc_expansion(dp(zero), 16, R, 5, 10, 2, 0, dp(u), dp(v), None, ctypes.byref(m)) == C.PD_ERR_ARG
+
+
 def _fake(n):
     return ctypes.c_void_p(0x1000 * n)
 
