@@ -480,8 +480,14 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
 {
     constexpr bool JOINT = NCH > 0;
     constexpr int NC = JOINT ? NCH : 1;
-    __shared__ T sIn[AR][AR + 4];  // pitch 56: aligned 16-byte reads
-    __shared__ T sRow[2][AR][TC + 1];  // low / high along x1
+    // LDS layouts without bank conflicts: the x1 pass reads 16-byte runs of
+    // sIn rows with the lanes of a 16-lane group on consecutive rows (pitch 52 =
+    // 13 x 16 bytes: each row starts on a different 16-byte bank group), and
+    // writes its four outputs per row as one 16-byte store; the x2 pass reads
+    // sRow columns with four row blocks per wave, which a pitch of 20 puts on
+    // disjoint banks (a block's rows are 4 x 20 = 80 values = 16 banks apart)
+    __shared__ __attribute__((aligned(16))) T sIn[AR][AR];
+    __shared__ __attribute__((aligned(16))) T sRow[2][AR][TC + 4];  // low / high along x1
     const int M1c = a.M1c, M2c = a.M2c;
     const int M1 = 2 * M1c, M2 = 2 * M2c;
     const int c01 = bx * TC, c02 = by * TC;
@@ -555,12 +561,14 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
         for (int i = 0; i < RPW; ++i)
             if (lok) sIn[wv + i * (NT / 64)][lane] = v[cc][i];
         __syncthreads();
-        // along x1: task = (fine row r, block of 4 coarse columns)
+        // along x1: task = (fine row r, block of 4 coarse columns), lanes on rows
         for (int t = tid; t < AR * (TC / 4); t += NT) {
-            int r = t / (TC / 4), blk = t - r * (TC / 4);
+            const int blk = t / AR, r = t - blk * AR;
             T x[28];
 #pragma unroll
             for (int j = 0; j < 28; ++j) x[j] = sIn[r][8 * blk + j];
+            using V4 = T __attribute__((ext_vector_type(4)));
+            V4 lo4, hi4;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 T lo = T(0), hi = T(0);
@@ -569,9 +577,11 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
                     lo = fma(a.f.h[m], x[2 * q + m + 10], lo);
                     hi = fma(a.f.g[m], x[2 * q + m], hi);
                 }
-                sRow[0][r][4 * blk + q] = lo;
-                sRow[1][r][4 * blk + q] = hi;
+                lo4[q] = lo;
+                hi4[q] = hi;
             }
+            *reinterpret_cast<V4 *>(&sRow[0][r][4 * blk]) = lo4;
+            *reinterpret_cast<V4 *>(&sRow[1][r][4 * blk]) = hi4;
         }
         __syncthreads();
         // along x2: 2 coarse rows of both x2 filters for one column of one band
