@@ -73,6 +73,8 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
         return 2.75 * es * m
     if kernel == "synthesis2":  # levels `level` and level + 1 in one launch
         return 2.75 * es * m + 2.75 * es * m / 4
+    if kernel == "synthesis3":  # levels `level` .. level + 2 in one launch
+        return 2.75 * es * m * (1.0 + 1.0 / 4 + 1.0 / 16)
     if kernel == "analysis":
         return (2.0 if plain else 3.5 + (0.75 if coeff_w else 0.0)) * es * m
     return 0.0

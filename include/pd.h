@@ -515,7 +515,9 @@ typedef enum {
     PD_K_DECOMP = 10,   /* Algorithm 1: level 0 probe convolutions, 1 multiplier,
                            2 spreading of B_k columns over A~_k, 3 count, 4 fill */
     PD_K_SYNTH2 = 11,   /* two synthesis levels in one launch (level = the finer) */
-    PD_K_JPROX = 12     /* joint colour prox over the whole coefficient plane  */
+    PD_K_JPROX = 12,    /* joint colour prox over the whole coefficient plane  */
+    PD_K_SYNTH3 = 13    /* three synthesis levels in one launch (level = the
+                           finest)                                             */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */
@@ -539,9 +541,9 @@ int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *l
  * recomputation.  Process-wide; not thread-safe. */
 int pd_graphs_enable(int32_t enable);
 
-/* Fusion of the two coarsest fine synthesis levels into one launch (default
- * on; results are bitwise the same either way).  Process-wide; not
- * thread-safe. */
+/* Fusion of the three (or, with two fine levels, two) coarsest fine synthesis
+ * levels into one launch (default on; results are bitwise the same either
+ * way).  Process-wide; not thread-safe. */
 int pd_fuse_enable(int32_t enable);
 
 /* Short description of a pd_status code. */

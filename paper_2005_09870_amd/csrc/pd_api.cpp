@@ -24,7 +24,7 @@ using namespace pd;
 
 namespace {
 
-bool g_synth2 = true;  // the two coarsest fine synthesis levels in one launch (pd_fuse_enable)
+bool g_synth2 = true;  // the coarsest fine synthesis levels (three, or two) in one launch (pd_fuse_enable)
 
 bool is_pow2_divisible(int n, int L) { return L >= 0 && L < 31 && (n % (1 << L)) == 0; }
 
@@ -342,7 +342,12 @@ int synth_fine(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIte
         return a;
     };
     int lev = c.lc - 1;
-    if (lev >= 2 && g_synth2) {  // the two coarsest fine levels in one launch
+    if (lev >= 3 && g_synth2) {  // the three coarsest fine levels in one launch
+        const SynthArgs<T> v = args(lev), u = args(lev - 1), d = args(lev - 2);
+        PD_TRY_HIP(
+            timed(PD_K_SYNTH3, lev - 2, c.st, [&] { return launch_synth3<T>(d, u, v, c.sh->channels, c.st); }));
+        lev -= 3;
+    } else if (lev >= 2 && g_synth2) {  // the two coarsest fine levels in one launch
         const SynthArgs<T> u = args(lev), d = args(lev - 1);
         PD_TRY_HIP(timed(PD_K_SYNTH2, lev - 1, c.st, [&] { return launch_synth2<T>(d, u, c.sh->channels, c.st); }));
         lev -= 2;

@@ -168,6 +168,9 @@ template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipS
 // (its output, d's approximation band, stays in LDS; u.out is not written)
 template <typename T>
 hipError_t launch_synth2(const SynthArgs<T> &d, const SynthArgs<T> &u, int C, hipStream_t s);
+// Levels D + 2, D + 1 and D in one launch (v, u, d), the same bits as three single-level launches
+template <typename T>
+hipError_t launch_synth3(const SynthArgs<T> &d, const SynthArgs<T> &u, const SynthArgs<T> &v, int C, hipStream_t s);
 template <typename T> hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_coarse(const CoarseArgs<T> &a, int groups, hipStream_t s);
 template <typename T> hipError_t launch_jprox(const JProxArgs<T> &a, int nch, hipStream_t s);

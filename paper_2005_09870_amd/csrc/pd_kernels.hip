@@ -304,6 +304,131 @@ __device__ __forceinline__ void synth_body(const SynthArgs<T> &a, const Live<T> 
 constexpr int UQ = SP / 2 + 6;   // level-U output pairs per axis (14): outputs [p0 - 6, p0 + 22)
 constexpr int UR = UQ + 10;      // level-U band positions per axis (24)
 constexpr int UO = 2 * UQ;       // level-U outputs per axis (28)
+constexpr int VQ = UR / 2;       // level-V output pairs per axis (12): level-U band positions [P0 - 5, P0 + 19)
+constexpr int VR = VQ + 10;      // level-V band positions per axis (22)
+
+// One synthesis level over a region in LDS: the bands src[b] (b = LL, HL, LH,
+// HH; NQ + 10 positions per axis, from 5 before the first output pair) give
+// 2 NQ outputs per axis, along x2 into mid, then along x1; output (r, c) goes
+// to dst[r - OFF][c - OFF] when both lie in [0, ND).  Same formula and order
+// as synth_body.
+template <typename T, int NQ, int ND, int OFF>
+__device__ __forceinline__ void syn_region(const Filt<T> &f, T (*src)[NQ + 10][NQ + 11], T (*mid)[2 * NQ][NQ + 11],
+                                           T (*dst)[ND + 1])
+{
+    constexpr int NR = NQ + 10;
+    const int tid = threadIdx.x;
+    // along x2: task = (band pair, column c, output pair q)
+    for (int t = tid; t < 2 * NR * NQ; t += NT) {
+        const int band = t / (NR * NQ), rem = t - band * (NR * NQ), q = rem / NR, c = rem - q * NR;
+        T lo[6], hi[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            lo[j] = src[band][q + j][c];
+            hi[j] = src[band + 2][q + 5 + j][c];
+        }
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
+                acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
+            }
+            mid[band][2 * q + par][c] = acc;
+        }
+    }
+    __syncthreads();
+    // along x1
+    for (int t = tid; t < 2 * NQ * NQ; t += NT) {
+        const int r = t / NQ, q = t - r * NQ;
+        T lo[6], hi[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            lo[j] = mid[0][r][q + j];
+            hi[j] = mid[1][r][q + 5 + j];
+        }
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                acc = fma(f.h[par + 10 - 2 * j], lo[j], acc);
+                acc = fma(f.g[par - 2 * j + 10], hi[j], acc);
+            }
+            const int rr = r - OFF, cc = 2 * q + par - OFF;
+            if (rr >= 0 && rr < ND && cc >= 0 && cc < ND) dst[rr][cc] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// Level D of a fused synthesis: the passes of synth_body over sB (its bands
+// at p0 - 5 .. p0 + 20), output tile at fine position 2 p0.
+template <typename T>
+__device__ __forceinline__ void syn_level_d(const SynthArgs<T> &d, T (*sB)[SR][SR + 1], T (*sLH)[SF][SR + 1], int64_t ch,
+                                            int p01, int p02)
+{
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 2 * SR * (SP / 4); t += NT) {
+        int band = t / (SR * (SP / 4)), rem = t - band * SR * (SP / 4);
+        int blk = rem / SR, c = rem - blk * SR;
+        const int bl = band, bh = band + 2;
+        T lo[9], hi[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            lo[j] = sB[bl][4 * blk + j][c];
+            hi[j] = sB[bh][4 * blk + 5 + j][c];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    acc = fma(d.f.h[par + 10 - 2 * j], lo[q + j], acc);
+                    acc = fma(d.f.g[par - 2 * j + 10], hi[q + j], acc);
+                }
+                sLH[band][8 * blk + 2 * q + par][c] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    T *out = d.out + ch * d.out_plane;
+    const int M1 = 2 * d.M1c, M2 = 2 * d.M2c;
+    for (int t = tid; t < SF * (SP / 2); t += NT) {
+        int f = t / (SP / 2), blk = t - f * (SP / 2);
+        T lo[7], hi[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            lo[j] = sLH[0][f][2 * blk + j];
+            hi[j] = sLH[1][f][2 * blk + 5 + j];
+        }
+        const int o2 = 2 * p02 + f;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    acc = fma(d.f.h[par + 10 - 2 * j], lo[q + j], acc);
+                    acc = fma(d.f.g[par - 2 * j + 10], hi[q + j], acc);
+                }
+                const int o1 = 2 * p01 + 4 * blk + 2 * q + par;
+                if (o2 < M2 && o1 < M1) out[(int64_t)o2 * d.out_pitch + o1] = acc;
+            }
+        }
+    }
+}
+
+// Index of a state-plane band value: band b (0 LL, 1 HL, 2 LH, 3 HH) of a
+// level with M1 x M2 bands, at wrapped band position (q2, q1).
+__device__ __forceinline__ int64_t band_at(int b, int q2, int q1, int M1, int M2, int pitch)
+{
+    return (int64_t)(q2 + (b >= 2 ? M2 : 0)) * pitch + q1 + ((b & 1) ? M1 : 0);
+}
 
 template <typename T>
 __device__ __forceinline__ void synth2_body(const SynthArgs<T> &d, const SynthArgs<T> &u, const Live<T> &lv, int bx,
@@ -336,13 +461,12 @@ __device__ __forceinline__ void synth2_body(const SynthArgs<T> &d, const SynthAr
             const int b = e / (UR * UR), rem = e - b * (UR * UR), r = rem / UR, c = rem - r * UR;
             const int q2 = wrap(P02 - 5 + r, M2u), q1 = wrap(P01 - 5 + c, M1u);
             from_apx = b == 0 && apx;
-            idx = from_apx ? (int64_t)q2 * M1u + q1
-                           : (int64_t)(q2 + (b >= 2 ? M2u : 0)) * d.pitch + q1 + ((b & 1) ? M1u : 0);
+            idx = from_apx ? (int64_t)q2 * M1u + q1 : band_at(b, q2, q1, M1u, M2u, d.pitch);
         } else {
             const int e2 = e - NU, b = 1 + e2 / (SR * SR), rem = e2 - (b - 1) * (SR * SR), r = rem / SR,
                       c = rem - r * SR;
             const int q2 = wrap(p02 - 5 + r, M2d), q1 = wrap(p01 - 5 + c, M1d);
-            idx = (int64_t)(q2 + (b >= 2 ? M2d : 0)) * d.pitch + q1 + ((b & 1) ? M1d : 0);
+            idx = band_at(b, q2, q1, M1d, M2d, d.pitch);
         }
         va[k] = (from_apx ? apx : zc)[idx];
         vb[k] = (from_apx ? apx : zp)[idx];
@@ -362,103 +486,88 @@ __device__ __forceinline__ void synth2_body(const SynthArgs<T> &d, const SynthAr
         }
     }
     __syncthreads();
+    // level U into the approximation band of level D (output n <-> sB row / column n - (p0 - 5))
+    syn_region<T, UQ, SR, 1>(d.f, sU, sUL, sB[0]);  // (u's filter bank is d's)
+    syn_level_d<T>(d, sB, sLH, ch, p01, p02);
+}
 
-    // level U along x2: task = (band pair, column c, output pair q)
-    for (int t = tid; t < 2 * UR * UQ; t += NT) {
-        const int band = t / (UR * UQ), rem = t - band * (UR * UQ), q = rem / UR, c = rem - q * UR;
-        T lo[6], hi[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            lo[j] = sU[band][q + j][c];
-            hi[j] = sU[band + 2][q + 5 + j][c];
-        }
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            T acc = T(0);
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                acc = fma(u.f.h[par + 10 - 2 * j], lo[j], acc);
-                acc = fma(u.f.g[par - 2 * j + 10], hi[j], acc);
-            }
-            sUL[band][2 * q + par][c] = acc;
-        }
-    }
-    __syncthreads();
-    // level U along x1, into the approximation band of level D (output n <-> sB row / column n - (p0 - 5))
-    for (int t = tid; t < UO * UQ; t += NT) {
-        const int f = t / UQ, q = t - f * UQ;
-        T lo[6], hi[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            lo[j] = sUL[0][f][q + j];
-            hi[j] = sUL[1][f][q + 5 + j];
-        }
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            T acc = T(0);
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                acc = fma(u.f.h[par + 10 - 2 * j], lo[j], acc);
-                acc = fma(u.f.g[par - 2 * j + 10], hi[j], acc);
-            }
-            const int r = f - 1, c = 2 * q + par - 1;
-            if (r >= 0 && r < SR && c >= 0 && c < SR) sB[0][r][c] = acc;
-        }
-    }
-    __syncthreads();
+// ===========================================================================
+// Three synthesis levels in one launch: V = D + 2, U = D + 1 and D.  As
+// synth2_body, with the 24 x 24 part of level U's approximation band that the
+// U stage reads computed from a 22 x 22 region of level V's bands in LDS
+// (level V's outputs [P0 - 5, P0 + 19) per axis, exactly that region).  Same
+// sums in the same order as the single-level launches: the same bits.
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ void synth3_body(const SynthArgs<T> &d, const SynthArgs<T> &u, const SynthArgs<T> &v,
+                                            const Live<T> &lv, int bx, int by, int bz)
+{
+    __shared__ T sV[4][VR][VR + 1];   // level V: LL, HL, LH, HH
+    __shared__ T sVL[2][UR][VR + 1];  // level V after x2
+    __shared__ T sU[4][UR][UR + 1];   // level U: LL (= level V's output), HL, LH, HH
+    __shared__ T sUL[2][UO][UR + 1];
+    __shared__ T sB[4][SR][SR + 1];   // level D: LL (= level U's output), HL, LH, HH
+    __shared__ T sLH[2][SF][SR + 1];
+    const int64_t ch = bz;
+    const int p01 = bx * SP, p02 = by * SP;          // level-D coarse tile origin
+    const int P01 = p01 / 2 - 3, P02 = p02 / 2 - 3;  // level-U output pair origin
+    const int R01 = (P01 - 5) / 2 - 5, R02 = (P02 - 5) / 2 - 5;  // level-V band region origin (P0 - 5 is even)
+    const T *zc = lv.zc + ch * d.plane;
+    const T *zp = lv.zp + ch * d.plane;
+    const T *apx = v.apx ? v.apx + ch * v.apx_plane : nullptr;
+    const int tid = threadIdx.x;
+    const int M1v = v.M1c, M2v = v.M2c, M1u = u.M1c, M2u = u.M2c, M1d = d.M1c, M2d = d.M2c;
 
-    // level D: the passes of synth_body
-    for (int t = tid; t < 2 * SR * (SP / 4); t += NT) {
-        int band = t / (SR * (SP / 4)), rem = t - band * SR * (SP / 4);
-        int blk = rem / SR, c = rem - blk * SR;
-        const int bl = band, bh = band + 2;
-        T lo[9], hi[9];
+    // every load up front: level V's four bands (22 x 22), level U's and level D's detail bands
+    constexpr int NV = 4 * VR * VR, NU = 3 * UR * UR, ND = 3 * SR * SR, NA = NV + NU + ND;
+    constexpr int NL = (NA + NT - 1) / NT;
+    T va[NL], vb[NL];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            lo[j] = sB[bl][4 * blk + j][c];
-            hi[j] = sB[bh][4 * blk + 5 + j][c];
+    for (int k = 0; k < NL; ++k) {
+        int e = tid + k * NT;
+        e = e < NA ? e : 0;  // past the end: an in-range duplicate, unused
+        int64_t idx;
+        bool from_apx = false;
+        if (e < NV) {
+            const int b = e / (VR * VR), rem = e - b * (VR * VR), r = rem / VR, c = rem - r * VR;
+            const int q2 = wrap(R02 + r, M2v), q1 = wrap(R01 + c, M1v);
+            from_apx = b == 0 && apx;
+            idx = from_apx ? (int64_t)q2 * M1v + q1 : band_at(b, q2, q1, M1v, M2v, d.pitch);
+        } else if (e < NV + NU) {
+            const int e2 = e - NV, b = 1 + e2 / (UR * UR), rem = e2 - (b - 1) * (UR * UR), r = rem / UR,
+                      c = rem - r * UR;
+            idx = band_at(b, wrap(P02 - 5 + r, M2u), wrap(P01 - 5 + c, M1u), M1u, M2u, d.pitch);
+        } else {
+            const int e2 = e - NV - NU, b = 1 + e2 / (SR * SR), rem = e2 - (b - 1) * (SR * SR), r = rem / SR,
+                      c = rem - r * SR;
+            idx = band_at(b, wrap(p02 - 5 + r, M2d), wrap(p01 - 5 + c, M1d), M1d, M2d, d.pitch);
         }
+        va[k] = (from_apx ? apx : zc)[idx];
+        vb[k] = (from_apx ? apx : zp)[idx];
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int par = 0; par < 2; ++par) {
-                T acc = T(0);
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    acc = fma(d.f.h[par + 10 - 2 * j], lo[q + j], acc);
-                    acc = fma(d.f.g[par - 2 * j + 10], hi[q + j], acc);
-                }
-                sLH[band][8 * blk + 2 * q + par][c] = acc;
-            }
+    for (int k = 0; k < NL; ++k) {
+        const int e = tid + k * NT;
+        if (e >= NA) continue;
+        const T y = momentum(va[k], vb[k], lv.beta);
+        if (e < NV) {
+            const int b = e / (VR * VR), rem = e - b * (VR * VR), r = rem / VR, c = rem - r * VR;
+            sV[b][r][c] = y;
+        } else if (e < NV + NU) {
+            const int e2 = e - NV, b = 1 + e2 / (UR * UR), rem = e2 - (b - 1) * (UR * UR), r = rem / UR,
+                      c = rem - r * UR;
+            sU[b][r][c] = y;
+        } else {
+            const int e2 = e - NV - NU, b = 1 + e2 / (SR * SR), rem = e2 - (b - 1) * (SR * SR), r = rem / SR,
+                      c = rem - r * SR;
+            sB[b][r][c] = y;
         }
     }
     __syncthreads();
-    T *out = d.out + ch * d.out_plane;
-    const int M1 = 2 * M1d, M2 = 2 * M2d;
-    for (int t = tid; t < SF * (SP / 2); t += NT) {
-        int f = t / (SP / 2), blk = t - f * (SP / 2);
-        T lo[7], hi[7];
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            lo[j] = sLH[0][f][2 * blk + j];
-            hi[j] = sLH[1][f][2 * blk + 5 + j];
-        }
-        const int o2 = 2 * p02 + f;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-#pragma unroll
-            for (int par = 0; par < 2; ++par) {
-                T acc = T(0);
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    acc = fma(d.f.h[par + 10 - 2 * j], lo[q + j], acc);
-                    acc = fma(d.f.g[par - 2 * j + 10], hi[q + j], acc);
-                }
-                const int o1 = 2 * p01 + 4 * blk + 2 * q + par;
-                if (o2 < M2 && o1 < M1) out[(int64_t)o2 * d.out_pitch + o1] = acc;
-            }
-        }
-    }
+    // (every level's arguments carry the same filter bank: d's is used throughout)
+    syn_region<T, VQ, UR, 0>(d.f, sV, sVL, sU[0]);  // level V into level U's approximation band
+    syn_region<T, UQ, SR, 1>(d.f, sU, sUL, sB[0]);  // level U into level D's approximation band
+    syn_level_d<T>(d, sB, sLH, ch, p01, p02);
 }
 
 // ===========================================================================
@@ -1653,6 +1762,16 @@ __global__ __launch_bounds__(NT) void k_synth2(SynthArgs<T> d, SynthArgs<T> u)
 }
 
 template <typename T>
+__global__ __launch_bounds__(NT) void k_synth3(SynthArgs<T> d, SynthArgs<T> u, SynthArgs<T> v)
+{
+    const T beta = d.di.it_dev ? beta_at<T>(*d.di.it_dev + d.di.it_off) : d.beta;
+    const Live<T> lv{d.zc, d.zp, nullptr, beta, T(0), nullptr};
+    const int t = xcd_tile(d.tx * d.ty);  // channel = blockIdx.y
+    if (t < 0) return;
+    synth3_body<T>(d, u, v, lv, t % d.tx, t / d.tx, blockIdx.y);
+}
+
+template <typename T>
 __device__ __forceinline__ Live<T> live_of(const ProxArgs<T> &p, T beta_next)
 {
     if (p.di.it_dev) {
@@ -2307,6 +2426,15 @@ hipError_t launch_synth2(const SynthArgs<T> &d, const SynthArgs<T> &u, int C, hi
 }
 
 template <typename T>
+hipError_t launch_synth3(const SynthArgs<T> &d, const SynthArgs<T> &u, const SynthArgs<T> &v, int C, hipStream_t s)
+{
+    SynthArgs<T> b = d;
+    tiles_synth(d.M1c, d.M2c, &b.tx, &b.ty);
+    hipLaunchKernelGGL(k_synth3<T>, dim3(xcd_grid(b.tx * b.ty), C), dim3(NT), 0, s, b, u, v);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s)
 {
     SynthArgs<T> b = a;
@@ -2589,6 +2717,8 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
     template hipError_t launch_synth<T>(const SynthArgs<T> &, int, hipStream_t);           \
     template hipError_t launch_analysis<T>(const AnalysisArgs<T> &, hipStream_t);          \
     template hipError_t launch_synth2<T>(const SynthArgs<T> &, const SynthArgs<T> &, int, hipStream_t); \
+    template hipError_t launch_synth3<T>(const SynthArgs<T> &, const SynthArgs<T> &, const SynthArgs<T> &, int,  \
+                                         hipStream_t);                                                         \
     template hipError_t launch_coarse<T>(const CoarseArgs<T> &, int, hipStream_t);         \
     template hipError_t launch_jprox<T>(const JProxArgs<T> &, int, hipStream_t); \
     template size_t coarse_lds_bytes<T>(int, int, int);                                    \

@@ -13,9 +13,12 @@
 // share a row; lane j reads entries j, j+G, ... of it, UR per trip, and each
 // group keeps NRG rows in flight together (their loads interleaved, all
 // issued before the first use), so a wave has enough bytes outstanding to
-// cover the HBM latency; the G partial sums meet in an xor tree.  Workgroups
-// take consecutive row ranges in XCD-aware order, so each XCD's L2 sees a
-// contiguous band of rows and the nearby columns they gather.
+// cover the three dependent latencies of a row (its bounds, its entries, the
+// gathered values); the G partial sums meet in an xor tree.  A workgroup owns
+// NRG x 256/G consecutive rows and writes their results through LDS as
+// contiguous runs (whole cache lines, not one value per row group).
+// Workgroups take consecutive row ranges in XCD-aware order, so each XCD's
+// L2 sees a contiguous band of rows and the nearby columns they gather.
 #include <hip/hip_runtime.h>
 
 #include "pd_wkernels.h"
@@ -73,7 +76,7 @@ __device__ __forceinline__ void row_bounds(const Csr<T> &A, int r, int64_t &b0, 
 __device__ __forceinline__ int clamp_col(int c, int n) { return (unsigned)c < (unsigned)n ? c : (c < 0 ? 0 : n - 1); }
 
 constexpr int UR = 4;    // entries per lane per trip
-constexpr int NRG = 2;   // rows per lane group in flight together
+constexpr int NRG = 2;   // rows per lane group in flight together (4: fewer waves fit, slower)
 
 // Partial sums of lane lg (0..G-1) over NRG rows [b0[j], b1[j]):
 // sum val[k] x[col[k]]; the rows' loads are interleaved so that all of a
@@ -147,11 +150,13 @@ __device__ __forceinline__ T soft_w(T v, T t)
     return a > T(0) ? copysign(a, v) : T(0);
 }
 
-// Rows of lane group gi of workgroup blk: (blk * NRG + j) * RPB + gi, j < NRG.
+// Rows of lane group gi of workgroup blk: (blk * NRG + j) * RPB + gi, j < NRG
+// (NRG RPB consecutive rows per workgroup).
 template <typename T, int G>
 __global__ __launch_bounds__(NTW) void k_wres(WResArgs<T> a)
 {
     constexpr int RPB = NTW / G;
+    __shared__ T su[NRG * RPB];
     const int nb = (a.a.n + RPB * NRG - 1) / (RPB * NRG);
     const int blk = xcd_block(nb);
     double st[1] = {0.0};
@@ -174,11 +179,13 @@ __global__ __launch_bounds__(NTW) void k_wres(WResArgs<T> a)
 #pragma unroll
         for (int j = 0; j < NRG; ++j) {
             const T u = group_sum<T, G>(acc[j]) - bv[j];
-            if (rok[j] && lg == 0) {
-                a.u[r[j]] = u;
-                st[0] += 0.5 * (double)u * (double)u;
-            }
+            if (lg == 0) su[j * RPB + gi] = u;
+            if (rok[j] && lg == 0) st[0] += 0.5 * (double)u * (double)u;
         }
+        __syncthreads();
+        const int row0 = blk * NRG * RPB;
+        for (int t = threadIdx.x; t < NRG * RPB; t += NTW)
+            if (row0 + t < a.a.n) a.u[row0 + t] = su[t];
     }
     if (a.slots) wblock_add<1>(st, a.slots);
 }
@@ -188,6 +195,7 @@ __global__ __launch_bounds__(NTW) void k_wprox(WProxArgs<T> a)
 {
     constexpr int RPB = NTW / G;
     __shared__ T sw[PD_MAXL + 1];
+    __shared__ T sz[NRG * RPB], sy[NRG * RPB];
     const int nb = (a.at.n + RPB * NRG - 1) / (RPB * NRG);
     const int blk = xcd_block(nb);
     if (!a.wmap && threadIdx.x <= a.levels) sw[threadIdx.x] = a.wlev[threadIdx.x];
@@ -224,14 +232,23 @@ __global__ __launch_bounds__(NTW) void k_wprox(WProxArgs<T> a)
             const T ts = a.tau * sg[j];
             const T v = y[j] - ts * g;
             const T z = soft_w(v, ts * w);
+            if (lg == 0) {
+                sz[j * RPB + gi] = z;
+                sy[j * RPB + gi] = fma(a.beta_next, z - zc[j], z);  // y(i+1), one explicit fma
+            }
             if (rok[j] && lg == 0) {
                 bad |= !isfinite(v);
                 st[0] += (double)w * fabs((double)y[j]);
                 st[1] += ((double)z - (double)y[j]) * ((double)z - (double)y[j]);
-                a.zn[r[j]] = z;
-                a.y[r[j]] = fma(a.beta_next, z - zc[j], z);  // y(i+1), one explicit fma
             }
         }
+        __syncthreads();  // sz, sy
+        const int row0 = blk * NRG * RPB;
+        for (int t = threadIdx.x; t < NRG * RPB; t += NTW)
+            if (row0 + t < a.at.n) {
+                a.zn[row0 + t] = sz[t];
+                a.y[row0 + t] = sy[t];
+            }
     } else {
         __syncthreads();
     }
