@@ -312,14 +312,14 @@ constexpr int VR = VQ + 10;      // level-V band positions per axis (22)
 // 2 NQ outputs per axis, along x2 into mid, then along x1; output (r, c) goes
 // to dst[r - OFF][c - OFF] when both lie in [0, ND).  Same formula and order
 // as synth_body.
-template <typename T, int NQ, int ND, int OFF>
+template <typename T, int NQ, int ND, int OFF, int NTS = NT>
 __device__ __forceinline__ void syn_region(const Filt<T> &f, T (*src)[NQ + 10][NQ + 11], T (*mid)[2 * NQ][NQ + 11],
                                            T (*dst)[ND + 1])
 {
     constexpr int NR = NQ + 10;
     const int tid = threadIdx.x;
     // along x2: task = (band pair, column c, output pair q)
-    for (int t = tid; t < 2 * NR * NQ; t += NT) {
+    for (int t = tid; t < 2 * NR * NQ; t += NTS) {
         const int band = t / (NR * NQ), rem = t - band * (NR * NQ), q = rem / NR, c = rem - q * NR;
         T lo[6], hi[6];
 #pragma unroll
@@ -340,7 +340,7 @@ __device__ __forceinline__ void syn_region(const Filt<T> &f, T (*src)[NQ + 10][N
     }
     __syncthreads();
     // along x1
-    for (int t = tid; t < 2 * NQ * NQ; t += NT) {
+    for (int t = tid; t < 2 * NQ * NQ; t += NTS) {
         const int r = t / NQ, q = t - r * NQ;
         T lo[6], hi[6];
 #pragma unroll
@@ -365,12 +365,12 @@ __device__ __forceinline__ void syn_region(const Filt<T> &f, T (*src)[NQ + 10][N
 
 // Level D of a fused synthesis: the passes of synth_body over sB (its bands
 // at p0 - 5 .. p0 + 20), output tile at fine position 2 p0.
-template <typename T>
+template <typename T, int NTS = NT>
 __device__ __forceinline__ void syn_level_d(const SynthArgs<T> &d, T (*sB)[SR][SR + 1], T (*sLH)[SF][SR + 1], int64_t ch,
                                             int p01, int p02)
 {
     const int tid = threadIdx.x;
-    for (int t = tid; t < 2 * SR * (SP / 4); t += NT) {
+    for (int t = tid; t < 2 * SR * (SP / 4); t += NTS) {
         int band = t / (SR * (SP / 4)), rem = t - band * SR * (SP / 4);
         int blk = rem / SR, c = rem - blk * SR;
         const int bl = band, bh = band + 2;
@@ -397,7 +397,7 @@ __device__ __forceinline__ void syn_level_d(const SynthArgs<T> &d, T (*sB)[SR][S
     __syncthreads();
     T *out = d.out + ch * d.out_plane;
     const int M1 = 2 * d.M1c, M2 = 2 * d.M2c;
-    for (int t = tid; t < SF * (SP / 2); t += NT) {
+    for (int t = tid; t < SF * (SP / 2); t += NTS) {
         int f = t / (SP / 2), blk = t - f * (SP / 2);
         T lo[7], hi[7];
 #pragma unroll
@@ -498,7 +498,7 @@ __device__ __forceinline__ void synth2_body(const SynthArgs<T> &d, const SynthAr
 // (level V's outputs [P0 - 5, P0 + 19) per axis, exactly that region).  Same
 // sums in the same order as the single-level launches: the same bits.
 // ===========================================================================
-template <typename T>
+template <typename T, int NTS = NT>
 __device__ __forceinline__ void synth3_body(const SynthArgs<T> &d, const SynthArgs<T> &u, const SynthArgs<T> &v,
                                             const Live<T> &lv, int bx, int by, int bz)
 {
@@ -520,11 +520,11 @@ __device__ __forceinline__ void synth3_body(const SynthArgs<T> &d, const SynthAr
 
     // every load up front: level V's four bands (22 x 22), level U's and level D's detail bands
     constexpr int NV = 4 * VR * VR, NU = 3 * UR * UR, ND = 3 * SR * SR, NA = NV + NU + ND;
-    constexpr int NL = (NA + NT - 1) / NT;
+    constexpr int NL = (NA + NTS - 1) / NTS;
     T va[NL], vb[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        int e = tid + k * NT;
+        int e = tid + k * NTS;
         e = e < NA ? e : 0;  // past the end: an in-range duplicate, unused
         int64_t idx;
         bool from_apx = false;
@@ -547,7 +547,7 @@ __device__ __forceinline__ void synth3_body(const SynthArgs<T> &d, const SynthAr
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        const int e = tid + k * NT;
+        const int e = tid + k * NTS;
         if (e >= NA) continue;
         const T y = momentum(va[k], vb[k], lv.beta);
         if (e < NV) {
@@ -565,9 +565,9 @@ __device__ __forceinline__ void synth3_body(const SynthArgs<T> &d, const SynthAr
     }
     __syncthreads();
     // (every level's arguments carry the same filter bank: d's is used throughout)
-    syn_region<T, VQ, UR, 0>(d.f, sV, sVL, sU[0]);  // level V into level U's approximation band
-    syn_region<T, UQ, SR, 1>(d.f, sU, sUL, sB[0]);  // level U into level D's approximation band
-    syn_level_d<T>(d, sB, sLH, ch, p01, p02);
+    syn_region<T, VQ, UR, 0, NTS>(d.f, sV, sVL, sU[0]);  // level V into level U's approximation band
+    syn_region<T, UQ, SR, 1, NTS>(d.f, sU, sUL, sB[0]);  // level U into level D's approximation band
+    syn_level_d<T, NTS>(d, sB, sLH, ch, p01, p02);
 }
 
 // ===========================================================================
@@ -1761,14 +1761,17 @@ __global__ __launch_bounds__(NT) void k_synth2(SynthArgs<T> d, SynthArgs<T> u)
     synth2_body<T>(d, u, lv, t % d.tx, t / d.tx, blockIdx.y);
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_synth3(SynthArgs<T> d, SynthArgs<T> u, SynthArgs<T> v)
+// NTS threads per tile: 1024 when the grid has fewer workgroups than CUs
+// can hold two of (the three LDS stages then have four waves per SIMD to
+// hide their latency instead of one); the same outputs either way.
+template <typename T, int NTS>
+__global__ __launch_bounds__(NTS) void k_synth3(SynthArgs<T> d, SynthArgs<T> u, SynthArgs<T> v)
 {
     const T beta = d.di.it_dev ? beta_at<T>(*d.di.it_dev + d.di.it_off) : d.beta;
     const Live<T> lv{d.zc, d.zp, nullptr, beta, T(0), nullptr};
     const int t = xcd_tile(d.tx * d.ty);  // channel = blockIdx.y
     if (t < 0) return;
-    synth3_body<T>(d, u, v, lv, t % d.tx, t / d.tx, blockIdx.y);
+    synth3_body<T, NTS>(d, u, v, lv, t % d.tx, t / d.tx, blockIdx.y);
 }
 
 template <typename T>
@@ -2425,12 +2428,17 @@ hipError_t launch_synth2(const SynthArgs<T> &d, const SynthArgs<T> &u, int C, hi
     return hipGetLastError();
 }
 
+constexpr int SYNTH3_WIDE_BELOW = 512;  // workgroups: two per CU
+
 template <typename T>
 hipError_t launch_synth3(const SynthArgs<T> &d, const SynthArgs<T> &u, const SynthArgs<T> &v, int C, hipStream_t s)
 {
     SynthArgs<T> b = d;
     tiles_synth(d.M1c, d.M2c, &b.tx, &b.ty);
-    hipLaunchKernelGGL(k_synth3<T>, dim3(xcd_grid(b.tx * b.ty), C), dim3(NT), 0, s, b, u, v);
+    if (b.tx * b.ty * C < SYNTH3_WIDE_BELOW)
+        hipLaunchKernelGGL((k_synth3<T, 4 * NT>), dim3(xcd_grid(b.tx * b.ty), C), dim3(4 * NT), 0, s, b, u, v);
+    else
+        hipLaunchKernelGGL((k_synth3<T, NT>), dim3(xcd_grid(b.tx * b.ty), C), dim3(NT), 0, s, b, u, v);
     return hipGetLastError();
 }
 
