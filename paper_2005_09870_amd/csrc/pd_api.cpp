@@ -808,14 +808,25 @@ struct BImg {
     int64_t off;          // element offset in the packed image arrays
     size_t apx[PD_MAXL + 1];
     size_t slots;
+    bool split;           // the blur as the two marching kernels (row blur, wide enough)
+    size_t btab;          // their per-row profile tables
 };
 
 struct BLayout {
     std::vector<BImg> img;
     int64_t total;        // packed elements
-    size_t zA, zB, x, s, flag, it, tab, tab_bytes, total_bytes;
+    size_t zA, zB, x, s, r, flag, it, tab, tab_bytes, total_bytes;
     int maxfine;
 };
+
+// Images at least this wide run the batched blur as the two marching kernels
+// (strips of 128 columns, blocks of BATCH_SPLIT_ROWS rows per wave); narrower
+// ones as the 32-row tile kernel.  The same sums either way.  Measured on the
+// 64-image batch (sides 96..1024): the batch's blur takes 283 us per iteration
+// with the tile kernel alone, 167 us with the marching pair from 256 columns
+// and 39-row blocks, 147 us from 128 columns and 58-row blocks.
+constexpr int BATCH_SPLIT_MIN_N1 = 128;
+constexpr int BATCH_SPLIT_ROWS = 58;
 
 template <typename Args>
 struct Table {
@@ -833,9 +844,9 @@ struct Table {
 
 size_t table_bytes_upper(int batch, int maxl)
 {
-    // per image at most: 2 coarse SYN + 2 coarse PROX + init coarse; per level
-    // synth (iteration and final) + analysis (plain, prox) + blur, all < 1 KiB
-    return align_up((size_t)batch * (8 + 4 * (size_t)maxl) * 1024 + 64 * 1024);
+    // per image at most: 2 coarse SYN + 2 coarse PROX + init coarse + 3 blur;
+    // per level synth (iteration and final) + analysis (plain, prox), all < 1 KiB
+    return align_up((size_t)batch * (10 + 4 * (size_t)maxl) * 1024 + 64 * 1024);
 }
 
 template <typename T>
@@ -850,6 +861,8 @@ BLayout batched_layout(int batch, const pd_image_desc *d)
         im.sh = d[b].shape;
         im.lc = coarse_level<T>(&im.sh, d[b].w.joint);
         im.off = L.total;
+        im.split = d[b].op.kind == PD_OP_ROWBLUR && im.sh.n1 >= BATCH_SPLIT_MIN_N1;
+        im.btab = 0;
         L.total += (int64_t)im.sh.n1 * im.sh.n2 * im.sh.channels;
         L.maxfine = std::max(L.maxfine, im.lc - 1);
         maxl = std::max(maxl, (int)im.sh.levels);
@@ -865,6 +878,8 @@ BLayout batched_layout(int batch, const pd_image_desc *d)
     off += plane;
     L.s = off;
     off += plane;
+    L.r = off;  // r = H x - f0 of the marching blur
+    off += plane;
     for (auto &im : L.img) {
         for (int j = 0; j <= PD_MAXL; ++j) im.apx[j] = 0;
         for (int j = 1; j < im.sh.levels; ++j) {
@@ -873,6 +888,10 @@ BLayout batched_layout(int batch, const pd_image_desc *d)
         }
         im.slots = off;
         off = align_up(off + (size_t)PD_RING * 3 * PD_NSLOT * sizeof(double));
+        if (im.split) {
+            im.btab = off;
+            off = align_up(off + 2 * (size_t)im.sh.n2 * BLUR_TAB_PITCH * es);
+        }
     }
     L.flag = off;
     off = align_up(off + 256);
@@ -931,6 +950,7 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     char *ws = (char *)workspace;
     const Filt<T> f = make_filt<T>(wav);
     T *zA = (T *)(ws + L.zA), *zB = (T *)(ws + L.zB), *X = (T *)(ws + L.x), *S = (T *)(ws + L.s);
+    T *Rp = (T *)(ws + L.r);
     int *flag = (int *)(ws + L.flag);
     int *it_dev = (int *)(ws + L.it);
     // joint prox: every image has the same channel count (checked by the caller)
@@ -942,7 +962,7 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     std::vector<Table<AnalysisArgs<T>>> t_init_ana(MF + 1), t_ana(MF + 1);
     std::vector<Table<SynthArgs<T>>> t_syn(MF + 1), t_fsyn(MF + 1);
     Table<CoarseArgs<T>> t_init_co, t_cosyn, t_fcosyn, t_coprox_syn, t_coprox;
-    Table<BlurArgs<T>> t_blur;
+    Table<BlurArgs<T>> t_blur, t_blur_h, t_blur_ht;  // tile kernel; the marching pair (same args)
     std::vector<double *> slots_tab(batch), stats_tab(batch);
     const T *f_zfinal = (iters % 2 == 0) ? zA : zB;  // z(K) after K in-place iterations
     // host image of the table region: tail matrices first (deduplicated), then the tables
@@ -1035,8 +1055,17 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         ba.slots = slots;
         ba.racc = nullptr;
         ba.rscale = T(0);
-        tiles_blur(n1, n2, &ba.tx, &ba.ty, 32);  // the batched blur runs the 32-row tile
-        t_blur.add(ba, ba.tx * ba.ty * C);
+        ba.r = Rp + im.off;
+        ba.tabs = im.split ? (const T *)(ws + im.btab) : nullptr;
+        ba.rows = im.split ? BATCH_SPLIT_ROWS : 0;
+        if (im.split) {  // tx, ty = workgroups per channel of the r and H^T kernels
+            tiles_blur_split(n1, n2, BATCH_SPLIT_ROWS, &ba.tx, &ba.ty);
+            t_blur_h.add(ba, ba.tx * C);
+            t_blur_ht.add(ba, ba.ty * C);
+        } else {
+            tiles_blur(n1, n2, &ba.tx, &ba.ty, 32);
+            t_blur.add(ba, ba.tx * ba.ty * C);
+        }
         if (coarse) {
             CoarseArgs<T> ca;
             ca.f = f;
@@ -1109,6 +1138,8 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     place(t_coprox_syn);
     place(t_coprox);
     place(t_blur);
+    place(t_blur_h);
+    place(t_blur_ht);
     size_t o_sl = align_up(host.size());
     host.resize(o_sl + batch * sizeof(double *));
     std::memcpy(host.data() + o_sl, slots_tab.data(), batch * sizeof(double *));
@@ -1119,6 +1150,10 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
     char *tab = ws + L.tab;
     int rc;
     if ((rc = upload_async(tab, host.data(), host.size(), st)) != PD_OK) return rc;
+    for (int b = 0; b < batch; ++b)  // the marching blur's profile tables, before the first iteration
+        if (L.img[b].split)
+            PD_TRY_HIP(launch_blur_tables<T>((const T *)d[b].op.taps, L.img[b].sh.n2, d[b].op.radius,
+                                             (T *)(ws + L.img[b].btab), st));
 
     auto targs = [&](auto &t) {
         using A = typename std::decay_t<decltype(t.args)>::value_type;
@@ -1167,8 +1202,16 @@ int solve_batched_impl(int batch, const pd_image_desc *d, const pd_wavelet *wav,
         int r;
         if (it == 0 && (r = run_coarse(t_cosyn, dy, s)) != PD_OK) return r;
         if ((r = run_synth(t_syn, dy, s)) != PD_OK) return r;
+        // one timed entry for the batch's whole blur (tile kernel and marching pair)
         PD_TRY_HIP(timed(PD_K_BLUR, 0, s, [&] {
-            return launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), dy.ring, s);
+            if (t_blur.n() > 0) {
+                hipError_t e = launch_blur_b<T>(targs(t_blur), tstart(t_blur), t_blur.n(), t_blur.tiles(), dy.ring, s);
+                if (e != hipSuccess) return e;
+            }
+            if (t_blur_h.n() > 0)
+                return launch_blur_split_b<T>(targs(t_blur_h), tstart(t_blur_h), tstart(t_blur_ht), t_blur_h.n(),
+                                              t_blur_h.tiles(), t_blur_ht.tiles(), BATCH_SPLIT_ROWS, dy.ring, s);
+            return hipSuccess;
         }));
         if ((r = run_ana(t_ana, dy, s)) != PD_OK) return r;
         if ((r = run_coarse(it == iters - 1 ? t_coprox : t_coprox_syn, dy, s)) != PD_OK) return r;

@@ -190,6 +190,14 @@ hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, in
                            Dyn<T> d, hipStream_t s);
 template <typename T>
 hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s);
+// The two marching kernels over many images (row blur, tables in a.tabs, r in
+// a.r, a.rows = rows for every image): start_h / start_ht are the prefix sums
+// of each image's workgroups (channels x a.tx for the r kernel, channels x a.ty
+// for the H^T kernel, as tiles_blur_split gives them), wg_h / wg_ht their totals.
+template <typename T>
+hipError_t launch_blur_split_b(const BlurArgs<T> *tab, const int *start_h, const int *start_ht, int n, int wg_h,
+                               int wg_ht, int rows, int ring, hipStream_t s);
+void tiles_blur_split(int n1, int n2, int rows, int *th, int *tht);
 // stats[it0+j][q] += sum of ring entry (it0+j) % PD_RING, then zeroed, for
 // j < count; batched: one image per grid row, ring/stats bases from tables.
 hipError_t launch_stats_finalize_b(double *const *ring, double *const *stats, int n, int it0, int count,

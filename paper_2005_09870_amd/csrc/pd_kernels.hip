@@ -1975,9 +1975,8 @@ __global__ void k_blur_tables(const T *__restrict__ taps, int n2, int R, T *__re
 
 // (strip, row block) of this wave, strips of `width` columns and blocks of
 // `rows` rows; workgroups in XCD-aware order (tx workgroups of items).
-__device__ __forceinline__ bool march_item(int width, int n1, int n2, int rows, int tx, int &c0, int &p0, int &np)
+__device__ __forceinline__ bool march_item(int width, int n1, int n2, int rows, int t, int &c0, int &p0, int &np)
 {
-    const int t = xcd_tile(tx);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nblk = (n2 + rows - 1) / rows, items = ((n1 + width - 1) / width) * nblk;
     const int item = t * NWS + wv;
@@ -2095,17 +2094,15 @@ __device__ __forceinline__ void load_taps(const T *gtab, const T *ltab, int grow
 // peeled so that its conditions are static.  The next step's taps are
 // requested once this step's LDS data has arrived.
 template <typename T>
-__global__ __launch_bounds__(64 * NWS) void k_blur_h(BlurArgs<T> a)
+__device__ __forceinline__ void blur_h_body(const BlurArgs<T> &a, int tile, int64_t ch)
 {
-    if (xcd_tile(a.tx) < 0) return;  // padding workgroup (uniform)
     extern __shared__ __align__(16) unsigned char blur_lds[];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n1 = a.n1, n2 = a.n2;
     double st[1] = {0.0};
     int c0, p0, np;
-    if (march_item(SWS, n1, n2, a.rows, a.tx, c0, p0, np)) {
-        const int64_t ch = blockIdx.y;
+    if (march_item(SWS, n1, n2, a.rows, tile, c0, p0, np)) {
         const T *x = a.x + ch * a.plane;
         const T *f0 = a.f0 ? a.f0 + ch * a.plane : x;
         T *r = a.r + ch * a.plane;
@@ -2230,19 +2227,26 @@ __global__ __launch_bounds__(64 * NWS) void k_blur_h(BlurArgs<T> a)
     if (a.slots) block_slot_add<1, 64 * NWS>(st, a.slots);
 }
 
+// tile = the workgroup's index among the tx of a channel; ch its channel
+template <typename T>
+__global__ __launch_bounds__(64 * NWS) void k_blur_h(BlurArgs<T> a)
+{
+    const int t = xcd_tile(a.tx);
+    if (t < 0) return;  // padding workgroup (uniform)
+    blur_h_body<T>(a, t, blockIdx.y);
+}
+
 // The H^T kernel reads its taps from the wave's LDS copy (one profile per
 // step, needed at the start of the step).
 template <typename T>
-__global__ __launch_bounds__(64 * NWS) void k_blur_ht(BlurArgs<T> a)
+__device__ __forceinline__ void blur_ht_body(const BlurArgs<T> &a, int tile, int64_t ch)
 {
-    if (xcd_tile(a.tx) < 0) return;
     extern __shared__ __align__(16) unsigned char blur_lds[];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n1 = a.n1, n2 = a.n2;
     int c0, p0, np;
-    if (!march_item(SOT, n1, n2, a.rows, a.tx, c0, p0, np)) return;
-    const int64_t ch = blockIdx.y;
+    if (!march_item(SOT, n1, n2, a.rows, tile, c0, p0, np)) return;
     const T *rin = a.r + ch * a.plane;
     T *s = a.s + ch * a.plane;
     T *lrow = reinterpret_cast<T *>(blur_lds) + wv * blur_ht_lds(a.rows);
@@ -2308,6 +2312,14 @@ __global__ __launch_bounds__(64 * NWS) void k_blur_ht(BlurArgs<T> a)
     });
     for (int base = WIN; base < nsteps; base += WIN)
         static_for<WIN>([&](auto kc) { step(base + decltype(kc)::value, kc, std::true_type{}); });
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * NWS) void k_blur_ht(BlurArgs<T> a)
+{
+    const int t = xcd_tile(a.tx);
+    if (t < 0) return;
+    blur_ht_body<T>(a, t, blockIdx.y);
 }
 
 __device__ __forceinline__ int locate(const int *__restrict__ start, int n, int blk)
@@ -2416,6 +2428,34 @@ __global__ __launch_bounds__(NTB) void k_blur_b(const BlurArgs<T> *__restrict__ 
     const int bx = loc % a.tx;
     loc /= a.tx;
     blur_tile<T, 32>(a, bx, loc % a.ty, loc / a.ty);
+}
+
+// The two marching kernels over many images: workgroup g of the launch is
+// tile (g - start[img]) % tx of channel (g - start[img]) / tx of its image
+// (tx = the image's workgroups per channel, a different count for each kernel).
+template <typename T>
+__global__ __launch_bounds__(64 * NWS) void k_blur_h_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
+                                                       int n, int ring)
+{
+    const int g = xcd_tile(start[n]);
+    if (g < 0) return;
+    const int img = locate(start, n, g);
+    BlurArgs<T> a = tab[img];
+    if (a.slots) a.slots += (size_t)ring * 3 * PD_NSLOT;
+    const int loc = g - start[img];
+    blur_h_body<T>(a, loc % a.tx, loc / a.tx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * NWS) void k_blur_ht_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
+                                                        int n)
+{
+    const int g = xcd_tile(start[n]);
+    if (g < 0) return;
+    const int img = locate(start, n, g);
+    const BlurArgs<T> &a = tab[img];
+    const int loc = g - start[img];
+    blur_ht_body<T>(a, loc % a.ty, loc / a.ty);  // (ty holds the H^T kernel's workgroups per channel)
 }
 
 // ------------------------------------------------------------ launchers ---
@@ -2595,6 +2635,25 @@ hipError_t launch_coarse_b(const CoarseArgs<T> *tab, const int *start, int n, in
     return hipGetLastError();
 }
 
+// Workgroups per channel of the two marching kernels for an n1 x n2 plane, `rows` rows per wave.
+void tiles_blur_split(int n1, int n2, int rows, int *th, int *tht)
+{
+    const int nb = (n2 + rows - 1) / rows;
+    *th = ((n1 + SWS - 1) / SWS * nb + NWS - 1) / NWS;
+    *tht = ((n1 + SOT - 1) / SOT * nb + NWS - 1) / NWS;
+}
+
+template <typename T>
+hipError_t launch_blur_split_b(const BlurArgs<T> *tab, const int *start_h, const int *start_ht, int n, int wg_h,
+                               int wg_ht, int rows, int ring, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_blur_h_b<T>, dim3(xcd_grid(wg_h)), dim3(64 * NWS), NWS * blur_h_lds<T>(rows) * sizeof(T), s,
+                       tab, start_h, n, ring);
+    hipLaunchKernelGGL(k_blur_ht_b<T>, dim3(xcd_grid(wg_ht)), dim3(64 * NWS), NWS * blur_ht_lds(rows) * sizeof(T), s,
+                       tab, start_ht, n);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s)
 {
@@ -2738,7 +2797,9 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
                                              hipStream_t);                                                      \
     template hipError_t launch_coarse_b<T>(const CoarseArgs<T> *, const int *, int, int, size_t, int, Dyn<T>,  \
                                            hipStream_t);                                                        \
-    template hipError_t launch_blur_b<T>(const BlurArgs<T> *, const int *, int, int, int, hipStream_t);
+    template hipError_t launch_blur_b<T>(const BlurArgs<T> *, const int *, int, int, int, hipStream_t);        \
+    template hipError_t launch_blur_split_b<T>(const BlurArgs<T> *, const int *, const int *, int, int, int, int, \
+                                               int, hipStream_t);
 PD_INST(float)
 PD_INST(double)
 

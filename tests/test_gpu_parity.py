@@ -275,6 +275,23 @@ def test_zero_weights_is_plain_gradient_descent():
     assert np.abs(_np(out["f"]) - ref["f"]).max() < 1e-10
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batched_marching_blur_mix(dtype):
+    """Images at least 128 wide run the batched blur as the two marching
+    kernels (ragged strips and row blocks here), narrower ones as the tile
+    kernel, in one batch; each equals pd_solve on its own bit for bit, and so
+    does a three-channel image."""
+    for shapes, C in (([(256, 128), (96, 64), (320, 160), (288, 40)], 1), ([(256, 96), (64, 96)], 3)):
+        f0s, ops, lws, _, taus, levels, pbs = _batch_inputs(shapes, C=C, seed=90)
+        if dtype == torch.float64:
+            f0s = [_t(f0, dtype) for _, f0, _ in pbs]
+            ops = [_op(pb, dtype) for pb, _, _ in pbs]
+        outs, _ = P.pd_solve_batched(f0s, ops, lws, taus, _h(), levels, 50)
+        for b in range(len(shapes)):
+            single = P.pd_solve(f0s[b], ops[b], _h(), levels[b], taus[b], 50, level_w=lws[b])["f"]
+            assert torch.equal(outs[b], single), (shapes[b], C)
+
+
 def test_batched_edge_cases():
     """A batch of one image, and a batch mixing an image whose coarse block is
     the whole image (no fine level) with larger ones; equal to pd_solve."""
