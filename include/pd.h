@@ -516,8 +516,10 @@ typedef enum {
                            2 spreading of B_k columns over A~_k, 3 count, 4 fill */
     PD_K_SYNTH2 = 11,   /* two synthesis levels in one launch (level = the finer) */
     PD_K_JPROX = 12,    /* joint colour prox over the whole coefficient plane  */
-    PD_K_SYNTH3 = 13    /* three synthesis levels in one launch (level = the
+    PD_K_SYNTH3 = 13,   /* three synthesis levels in one launch (level = the
                            finest)                                             */
+    PD_K_ANALYSIS2 = 14 /* two analysis levels with the fused prox in one
+                           launch (level = the finer)                          */
 } pd_kernel_class;
 
 /* Start (enable != 0) or stop recording.  Starting clears the record. */
@@ -542,8 +544,9 @@ int pd_timing_read(int32_t max_rows, int32_t *kclass, int32_t *level, int64_t *l
 int pd_graphs_enable(int32_t enable);
 
 /* Fusion of the three (or, with two fine levels, two) coarsest fine synthesis
- * levels into one launch (default on; results are bitwise the same either
- * way).  Process-wide; not thread-safe. */
+ * levels into one launch, and of the two coarsest fine analysis levels of an
+ * iteration (one channel per tile set) into one launch (default on; results
+ * are bitwise the same either way).  Process-wide; not thread-safe. */
 int pd_fuse_enable(int32_t enable);
 
 /* Short description of a pd_status code. */

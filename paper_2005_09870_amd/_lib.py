@@ -70,10 +70,10 @@ EXPORTS = [
 
 PD_K_BLUR, PD_K_SYNTH, PD_K_ANALYSIS, PD_K_COARSE, PD_K_OTHER = 1, 2, 3, 4, 5
 PD_K_WRES, PD_K_WPROX = 6, 7
-PD_K_FFT, PD_K_ADMM, PD_K_DECOMP, PD_K_SYNTH2, PD_K_JPROX, PD_K_SYNTH3 = 8, 9, 10, 11, 12, 13
+PD_K_FFT, PD_K_ADMM, PD_K_DECOMP, PD_K_SYNTH2, PD_K_JPROX, PD_K_SYNTH3, PD_K_ANALYSIS2 = 8, 9, 10, 11, 12, 13, 14
 KCLASS_NAMES = {1: "blur", 2: "synthesis", 3: "analysis", 4: "coarse", 5: "other",
                 6: "wres", 7: "wprox", 8: "fft", 9: "admm", 10: "decomp", 11: "synthesis2",
-                12: "jprox", 13: "synthesis3"}
+                12: "jprox", 13: "synthesis3", 14: "analysis2"}
 
 _lib = None
 

@@ -378,7 +378,7 @@ template <typename T>
 int analysis_fine(const Ctx<T> &c, const T *in, int mode, const ProxArgs<T> &p)
 {
     const int L = c.sh->levels, n1 = c.sh->n1, n2 = c.sh->n2;
-    for (int lev = 1; lev <= c.lc - 1; ++lev) {
+    auto args = [&](int lev) {
         AnalysisArgs<T> a;
         a.f = c.f;
         a.in = lev == 1 ? in : c.apx(lev - 1);
@@ -392,7 +392,18 @@ int analysis_fine(const Ctx<T> &c, const T *in, int mode, const ProxArgs<T> &p)
         a.mode = mode;
         a.band_detail = L + 1 - lev;
         a.p = p;
+        return a;
+    };
+    // the two coarsest fine levels of an iteration in one launch
+    const bool fuse = g_synth2 && mode == MODE_PROX && !p.joint && c.lc - 1 >= 2;
+    const int single = fuse ? c.lc - 3 : c.lc - 1;
+    for (int lev = 1; lev <= single; ++lev) {
+        const AnalysisArgs<T> a = args(lev);
         PD_TRY_HIP(timed(PD_K_ANALYSIS, lev, c.st, [&] { return launch_analysis<T>(a, c.st); }));
+    }
+    if (fuse) {
+        const AnalysisArgs<T> a = args(c.lc - 2), e = args(c.lc - 1);
+        PD_TRY_HIP(timed(PD_K_ANALYSIS2, c.lc - 2, c.st, [&] { return launch_analysis2<T>(a, e, c.st); }));
     }
     return PD_OK;
 }

@@ -772,6 +772,227 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
 }
 
 // ===========================================================================
+// Two analysis levels in one launch (gradient step + prox mode, one channel
+// per tile set): levels D and E = D + 1.  A workgroup owns a 16 x 16 tile of
+// level D's bands and the 8 x 8 tile of level E's bands below it.  From one
+// 82 x 82 region of level D's input in LDS it computes (i) level D's detail
+// bands on the owned tile, exactly as analysis_body does, and (ii) level D's
+// approximation band on the 36 x 36 region that level E's tile reads (the
+// owned 16 x 16 and a 10-wide ring, which neighbouring workgroups own too),
+// then level E from that region.  Every value is the same sum in the same
+// order as in the single-level launches, so the outputs carry the same bits;
+// level D's approximation band never leaves LDS.
+// ===========================================================================
+constexpr int TE = TC / 2;          // level E tile
+constexpr int LR = 2 * TE + 20;     // level D approximation region (36)
+constexpr int BR = 2 * LR + 10;     // level D input region (82)
+constexpr int BRP = BR + 2;         // its LDS pitch
+
+template <typename T, int NTS>
+__device__ __forceinline__ void analysis2_body(const AnalysisArgs<T> &a, const AnalysisArgs<T> &e, const Live<T> &lv,
+                                               int bx, int by, int bz)
+{
+    static_assert(NTS >= NT && NTS % 64 == 0, "the epilogue uses the first NT threads");
+    __shared__ __attribute__((aligned(16))) T sIn[BR][BRP];
+    __shared__ __attribute__((aligned(16))) T sRow[2][AR][TC + 4];  // level D details, as analysis_body
+    __shared__ T sLo[BR][LR + 1];                                   // level D low-pass along x1
+    __shared__ T sLL[LR][LR + 1];                                   // level D approximation region
+    __shared__ T sRowE[2][LR][TE + 1];                              // level E along x1
+    const int M1c = a.M1c, M2c = a.M2c, M1 = 2 * M1c, M2 = 2 * M2c;
+    const int M1e = e.M1c, M2e = e.M2c;
+    const int c01 = bx * TC, c02 = by * TC;  // level D tile origin
+    const int e01 = bx * TE, e02 = by * TE;  // level E tile origin
+    const int tid = threadIdx.x;
+    const ProxArgs<T> &p = a.p;
+    const int64_t ch = bz;
+    const T *in = a.in + ch * a.in_plane;
+
+    // level D outputs of this thread (analysis_body's mapping) and the level E
+    // output (band src + 2 hx2, row er, column ec); prox operands loaded first
+    const int src = tid / (TC * (TC / 2));
+    const int rem = tid - src * (TC * (TC / 2));
+    const int rblk = rem / TC, l1 = rem - rblk * TC;
+    const int g1 = c01 + l1;
+    const int esrc = tid >> 7, ehx2 = (tid >> 6) & 1, er = (tid >> 3) & 7, ec = tid & 7;
+    const int eg1 = e01 + ec, eg2 = e02 + er;
+    T zcr[5], zpr[5], wr[5];
+    int64_t idxs[5];
+    bool valid[5], use[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        int64_t idx, near;
+        if (o < 4) {
+            const int q = o >> 1, hx2 = o & 1;
+            const int g2 = c02 + 2 * rblk + q;
+            valid[o] = g2 < M2c && g1 < M1c;
+            use[o] = tid < NT && valid[o] && src + 2 * hx2 != 0;  // level D's approximation stays in LDS
+            idx = (int64_t)(g2 + (hx2 ? M2c : 0)) * p.pitch + g1 + (src ? M1c : 0);
+            near = (int64_t)((g2 < M2c ? g2 : M2c - 1) + (hx2 ? M2c : 0)) * p.pitch + (g1 < M1c ? g1 : M1c - 1) +
+                   (src ? M1c : 0);
+        } else {
+            valid[o] = eg2 < M2e && eg1 < M1e;
+            use[o] = tid < NT && valid[o] && !(esrc + ehx2 == 0 && !e.last);
+            idx = (int64_t)(eg2 + (ehx2 ? M2e : 0)) * p.pitch + eg1 + (esrc ? M1e : 0);
+            near = (int64_t)((eg2 < M2e ? eg2 : M2e - 1) + (ehx2 ? M2e : 0)) * p.pitch +
+                   (eg1 < M1e ? eg1 : M1e - 1) + (esrc ? M1e : 0);
+        }
+        idxs[o] = idx;
+        const int64_t ci = ch * p.plane + near;
+        const T u = lv.zc[ci], v = lv.zp[ci];
+        zcr[o] = use[o] ? u : T(0);
+        zpr[o] = use[o] ? v : T(0);
+        const T w = (p.wmap ? p.wmap : lv.zc)[ci];
+        wr[o] = use[o] && p.wmap ? w : T(0);
+    }
+
+    // level D input region: rows and columns 2 c0 - 20 .. 2 c0 + 61 (periodic);
+    // lane = column (and column 64 + lane for the first 18 lanes), wave = rows
+    constexpr int NW = NTS / 64, RPW = (BR + NW - 1) / NW;
+    const int lane = tid & 63, wv = tid >> 6;
+    const bool l2 = lane < BR - 64;
+    const int qa = wrap(2 * c01 - 20 + lane, M1), qb = wrap(2 * c01 - 20 + 64 + (l2 ? lane : 0), M1);
+    T va[RPW], vb[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        int r = wv + i * NW;
+        r = r < BR ? r : BR - 1;  // past the end: an in-range duplicate, unused
+        const T *rowp = in + (int64_t)wrap(2 * c02 - 20 + r, M2) * a.in_pitch;
+        va[i] = rowp[qa];
+        vb[i] = rowp[qb];
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int r = wv + i * NW;
+        if (r < BR) {
+            sIn[r][lane] = va[i];
+            if (l2) sIn[r][64 + lane] = vb[i];
+        }
+    }
+    __syncthreads();
+    // along x1: level D's tile (rows 10..61, both filters, as analysis_body)
+    // and the low-pass of the approximation region (all 82 rows, 36 columns)
+    for (int t = tid; t < AR * (TC / 4) + BR * (LR / 4); t += NTS) {
+        if (t < AR * (TC / 4)) {
+            const int blk = t / AR, r = t - blk * AR;
+            T x[28];
+#pragma unroll
+            for (int j = 0; j < 28; ++j) x[j] = sIn[10 + r][10 + 8 * blk + j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T lo = T(0), hi = T(0);
+#pragma unroll
+                for (int m = 0; m < 12; ++m) {
+                    lo = fma(a.f.h[m], x[2 * q + m + 10], lo);
+                    hi = fma(a.f.g[m], x[2 * q + m], hi);
+                }
+                sRow[0][r][4 * blk + q] = lo;
+                sRow[1][r][4 * blk + q] = hi;
+            }
+        } else {
+            const int t2 = t - AR * (TC / 4), blk = t2 / BR, r = t2 - blk * BR;
+            T x[18];
+#pragma unroll
+            for (int j = 0; j < 18; ++j) x[j] = sIn[r][8 * blk + j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                T lo = T(0);
+#pragma unroll
+                for (int m = 0; m < 12; ++m) lo = fma(a.f.h[m], x[2 * q + m], lo);
+                sLo[r][4 * blk + q] = lo;
+            }
+        }
+    }
+    __syncthreads();
+    // along x2: level D's tile into registers; the approximation region into sLL
+    T res[4] = {T(0), T(0), T(0), T(0)};
+    if (tid < NT) {
+        T x[24];
+#pragma unroll
+        for (int j = 0; j < 24; ++j) x[j] = sRow[src][4 * rblk + j][l1];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            T lo = T(0), hi = T(0);
+#pragma unroll
+            for (int m = 0; m < 12; ++m) {
+                lo = fma(a.f.h[m], x[2 * q + m + 10], lo);
+                hi = fma(a.f.g[m], x[2 * q + m], hi);
+            }
+            res[2 * q + 0] = lo;
+            res[2 * q + 1] = hi;
+        }
+    }
+    constexpr int B0 = NTS > NT ? NT : 0;  // first thread of the region's x2 pass
+    for (int t = tid - B0; t >= 0 && t < LR * (LR / 4); t += NTS - B0) {
+        const int blk = t / LR, c = t - blk * LR;
+        T x[18];
+#pragma unroll
+        for (int j = 0; j < 18; ++j) x[j] = sLo[8 * blk + j][c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            T lo = T(0);
+#pragma unroll
+            for (int m = 0; m < 12; ++m) lo = fma(a.f.h[m], x[2 * q + m], lo);
+            sLL[4 * blk + q][c] = lo;
+        }
+    }
+    __syncthreads();
+    // level E along x1: 36 rows x 8 columns of both filters
+    if (tid < LR * (TE / 4)) {
+        const int blk = tid / LR, r = tid - blk * LR;
+        T x[28];
+#pragma unroll
+        for (int j = 0; j < 28; ++j) x[j] = sLL[r][8 * blk + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            T lo = T(0), hi = T(0);
+#pragma unroll
+            for (int m = 0; m < 12; ++m) {
+                lo = fma(a.f.h[m], x[2 * q + m + 10], lo);
+                hi = fma(a.f.g[m], x[2 * q + m], hi);
+            }
+            sRowE[0][r][4 * blk + q] = lo;
+            sRowE[1][r][4 * blk + q] = hi;
+        }
+    }
+    __syncthreads();
+    // level E along x2: one output per thread
+    T reso = T(0);
+    if (tid < NT) {
+        T x[12];
+        const int r0 = 2 * er + (ehx2 ? 0 : 10);
+#pragma unroll
+        for (int j = 0; j < 12; ++j) x[j] = sRowE[esrc][r0 + j][ec];
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < 12; ++m) acc = fma(ehx2 ? a.f.g[m] : a.f.h[m], x[m], acc);
+        reso = acc;
+    }
+
+    // epilogue: level D's details, then level E's output (approximation to
+    // e.apx_out unless it is the last level)
+    double st[2] = {0.0, 0.0};
+    bool bad = false;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        if (tid >= NT || !valid[o]) continue;
+        const int b = o < 4 ? src + 2 * (o & 1) : esrc + 2 * ehx2;
+        const T val = o < 4 ? res[2 * (o >> 1) + (o & 1)] : reso;
+        if (o < 4 && b == 0) continue;
+        if (o == 4 && b == 0 && !e.last) {
+            e.apx_out[ch * e.apx_plane + (int64_t)eg2 * M1e + eg1] = val;
+            continue;
+        }
+        const int bd = o < 4 ? a.band_detail : e.band_detail;
+        const T wband = b == 0 ? uniform(p.wlev[0]) : uniform(p.wlev[bd]);
+        const T w = p.wmap ? wr[o] : wband;
+        const T y = momentum(zcr[o], zpr[o], lv.beta);
+        lv.zn[ch * p.plane + idxs[o]] = prox1(y, val, p.tau, w, st, bad);
+    }
+    if (lv.slots) block_slot_add<2, NTS>(st, lv.slots + PD_NSLOT);
+    if (bad) atomicOr(p.flag, 1);
+}
+
+// ===========================================================================
 // Coarse levels lc..L in one workgroup per channel (per image when joint):
 // everything stays in LDS.  Analysis of the level lc-1 approximation (m2 x
 // m1), gradient step + prox + momentum on the coarse block of the Mallat
@@ -1792,6 +2013,19 @@ __global__ __launch_bounds__(NT) void k_analysis(AnalysisArgs<T> a)
     analysis_body<T, NCH>(a, live_of<T>(a.p, T(0)), t % a.tx, t / a.tx, blockIdx.y);
 }
 
+// 1024 threads per tile in FP32 (the passes over the region spread over four
+// waves per SIMD), 512 in FP64 (register budget)
+template <typename T>
+constexpr int analysis2_threads() { return sizeof(T) == 4 ? 4 * NT : 2 * NT; }
+
+template <typename T>
+__global__ __launch_bounds__(analysis2_threads<T>()) void k_analysis2(AnalysisArgs<T> a, AnalysisArgs<T> e)
+{
+    const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
+    if (t < 0) return;
+    analysis2_body<T, analysis2_threads<T>()>(a, e, live_of<T>(a.p, T(0)), t % a.tx, t / a.tx, blockIdx.y);
+}
+
 // The scalar coarse body, specialised for the geometry every large
 // power-of-two plane reaches (a CM x CM block, levels down to an 8 x 8 tail):
 // 64 x 64 with 3 pass-by-pass levels in FP32, 32 x 32 with 2 in FP64; and
@@ -2492,6 +2726,18 @@ hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s)
 }
 
 template <typename T>
+hipError_t launch_analysis2(const AnalysisArgs<T> &a, const AnalysisArgs<T> &e, hipStream_t s)
+{
+    if (a.mode != MODE_PROX || a.p.joint || e.M1c * 2 != a.M1c || e.M2c * 2 != a.M2c || a.last)
+        return hipErrorInvalidValue;
+    AnalysisArgs<T> b = a;
+    tiles_analysis(a.M1c, a.M2c, &b.tx, &b.ty);
+    hipLaunchKernelGGL(k_analysis2<T>, dim3(xcd_grid(b.tx * b.ty), a.p.C), dim3(analysis2_threads<T>()), 0, s, b,
+                       e);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_analysis(const AnalysisArgs<T> &a, hipStream_t s)
 {
     AnalysisArgs<T> b = a;
@@ -2790,6 +3036,7 @@ hipError_t launch_set_int(int *dst, int v, hipStream_t s)
     template hipError_t launch_jprox<T>(const JProxArgs<T> &, int, hipStream_t); \
     template size_t coarse_lds_bytes<T>(int, int, int);                                    \
     template hipError_t launch_blur<T>(const BlurArgs<T> &, bool, hipStream_t);            \
+    template hipError_t launch_analysis2<T>(const AnalysisArgs<T> &, const AnalysisArgs<T> &, hipStream_t); \
     template hipError_t launch_blur_single<T>(const BlurArgs<T> &, int, hipStream_t);      \
     template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                   \
     template hipError_t launch_synth_b<T>(const SynthArgs<T> *, const int *, int, int, Dyn<T>, hipStream_t); \

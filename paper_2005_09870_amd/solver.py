@@ -333,7 +333,8 @@ def pd_solve_batched(f0s: list[torch.Tensor], ops: list[Operator], level_ws, tau
 
 # ------------------------------------------------------------- diagnostics ---
 def pd_fuse_enable(enable: bool = True) -> None:
-    """Fusion of the two coarsest fine synthesis levels into one launch (bitwise-identical results)."""
+    """Fusion of the coarsest fine synthesis levels (three, or two) and of the two coarsest
+    fine analysis levels of an iteration into one launch each (bitwise-identical results)."""
     C.check(C.load().pd_fuse_enable(1 if enable else 0), "pd_fuse_enable")
 
 

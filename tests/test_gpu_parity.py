@@ -465,8 +465,9 @@ def test_blur_variants_reverse_mode_is_bitwise(n1, n2):
                                                    (352, 224, 1, 5, True), (320, 256, 2, 6, False)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fused_levels_are_bitwise(n1, n2, C, levels, coeff, dtype):
-    """The coarsest fine synthesis levels in one launch (three, or two) give the same
-    iterates and, statistics aside, bit for bit as one launch per level (and
+    """The coarsest fine synthesis levels in one launch (three, or two) and the two
+    coarsest fine analysis levels in one launch give the same iterates and,
+    statistics aside, bit for bit as one launch per level (and
     pd_fwt's forward and inverse transforms the same output), with level or
     per-coefficient weights."""
     pb, f0, case = _problem(n1, n2, C=C, levels=levels, seed=99, coeff=coeff)
