@@ -54,6 +54,7 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
                 (+0.75 x input with a per-coefficient weight map)
     analysis2 : levels l and l+1 in one launch; level l's approximation
                 never reaches HBM                            -> 3.875 x input
+                (plain: 2 x input)
     coarse    : all levels from l on, one workgroup          -> 5 x input
     analysis, plain (the joint prox's split form): reads its input, writes
                 the coefficients and the coarser approximation -> 2 x input
@@ -80,7 +81,7 @@ def alg_bytes(kernel: str, level: int, n1: int, n2: int, C: int, es: int, coeff_
     if kernel == "analysis":
         return (2.0 if plain else 3.5 + (0.75 if coeff_w else 0.0)) * es * m
     if kernel == "analysis2":  # levels `level` and level + 1; the finer approximation stays on chip
-        return (3.875 + (0.75 * 1.25 if coeff_w else 0.0)) * es * m
+        return (2.0 if plain else 3.875 + (0.75 * 1.25 if coeff_w else 0.0)) * es * m
     return 0.0
 
 

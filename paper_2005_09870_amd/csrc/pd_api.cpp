@@ -394,8 +394,8 @@ int analysis_fine(const Ctx<T> &c, const T *in, int mode, const ProxArgs<T> &p)
         a.p = p;
         return a;
     };
-    // the two coarsest fine levels of an iteration in one launch
-    const bool fuse = g_synth2 && mode == MODE_PROX && !p.joint && c.lc - 1 >= 2;
+    // the two coarsest fine levels in one launch
+    const bool fuse = g_synth2 && !p.joint && c.lc - 1 >= 2;
     const int single = fuse ? c.lc - 3 : c.lc - 1;
     for (int lev = 1; lev <= single; ++lev) {
         const AnalysisArgs<T> a = args(lev);

@@ -164,9 +164,9 @@ struct Dyn {
 };
 
 template <typename T> hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s);
-// Analysis levels D (a) and D + 1 (e) in one launch, gradient step + prox
-// mode, one channel per tile set; level D's approximation band stays in LDS
-// (a.apx_out is not written).  Same outputs as two launch_analysis calls.
+// Analysis levels D (a) and D + 1 (e) in one launch, gradient step + prox or
+// plain mode, one channel per tile set; level D's approximation band stays in
+// LDS (a.apx_out is not written).  Same outputs as two launch_analysis calls.
 template <typename T>
 hipError_t launch_analysis2(const AnalysisArgs<T> &a, const AnalysisArgs<T> &e, hipStream_t s);
 // two synthesis levels in one launch: d = the finer level, u = the next coarser

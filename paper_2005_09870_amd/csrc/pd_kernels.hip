@@ -772,8 +772,8 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
 }
 
 // ===========================================================================
-// Two analysis levels in one launch (gradient step + prox mode, one channel
-// per tile set): levels D and E = D + 1.  A workgroup owns a 16 x 16 tile of
+// Two analysis levels in one launch (gradient step + prox or plain mode, one
+// channel per tile set): levels D and E = D + 1.  A workgroup owns a 16 x 16 tile of
 // level D's bands and the 8 x 8 tile of level E's bands below it.  From one
 // 82 x 82 region of level D's input in LDS it computes (i) level D's detail
 // bands on the owned tile, exactly as analysis_body does, and (ii) level D's
@@ -804,6 +804,7 @@ __device__ __forceinline__ void analysis2_body(const AnalysisArgs<T> &a, const A
     const int e01 = bx * TE, e02 = by * TE;  // level E tile origin
     const int tid = threadIdx.x;
     const ProxArgs<T> &p = a.p;
+    const bool prox = a.mode == MODE_PROX;
     const int64_t ch = bz;
     const T *in = a.in + ch * a.in_plane;
 
@@ -837,11 +838,12 @@ __device__ __forceinline__ void analysis2_body(const AnalysisArgs<T> &a, const A
                    (eg1 < M1e ? eg1 : M1e - 1) + (esrc ? M1e : 0);
         }
         idxs[o] = idx;
-        const int64_t ci = ch * p.plane + near;
-        const T u = lv.zc[ci], v = lv.zp[ci];
+        // (plain mode: element 0 of the input, which this launch reads anyway)
+        const int64_t ci = prox ? ch * p.plane + near : 0;
+        const T u = (prox ? lv.zc : a.in)[ci], v = (prox ? lv.zp : a.in)[ci];
         zcr[o] = use[o] ? u : T(0);
         zpr[o] = use[o] ? v : T(0);
-        const T w = (p.wmap ? p.wmap : lv.zc)[ci];
+        const T w = (prox && p.wmap ? p.wmap : a.in)[ci];
         wr[o] = use[o] && p.wmap ? w : T(0);
     }
 
@@ -982,14 +984,20 @@ __device__ __forceinline__ void analysis2_body(const AnalysisArgs<T> &a, const A
             e.apx_out[ch * e.apx_plane + (int64_t)eg2 * M1e + eg1] = val;
             continue;
         }
+        if (!prox) {
+            lv.zn[ch * p.plane + idxs[o]] = val;
+            continue;
+        }
         const int bd = o < 4 ? a.band_detail : e.band_detail;
         const T wband = b == 0 ? uniform(p.wlev[0]) : uniform(p.wlev[bd]);
         const T w = p.wmap ? wr[o] : wband;
         const T y = momentum(zcr[o], zpr[o], lv.beta);
         lv.zn[ch * p.plane + idxs[o]] = prox1(y, val, p.tau, w, st, bad);
     }
-    if (lv.slots) block_slot_add<2, NTS>(st, lv.slots + PD_NSLOT);
-    if (bad) atomicOr(p.flag, 1);
+    if (prox) {
+        if (lv.slots) block_slot_add<2, NTS>(st, lv.slots + PD_NSLOT);
+        if (bad) atomicOr(p.flag, 1);
+    }
 }
 
 // ===========================================================================
@@ -2728,7 +2736,7 @@ hipError_t launch_synth(const SynthArgs<T> &a, int C, hipStream_t s)
 template <typename T>
 hipError_t launch_analysis2(const AnalysisArgs<T> &a, const AnalysisArgs<T> &e, hipStream_t s)
 {
-    if (a.mode != MODE_PROX || a.p.joint || e.M1c * 2 != a.M1c || e.M2c * 2 != a.M2c || a.last)
+    if (a.p.joint || e.M1c * 2 != a.M1c || e.M2c * 2 != a.M2c || a.last || e.mode != a.mode)
         return hipErrorInvalidValue;
     AnalysisArgs<T> b = a;
     tiles_analysis(a.M1c, a.M2c, &b.tx, &b.ty);
