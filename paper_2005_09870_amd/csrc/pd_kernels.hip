@@ -843,7 +843,7 @@ __device__ __forceinline__ void analysis2_body(const AnalysisArgs<T> &a, const A
         const T u = (prox ? lv.zc : a.in)[ci], v = (prox ? lv.zp : a.in)[ci];
         zcr[o] = use[o] ? u : T(0);
         zpr[o] = use[o] ? v : T(0);
-        const T w = (prox && p.wmap ? p.wmap : a.in)[ci];
+        const T w = (prox ? (p.wmap ? p.wmap : lv.zc) : a.in)[ci];  // ci indexes the Mallat plane or is 0
         wr[o] = use[o] && p.wmap ? w : T(0);
     }
 
