@@ -1596,14 +1596,18 @@ constexpr int BT1 = BW - 2 * RM;       // 46 output columns
 constexpr int BX1 = BT1 + 4 * RM;      // 82 x columns
 constexpr int XP = 84;                 // LDS pitch of x (multiple of 4)
 constexpr int TP = 68;                 // LDS pitch of t, r, u (multiple of 4)
-constexpr int NTB = 512;               // blur workgroup: 8 waves (two per SIMD hide LDS latency)
+// Blur workgroup: 1024 threads for the FP32 32-row tile (four waves per SIMD,
+// every pass's tasks in one round), else 512 (two waves per SIMD hide the LDS
+// latency; 1024 would spill).  The same outputs either way.
+template <typename T, int BT2>
+constexpr int blur_threads() { return sizeof(T) == 4 && BT2 == 32 ? 1024 : 512; }
 static_assert(BX1 <= 128 && BX1 > 64, "blur load columns");
 constexpr int UVH = 4;                 // rows per column task in the u pass
 
 // Tile height variants (the tuned parameter; every output pixel is computed by
 // the same sums in the same order whatever the variant): BT2 output rows,
 // BX2 rows of x and t, BR2 rows of r, RVH rows per column task of the r pass.
-template <int BT2_>
+template <int BT2_, int NTB>
 struct BlurGeom {
     static constexpr int BT2 = BT2_;
     static constexpr int BX2 = BT2 + 4 * RM;
@@ -1615,7 +1619,7 @@ struct BlurGeom {
 
 template <typename T, int BT2>
 struct BlurLds {
-    using G = BlurGeom<BT2>;
+    using G = BlurGeom<BT2, blur_threads<T, BT2>()>;
     alignas(16) T sA[G::BX2 * XP];         // x, later r (BR2 x TP)
     alignas(16) T sB[G::BX2 * TP];         // t, later u (BT2 x TP)
     alignas(16) T sK[G::BX2][2 * RM + 2];  // profiles of the rows of x / t
@@ -1623,11 +1627,10 @@ struct BlurLds {
 };
 
 // The four passes on a staged tile (profiles zero-padded to RM).
-template <typename T, int BT2>
+template <typename T, int BT2, int NTB = blur_threads<T, BT2>(), typename G = BlurGeom<BT2, NTB>>
 __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, int bz, BlurLds<T, BT2> &lds,
-                                          const T (&f0pre)[BlurGeom<BT2>::RB_PER_WAVE][BlurGeom<BT2>::RVH])
+                                          const T (&f0pre)[G::RB_PER_WAVE][G::RVH])
 {
-    using G = BlurGeom<BT2>;
     constexpr int BX2 = G::BX2, BR2 = G::BR2, RVH = G::RVH, RB_PER_WAVE = G::RB_PER_WAVE;
     T *__restrict__ sA = lds.sA;
     T *__restrict__ sB = lds.sB;
@@ -1752,7 +1755,8 @@ __device__ __forceinline__ void blur_body(const BlurArgs<T> &a, int bx, int by, 
 template <typename T, int BT2>
 __device__ __forceinline__ void blur_tile(const BlurArgs<T> &a, int bx, int by, int bz)
 {
-    using G = BlurGeom<BT2>;
+    constexpr int NTB = blur_threads<T, BT2>();
+    using G = BlurGeom<BT2, NTB>;
     constexpr int BX2 = G::BX2, BR2 = G::BR2, RVH = G::RVH, RB_PER_WAVE = G::RB_PER_WAVE;
     __shared__ BlurLds<T, BT2> lds;
     T *__restrict__ sA = lds.sA;
@@ -2142,7 +2146,7 @@ __global__ __launch_bounds__(NT) void k_jprox(JProxArgs<T> a)
 }
 
 template <typename T, int BT2>
-__global__ __launch_bounds__(NTB) void k_blur(BlurArgs<T> a)
+__global__ __launch_bounds__((blur_threads<T, BT2>())) void k_blur(BlurArgs<T> a)
 {
     const int t = xcd_tile(a.tx * a.ty);  // channel = blockIdx.y
     if (t < 0) return;
@@ -2658,7 +2662,7 @@ __global__ __launch_bounds__(NTC) void k_coarse_b(const CoarseArgs<T> *__restric
 }
 
 template <typename T>
-__global__ __launch_bounds__(NTB) void k_blur_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
+__global__ __launch_bounds__((blur_threads<T, 32>())) void k_blur_b(const BlurArgs<T> *__restrict__ tab, const int *__restrict__ start,
                                                 int n, int ring)
 {
     const int g = xcd_tile(start[n]);
@@ -2824,9 +2828,11 @@ hipError_t launch_blur(const BlurArgs<T> &a, bool identity, hipStream_t s)
         const int bt2 = v == 48 ? 48 : 32;
         tiles_blur(a.n1, a.n2, &b.tx, &b.ty, bt2);
         if (bt2 == 48)
-            hipLaunchKernelGGL((k_blur<T, 48>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
+            hipLaunchKernelGGL((k_blur<T, 48>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(blur_threads<T, 48>()), 0, s,
+                               b);
         else
-            hipLaunchKernelGGL((k_blur<T, 32>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(NTB), 0, s, b);
+            hipLaunchKernelGGL((k_blur<T, 32>), dim3(xcd_grid(b.tx * b.ty), a.C), dim3(blur_threads<T, 32>()), 0, s,
+                               b);
     }
     return hipGetLastError();
 }
@@ -2911,7 +2917,7 @@ hipError_t launch_blur_split_b(const BlurArgs<T> *tab, const int *start_h, const
 template <typename T>
 hipError_t launch_blur_b(const BlurArgs<T> *tab, const int *start, int n, int tiles, int ring, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_blur_b<T>, dim3(xcd_grid(tiles)), dim3(NTB), 0, s, tab, start, n, ring);
+    hipLaunchKernelGGL(k_blur_b<T>, dim3(xcd_grid(tiles)), dim3(blur_threads<T, 32>()), 0, s, tab, start, n, ring);
     return hipGetLastError();
 }
 
