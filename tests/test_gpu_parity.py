@@ -462,12 +462,15 @@ def test_blur_variants_reverse_mode_is_bitwise(n1, n2):
 @pytest.mark.parametrize("n1,n2,C,levels,coeff", [(512, 512, 1, 9, False), (160, 96, 2, 5, False),
                                                    (256, 128, 1, 3, False), (1024, 64, 1, 6, False),
                                                    (512, 256, 1, 2, False), (512, 512, 1, 9, True),
-                                                   (352, 224, 1, 5, True), (320, 256, 2, 6, False)])
+                                                   (352, 224, 1, 5, True), (320, 256, 2, 6, False),
+                                                   (2048, 16, 1, 4, False), (16, 2048, 1, 4, True)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_fused_levels_are_bitwise(n1, n2, C, levels, coeff, dtype):
     """The coarsest fine synthesis levels in one launch (three, or two) and the two
     coarsest fine analysis levels in one launch give the same iterates and,
-    statistics aside, bit for bit as one launch per level (and
+    statistics aside, bit for bit as one launch per level (on 2048 x 16 the
+    fused analysis pair is levels 3 and 4, bands 2 and 1 rows high with level
+    4 the last, and its 82-row input region wraps around a 4-row plane; and
     pd_fwt's forward and inverse transforms the same output), with level or
     per-coefficient weights."""
     pb, f0, case = _problem(n1, n2, C=C, levels=levels, seed=99, coeff=coeff)
