@@ -267,6 +267,7 @@ ProxArgs<T> prox_args(const Ctx<T> &c, const T *zc, const T *zp, T *zn, T beta, 
     p.zc = zc;
     p.zp = zp;
     p.zn = zn;
+    p.zsave = nullptr;
     p.beta = beta;
     p.tau = tau;
     p.plane = c.N();
@@ -495,7 +496,7 @@ inline double beta_y(int i) { return i >= 2 ? (double)(i - 2) / (double)(i + 1) 
 // di.it_off == i), so that a captured graph of them replays for any i.
 template <typename T>
 int one_iteration(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, const T *zc,
-                  T *zp, int it, int i, int count, double *stats, int i_first, DevIter di)
+                  T *zp, int it, int i, int count, double *stats, int i_first, DevIter di, T *zsave = nullptr)
 {
     const pd_shape *sh = c.sh;
     const hipStream_t st = c.st;
@@ -514,6 +515,7 @@ int one_iteration(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T
     // z(i) overwrites z(i-2) in place (each coefficient is read, then written, by one thread)
     ProxArgs<T> p = prox_args<T>(c, zc, zp, zp, beta, tau, w, sti);
     p.di = di;
+    p.zsave = zsave;  // every coefficient of z(i) is stored by exactly one prox epilogue
     if (p.joint && sh->channels > 1) {
         // joint prox over several channels: per-channel plain analysis (fine levels, then the coarse
         // block) into the x plane (free after the blur), the joint prox over the whole plane, then
@@ -729,7 +731,7 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
     for (int it = 1; it + PD_RING < count; it += PD_RING) ++chunks;
     const bool may_capture = chunks >= 4;
     for (int it = 0; it < count;) {
-        if (graphs && it % PD_RING == 1 && it + PD_RING < count) {
+        if (graphs && !seg && it % PD_RING == 1 && it + PD_RING < count) {
             int err = PD_OK;
             if (launch_chunk_graph<T>(c, op, w, tau, f0, zc, zp, it, count, stats, i_first, may_capture, &err)) {
                 if (err != PD_OK) return err;
@@ -738,9 +740,8 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
             }
         }
         if ((rc = one_iteration<T>(c, op, w, tau, f0, zc, zp, it, i_first + it, count, stats, i_first,
-                                   DevIter{nullptr, 0})) != PD_OK)
+                                   DevIter{nullptr, 0}, seg ? seg + (int64_t)it * NC : nullptr)) != PD_OK)
             return rc;
-        if (seg) PD_TRY_HIP(launch_copy<T>(zp, seg + (int64_t)it * NC, NC, st));
         T *t = zc;
         zc = zp;
         zp = t;
@@ -749,8 +750,8 @@ int iterate(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, 
     return PD_OK;
 }
 
-// The recomputation of pd_backward: count iterations from (zc, zp) with a
-// copy of every z(i) in seg.  it_dev set: the launches read i = *it_dev +
+// The recomputation of pd_backward: count iterations from (zc, zp), every
+// z(i) also stored in seg by the kernels that compute it.  it_dev set: the launches read i = *it_dev +
 // local index from device memory (for a captured segment).
 template <typename T>
 int iterate_seg(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T tau, const T *f0, T *zc, T *zp,
@@ -760,9 +761,8 @@ int iterate_seg(const Ctx<T> &c, const pd_operator *op, const pd_weights *w, T t
     int rc;
     for (int it = 0; it < count; ++it) {
         if ((rc = one_iteration<T>(c, op, w, tau, f0, zc, zp, it, i_first + it, count, nullptr, i_first,
-                                   DevIter{it_dev, it_dev ? it : 0})) != PD_OK)
+                                   DevIter{it_dev, it_dev ? it : 0}, seg + (int64_t)it * NC)) != PD_OK)
             return rc;
-        PD_TRY_HIP(launch_copy<T>(zp, seg + (int64_t)it * NC, NC, c.st));
         std::swap(zc, zp);
     }
     return PD_OK;

@@ -58,6 +58,8 @@ template <typename T>
 struct ProxArgs {
     const T *zc, *zp;
     T *zn;
+    T *zsave;               // nullptr, or a second plane that also receives z(i) (the
+                            // recomputation's per-iteration record in pd_backward)
     T beta, tau;
     int64_t plane;
     int pitch;

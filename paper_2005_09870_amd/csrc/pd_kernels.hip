@@ -739,7 +739,9 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
         if (!JOINT) {
             T w = p.wmap ? wr[o] : wband;
             T y = momentum(zcr[0][o], zpr[0][o], lv.beta);
-            lv.zn[(int64_t)ch0 * p.plane + idx] = prox1(y, res[0][2 * q + hx2], p.tau, w, st, bad);
+            const T z = prox1(y, res[0][2 * q + hx2], p.tau, w, st, bad);
+            lv.zn[(int64_t)ch0 * p.plane + idx] = z;
+            if (p.zsave) p.zsave[(int64_t)ch0 * p.plane + idx] = z;
         } else {
             T yv[NC], vv[NC];
             T nv = T(0);
@@ -761,6 +763,7 @@ __device__ __forceinline__ void analysis_body(const AnalysisArgs<T> &a, const Li
             for (int cc = 0; cc < NC; ++cc) {
                 T z = mul_rn(vv[cc], sc);
                 lv.zn[(int64_t)cc * p.plane + idx] = z;
+                if (p.zsave) p.zsave[(int64_t)cc * p.plane + idx] = z;
                 st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
             }
         }
@@ -992,7 +995,9 @@ __device__ __forceinline__ void analysis2_body(const AnalysisArgs<T> &a, const A
         const T wband = b == 0 ? uniform(p.wlev[0]) : uniform(p.wlev[bd]);
         const T w = p.wmap ? wr[o] : wband;
         const T y = momentum(zcr[o], zpr[o], lv.beta);
-        lv.zn[ch * p.plane + idxs[o]] = prox1(y, val, p.tau, w, st, bad);
+        const T z = prox1(y, val, p.tau, w, st, bad);
+        lv.zn[ch * p.plane + idxs[o]] = z;
+        if (p.zsave) p.zsave[ch * p.plane + idxs[o]] = z;
     }
     if (prox) {
         if (lv.slots) block_slot_add<2, NTS>(st, lv.slots + PD_NSLOT);
@@ -1464,6 +1469,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 T y = momentum(zcr[0][k], zpr[0][k], lv.beta);
                 T z = prox1(y, A[li], p.tau, w, st, bad);
                 lv.zn[(int64_t)ch0 * p.plane + gi[k]] = z;
+                if (p.zsave) p.zsave[(int64_t)ch0 * p.plane + gi[k]] = z;
                 const T yn = momentum(z, zcr[0][k], lv.beta_next);
                 if (!routed || (kw < nlev && r < tM2 && c < tM1)) {
                     A[li] = yn;  // the tail's input (or the whole block)
@@ -1497,6 +1503,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
                 for (int cc = 0; cc < NCH; ++cc) {
                     T z = mul_rn(vv[cc], sc);
                     lv.zn[(int64_t)cc * p.plane + gi[k]] = z;
+                    if (p.zsave) p.zsave[(int64_t)cc * p.plane + gi[k]] = z;
                     st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
                     home(cc)[li] = momentum(z, zcr[cc][k], lv.beta_next);
                 }
@@ -2137,6 +2144,7 @@ __global__ __launch_bounds__(NT) void k_jprox(JProxArgs<T> a)
             for (int cc = 0; cc < NCH; ++cc) {
                 T z = mul_rn(vv[cc], sc);
                 lv.zn[(int64_t)cc * p.plane + gi[u]] = z;
+                if (p.zsave) p.zsave[(int64_t)cc * p.plane + gi[u]] = z;
                 st[1] += ((double)z - (double)yv[cc]) * ((double)z - (double)yv[cc]);
             }
         }
