@@ -375,6 +375,8 @@ int synth_chain(const Ctx<T> &c, const T *zc, const T *zp, T beta, T *out, DevIt
 
 // Fine analysis levels 1 .. lc-1: plain coefficients (MODE_PLAIN) or the fused
 // gradient step + prox + momentum (MODE_PROX).
+constexpr int64_t ANA2_MAX_INPUT = 512 * 512;
+
 template <typename T>
 int analysis_fine(const Ctx<T> &c, const T *in, int mode, const ProxArgs<T> &p)
 {
@@ -395,16 +397,20 @@ int analysis_fine(const Ctx<T> &c, const T *in, int mode, const ProxArgs<T> &p)
         a.p = p;
         return a;
     };
-    // the two coarsest fine levels in one launch
-    const bool fuse = g_synth2 && !p.joint && c.lc - 1 >= 2;
-    const int single = fuse ? c.lc - 3 : c.lc - 1;
+    // Levels in pairs (one launch each) from the coarsest fine level down,
+    // while the finer level of the pair reads at most ANA2_MAX_INPUT values per
+    // channel (the latency-bound sizes; on larger planes the pair's overlapping
+    // input regions cost more than the launch it saves); the rest one by one.
+    int single = c.lc - 1;
+    if (g_synth2 && !p.joint)
+        while (single >= 2 && (int64_t)(n1 >> (single - 2)) * (n2 >> (single - 2)) <= ANA2_MAX_INPUT) single -= 2;
     for (int lev = 1; lev <= single; ++lev) {
         const AnalysisArgs<T> a = args(lev);
         PD_TRY_HIP(timed(PD_K_ANALYSIS, lev, c.st, [&] { return launch_analysis<T>(a, c.st); }));
     }
-    if (fuse) {
-        const AnalysisArgs<T> a = args(c.lc - 2), e = args(c.lc - 1);
-        PD_TRY_HIP(timed(PD_K_ANALYSIS2, c.lc - 2, c.st, [&] { return launch_analysis2<T>(a, e, c.st); }));
+    for (int lev = single + 1; lev + 1 <= c.lc - 1; lev += 2) {
+        const AnalysisArgs<T> a = args(lev), e = args(lev + 1);
+        PD_TRY_HIP(timed(PD_K_ANALYSIS2, lev, c.st, [&] { return launch_analysis2<T>(a, e, c.st); }));
     }
     return PD_OK;
 }
