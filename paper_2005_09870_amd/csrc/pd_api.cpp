@@ -1743,15 +1743,20 @@ int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *w
         const hipStream_t s = cs.st;
         if ((rc = iterate_seg<T>(cs, op, w, tau, f0, zc, zp, i0, cnt, seg, dev ? cs.it_dev() : nullptr)) != PD_OK)
             return rc;
+        // the mask of iteration j-1 runs in the same launch as the combine of j
+        if (cnt > 0) PD_TRY_HIP(launch_rev_mask<T>(zbar, seg + (int64_t)(cnt - 1) * NC, vbar, gw, tau, NC, s));
         for (int j = cnt - 1; j >= 0; --j) {
             const int i = i0 + j;
-            PD_TRY_HIP(launch_rev_mask<T>(zbar, seg + (int64_t)j * NC, vbar, gw, tau, NC, s));
             if ((rc = synth_chain<T>(cs, vbar, vbar, T(0), cs.x())) != PD_OK) return rc;         // Psi vbar
             if ((rc = blur_step<T>(cs, op, cs.x(), nullptr, cs.s(), nullptr, gf0, tau)) != PD_OK) return rc;
             if ((rc = analysis_plain<T>(cs, cs.s(), gbar)) != PD_OK) return rc;                   // Psi^* H^T H Psi vbar
             const T b = (T)beta_y(i);  // b_{i-1}
-            PD_TRY_HIP(launch_rev_combine<T>(vbar, gbar, zbar, zbarm, tau, b, i == 1 ? 1 : 0, NC,
-                                             DevIter{dev ? cs.it_dev() : nullptr, j}, s));
+            const DevIter di{dev ? cs.it_dev() : nullptr, j};
+            if (j > 0)
+                PD_TRY_HIP(launch_rev_combine_mask<T>(vbar, gbar, zbar, zbarm, seg + (int64_t)(j - 1) * NC, gw, tau, b,
+                                                      i == 1 ? 1 : 0, NC, di, s));
+            else
+                PD_TRY_HIP(launch_rev_combine<T>(vbar, gbar, zbar, zbarm, tau, b, i == 1 ? 1 : 0, NC, di, s));
         }
         return PD_OK;
     };

@@ -235,6 +235,10 @@ hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, i
 template <typename T>
 hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
                               DevIter di, hipStream_t s);
+// launch_rev_combine of iteration i, then launch_rev_mask of iteration i-1 with z = z(i-1), in one launch
+template <typename T>
+hipError_t launch_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, const T *z, T *wbar, T tau, T b,
+                                   int first, int64_t n, DevIter di, hipStream_t s);
 template <typename T> hipError_t launch_add(const T *x, T *y, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C, int levels, hipStream_t s);

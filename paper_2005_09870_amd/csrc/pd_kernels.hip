@@ -1914,14 +1914,44 @@ __global__ void k_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T
         b = beta_at<T>(i);
         first = i == 1;
     }
+    // explicit fused multiply-adds (the same in k_rev_combine_mask: the same bits)
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const T yb = vbar[e] - tau * gbar[e];
+        const T yb = fma(-tau, gbar[e], vbar[e]);
         if (first) {
             zbar[e] = yb + zbarm[e];
         } else {
-            zbar[e] = zbarm[e] + (T(1) + b) * yb;
+            zbar[e] = fma(T(1) + b, yb, zbarm[e]);
             zbarm[e] = -b * yb;
         }
+    }
+}
+
+// k_rev_combine of iteration i followed, element by element, by k_rev_mask of
+// iteration i-1 (z = z(i-1)): the same operations in the same order as the
+// two launches, so the same bits.
+template <typename T>
+__global__ void k_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, const T *z, T *wbar, T tau, T b,
+                                   int first, int64_t n, DevIter di)
+{
+    if (di.it_dev) {
+        const int i = *di.it_dev + di.it_off;
+        b = beta_at<T>(i);
+        first = i == 1;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const T yb = fma(-tau, gbar[e], vbar[e]);
+        T zb;
+        if (first) {
+            zb = yb + zbarm[e];
+        } else {
+            zb = fma(T(1) + b, yb, zbarm[e]);
+            zbarm[e] = -b * yb;
+        }
+        zbar[e] = zb;
+        const T zv = z[e];
+        const bool act = zv != T(0);
+        vbar[e] = act ? zb : T(0);
+        if (wbar && act) wbar[e] -= tau * zb * (zv > T(0) ? T(1) : T(-1));
     }
 }
 
@@ -2969,6 +2999,14 @@ hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T
     return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, const T *z, T *wbar, T tau, T b,
+                                   int first, int64_t n, DevIter di, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rev_combine_mask<T>, dim3(ew_blocks(n)), dim3(256), 0, s, vbar, gbar, zbar, zbarm, z, wbar,
+                       tau, b, first, n, di);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_add(const T *x, T *y, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add<T>, dim3(ew_blocks(n)), dim3(256), 0, s, x, y, n);
@@ -2985,6 +3023,8 @@ hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C,
     template hipError_t launch_rev_mask<T>(const T *, const T *, T *, T *, T, int64_t, hipStream_t);    \
     template hipError_t launch_rev_combine<T>(const T *, const T *, T *, T *, T, T, int, int64_t, DevIter, \
                                               hipStream_t);                                             \
+    template hipError_t launch_rev_combine_mask<T>(T *, const T *, T *, T *, const T *, T *, T, T, int, int64_t, \
+                                                   DevIter, hipStream_t);                                        \
     template hipError_t launch_add<T>(const T *, T *, int64_t, hipStream_t);                            \
     template hipError_t launch_expand_weights<T>(T *, const T *, int, int, int, int, hipStream_t);
 PD_INST_REV(float)
