@@ -292,7 +292,8 @@ ProxArgs<T> prox_args(const Ctx<T> &c, const T *zc, const T *zp, T *zn, T beta, 
 // approximation (apx[lc-1], or `in` when lc == 1); synthesis output goes to
 // apx[lc-1] or `out` when lc == 1.
 template <typename T>
-int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T> &p, T beta_next)
+int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T> &p, T beta_next,
+                const CoarseArgs<T> *rv = nullptr)
 {
     const int L = c.sh->levels, lc = c.lc;
     CoarseArgs<T> a;
@@ -313,6 +314,15 @@ int coarse_step(const Ctx<T> &c, int ops, const T *in, T *out, const ProxArgs<T>
     a.tail = c.tail;
     if (c.ts.nt > 0 && !c.tail) return PD_ERR_HIP;
     a.p = p;
+    if (rv) {  // the reverse sweep's combine and mask (COARSE_REVCM)
+        a.rv_vbar = rv->rv_vbar;
+        a.rv_zbar = rv->rv_zbar;
+        a.rv_zbarm = rv->rv_zbarm;
+        a.rv_wbar = rv->rv_wbar;
+        a.rv_b = rv->rv_b;
+        a.rv_first = rv->rv_first;
+        a.rv_di = rv->rv_di;
+    }
     const int groups = p.joint ? 1 : c.sh->channels;
     PD_TRY_HIP(timed(PD_K_COARSE, lc, c.st, [&] { return launch_coarse<T>(a, groups, c.st); }));
     return PD_OK;
@@ -1743,18 +1753,48 @@ int backward_impl(const pd_shape *sh, const pd_operator *op, const pd_wavelet *w
         const hipStream_t s = cs.st;
         if ((rc = iterate_seg<T>(cs, op, w, tau, f0, zc, zp, i0, cnt, seg, dev ? cs.it_dev() : nullptr)) != PD_OK)
             return rc;
-        // the mask of iteration j-1 runs in the same launch as the combine of j
+        // The mask of iteration j-1 runs in the same launch as the combine of j.
+        // With a coarse block, iterations j > 0 end with one coarse launch: the
+        // analysis of gbar on the block, combine and mask there, and the
+        // synthesis of the next vbar (the element-wise launch skips the block),
+        // so the next iteration synthesises the fine levels only.
+        const bool fco = g_synth2 && cs.lc <= cs.sh->levels;
+        const int cm1 = cs.sh->n1 >> (cs.lc - 1), cm2 = cs.sh->n2 >> (cs.lc - 1);
         if (cnt > 0) PD_TRY_HIP(launch_rev_mask<T>(zbar, seg + (int64_t)(cnt - 1) * NC, vbar, gw, tau, NC, s));
         for (int j = cnt - 1; j >= 0; --j) {
             const int i = i0 + j;
-            if ((rc = synth_chain<T>(cs, vbar, vbar, T(0), cs.x())) != PD_OK) return rc;         // Psi vbar
+            if (fco && j < cnt - 1) {
+                if ((rc = synth_fine<T>(cs, vbar, vbar, T(0), cs.x())) != PD_OK) return rc;      // Psi vbar
+            } else if ((rc = synth_chain<T>(cs, vbar, vbar, T(0), cs.x())) != PD_OK) {
+                return rc;
+            }
             if ((rc = blur_step<T>(cs, op, cs.x(), nullptr, cs.s(), nullptr, gf0, tau)) != PD_OK) return rc;
-            if ((rc = analysis_plain<T>(cs, cs.s(), gbar)) != PD_OK) return rc;                   // Psi^* H^T H Psi vbar
             const T b = (T)beta_y(i);  // b_{i-1}
             const DevIter di{dev ? cs.it_dev() : nullptr, j};
+            if (j > 0 && fco) {
+                // Psi^* H^T H Psi vbar: the fine levels, then the block in the coarse launch
+                ProxArgs<T> pl = prox_args<T>(cs, nullptr, nullptr, gbar, T(0), T(0), nullptr, nullptr);
+                if ((rc = analysis_fine<T>(cs, cs.s(), MODE_PLAIN, pl)) != PD_OK) return rc;
+                ProxArgs<T> pr = prox_args<T>(cs, vbar, seg + (int64_t)(j - 1) * NC, gbar, T(0), tau, nullptr, nullptr);
+                CoarseArgs<T> rv;
+                rv.rv_vbar = vbar;
+                rv.rv_zbar = zbar;
+                rv.rv_zbarm = zbarm;
+                rv.rv_wbar = gw;
+                rv.rv_b = b;
+                rv.rv_first = i == 1 ? 1 : 0;
+                rv.rv_di = di;
+                if ((rc = coarse_step<T>(cs, COARSE_ANA | COARSE_REVCM | COARSE_SYN, cs.s(), cs.x(), pr, T(0), &rv)) !=
+                    PD_OK)
+                    return rc;
+                PD_TRY_HIP(launch_rev_combine_mask<T>(vbar, gbar, zbar, zbarm, seg + (int64_t)(j - 1) * NC, gw, tau, b,
+                                                      i == 1 ? 1 : 0, NC, di, cm1, cm2, cs.sh->n1, cs.N(), s));
+                continue;
+            }
+            if ((rc = analysis_plain<T>(cs, cs.s(), gbar)) != PD_OK) return rc;                   // Psi^* H^T H Psi vbar
             if (j > 0)
                 PD_TRY_HIP(launch_rev_combine_mask<T>(vbar, gbar, zbar, zbarm, seg + (int64_t)(j - 1) * NC, gw, tau, b,
-                                                      i == 1 ? 1 : 0, NC, di, s));
+                                                      i == 1 ? 1 : 0, NC, di, 0, 0, cs.sh->n1, cs.N(), s));
             else
                 PD_TRY_HIP(launch_rev_combine<T>(vbar, gbar, zbar, zbarm, tau, b, i == 1 ? 1 : 0, NC, di, s));
         }

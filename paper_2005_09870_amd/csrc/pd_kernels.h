@@ -97,7 +97,7 @@ struct AnalysisArgs {
 // the approximation of level lc-1 (m1 x m2, dense) is analysed, the prox and
 // momentum are applied to the coarse block [0,m2) x [0,m1) of the Mallat
 // plane, and/or the block is synthesised back to a level lc-1 approximation.
-enum { COARSE_ANA = 1, COARSE_PROX = 2, COARSE_SYN = 4 };
+enum { COARSE_ANA = 1, COARSE_PROX = 2, COARSE_SYN = 4, COARSE_REVCM = 8 };
 template <typename T>
 struct CoarseArgs {
     Filt<T> f;
@@ -115,6 +115,14 @@ struct CoarseArgs {
     const T *tail;          // [2][tn][tn], tn = tM1*tM2: the tail's analysis matrix (row = output,
                             // Mallat position) then its transpose (synthesis); nullptr if kw == nlev
     ProxArgs<T> p;          // in PLAIN analysis (ops == ANA) zn receives coefficients
+    // Reverse sweep (COARSE_REVCM, one channel per workgroup): after the analysis
+    // of gbar, the combine of iteration i and the mask of iteration i-1 on the
+    // block (vbar in p.zc, z(i-1) in p.zp, tau in p.tau; b = b_{i-1}), then the
+    // synthesis of the new vbar (with COARSE_SYN)
+    T *rv_vbar = nullptr, *rv_zbar = nullptr, *rv_zbarm = nullptr, *rv_wbar = nullptr;
+    T rv_b = T(0);
+    int rv_first = 0;
+    DevIter rv_di{nullptr, 0};
 };
 
 // The joint prox on a coarse block (m1 x m2 at the top left of each channel's
@@ -235,10 +243,12 @@ hipError_t launch_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, i
 template <typename T>
 hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T tau, T b, int first, int64_t n,
                               DevIter di, hipStream_t s);
-// launch_rev_combine of iteration i, then launch_rev_mask of iteration i-1 with z = z(i-1), in one launch
+// launch_rev_combine of iteration i, then launch_rev_mask of iteration i-1 with z = z(i-1), in one launch;
+// the sk2 x sk1 block at the top left of each plane (rows of `pitch`) is skipped (sk1 = 0: none)
 template <typename T>
 hipError_t launch_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, const T *z, T *wbar, T tau, T b,
-                                   int first, int64_t n, DevIter di, hipStream_t s);
+                                   int first, int64_t n, DevIter di, int sk1, int sk2, int pitch, int64_t plane,
+                                   hipStream_t s);
 template <typename T> hipError_t launch_add(const T *x, T *y, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C, int levels, hipStream_t s);

@@ -1334,6 +1334,9 @@ struct CLayout {
     }
 };
 
+template <typename T>
+__device__ __forceinline__ T beta_at(int i);  // (below, with the reverse kernels)
+
 // NCH: channels handled by the workgroup (the joint colour prox couples them);
 // JOINT: the prox is the joint (group) one -- a compile-time choice, so the
 // scalar kernel carries no code of the other.  SM, SKW, STM, SNL, SOPS: when
@@ -1361,8 +1364,9 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
     const int cnt = m1 * m2;  // <= CPT * NTC
     const int tid = threadIdx.x;
     const bool ana = (ops & COARSE_ANA) != 0, prox = (ops & COARSE_PROX) != 0;
-    const bool need_z = !ana || prox;
-    const bool routed = NCH == 1 && !JOINT && ana && prox && (ops & COARSE_SYN) && kw > 0;
+    const bool revcm = NCH == 1 && !JOINT && (ops & COARSE_REVCM) != 0;
+    const bool need_z = !ana || prox || revcm;
+    const bool routed = NCH == 1 && !JOINT && ana && (prox || revcm) && (ops & COARSE_SYN) && kw > 0;
     auto home = [&](int cc) { return lds + L.a + cc * m2 * G::PA; };
 
     // 1. every global load at once (clamped indices, no data-dependent branch):
@@ -1436,7 +1440,65 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
 #pragma unroll
         for (int cc = 0; cc < NCH; ++cc)
             coarse_analysis<T>(home(cc), B, Cb, m1, m2, nlev, a.f, kw, tM1, tM2, Mat, in_c);
-        if (!prox) {  // plain forward transform
+        if constexpr (NCH == 1 && !JOINT) {
+            if (revcm) {
+                // reverse sweep: combine of iteration i, mask of iteration i-1
+                // (the element-wise kernels' formulas), the new vbar routed to
+                // the synthesis like y(i+1) in the prox branch
+                T b = a.rv_b;
+                int first = a.rv_first;
+                if (a.rv_di.it_dev) {
+                    const int i = *a.rv_di.it_dev + a.rv_di.it_off;
+                    b = beta_at<T>(i);
+                    first = i == 1;
+                }
+                T zbm[CPT], wb[CPT];
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    const int64_t gidx = (int64_t)ch0 * p.plane + gi[k];
+                    zbm[k] = a.rv_zbarm[gidx];
+                    wb[k] = (a.rv_wbar ? a.rv_wbar : a.rv_zbarm)[gidx];
+                }
+                T *A = home(0);
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (tid + k * NTC >= cnt) continue;
+                    const int r = rr[k], c = cr[k];
+                    const int li = r * G::PA + c;
+                    const int64_t gidx = (int64_t)ch0 * p.plane + gi[k];
+                    const T yb = fma(-p.tau, A[li], zcr[0][k]);
+                    T zb;
+                    if (first) {
+                        zb = yb + zbm[k];
+                    } else {
+                        zb = fma(T(1) + b, yb, zbm[k]);
+                        a.rv_zbarm[gidx] = -b * yb;
+                    }
+                    a.rv_zbar[gidx] = zb;
+                    const T zv = zpr[0][k];
+                    const bool act = zv != T(0);
+                    const T vn = act ? zb : T(0);
+                    a.rv_vbar[gidx] = vn;
+                    if (a.rv_wbar && act) {
+                        const T t = p.tau * zb;
+                        a.rv_wbar[gidx] = wb[k] - (zv > T(0) ? t : -t);
+                    }
+                    if (!routed || (kw < nlev && r < tM2 && c < tM1)) {
+                        A[li] = vn;
+                    } else {
+                        int lev = kw - 1;
+                        for (int j = 0; j < kw - 1; ++j)
+                            if (r >= (m2 >> (j + 1)) || c >= (m1 >> (j + 1))) {
+                                lev = j;
+                                break;
+                            }
+                        put_d<T>(B + drow_base<T>(m2, lev) * G::PB, m2 >> lev, r, c, vn);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (!prox && !revcm) {  // plain forward transform
 #pragma unroll
             for (int cc = 0; cc < NCH; ++cc)
 #pragma unroll
@@ -1448,6 +1510,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         // 2. gradient step + prox + momentum on the coarse block; with one
         //    channel and a synthesis to follow, y(i+1) is routed to where the
         //    synthesis reads it
+        if (prox) {
         double st[2] = {0.0, 0.0};
         bool bad = false;
 #pragma unroll
@@ -1512,6 +1575,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs<T> &a, const Live<T
         if (bad) atomicOr(p.flag, 1);
         if (lv.slots) block_slot_add<2, NTC>(st, lv.slots + PD_NSLOT);  // contains a barrier
         else __syncthreads();
+        }
     }
     if (!(ops & COARSE_SYN)) return;
     // 3. synthesis of the block back to the level lc-1 approximation
@@ -1891,7 +1955,10 @@ __global__ void k_rev_mask(const T *zbar, const T *z, T *vbar, T *wbar, T tau, i
         const T zv = z[e], zb = zbar[e];
         const bool act = zv != T(0);
         vbar[e] = act ? zb : T(0);
-        if (wbar && act) wbar[e] -= tau * zb * (zv > T(0) ? T(1) : T(-1));
+        if (wbar && act) {
+            const T t = tau * zb;
+            wbar[e] = wbar[e] - (zv > T(0) ? t : -t);
+        }
     }
 }
 
@@ -1928,10 +1995,12 @@ __global__ void k_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T
 
 // k_rev_combine of iteration i followed, element by element, by k_rev_mask of
 // iteration i-1 (z = z(i-1)): the same operations in the same order as the
-// two launches, so the same bits.
+// two launches, so the same bits.  Elements of the sk2 x sk1 block at the top
+// left of each plane (rows of `pitch` values) are skipped (the coarse kernel
+// treats them); sk1 = 0: none.
 template <typename T>
 __global__ void k_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, const T *z, T *wbar, T tau, T b,
-                                   int first, int64_t n, DevIter di)
+                                   int first, int64_t n, DevIter di, int sk1, int sk2, int pitch, int64_t plane)
 {
     if (di.it_dev) {
         const int i = *di.it_dev + di.it_off;
@@ -1939,6 +2008,10 @@ __global__ void k_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, co
         first = i == 1;
     }
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        if (sk1 > 0) {
+            const int64_t q = e % plane;
+            if (q / pitch < sk2 && q % pitch < sk1) continue;
+        }
         const T yb = fma(-tau, gbar[e], vbar[e]);
         T zb;
         if (first) {
@@ -1951,7 +2024,10 @@ __global__ void k_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, co
         const T zv = z[e];
         const bool act = zv != T(0);
         vbar[e] = act ? zb : T(0);
-        if (wbar && act) wbar[e] -= tau * zb * (zv > T(0) ? T(1) : T(-1));
+        if (wbar && act) {
+            const T t = tau * zb;
+            wbar[e] = wbar[e] - (zv > T(0) ? t : -t);
+        }
     }
 }
 
@@ -3000,10 +3076,11 @@ hipError_t launch_rev_combine(const T *vbar, const T *gbar, T *zbar, T *zbarm, T
 }
 template <typename T>
 hipError_t launch_rev_combine_mask(T *vbar, const T *gbar, T *zbar, T *zbarm, const T *z, T *wbar, T tau, T b,
-                                   int first, int64_t n, DevIter di, hipStream_t s)
+                                   int first, int64_t n, DevIter di, int sk1, int sk2, int pitch, int64_t plane,
+                                   hipStream_t s)
 {
     hipLaunchKernelGGL(k_rev_combine_mask<T>, dim3(ew_blocks(n)), dim3(256), 0, s, vbar, gbar, zbar, zbarm, z, wbar,
-                       tau, b, first, n, di);
+                       tau, b, first, n, di, sk1, sk2, pitch, plane);
     return hipGetLastError();
 }
 template <typename T>
@@ -3024,7 +3101,7 @@ hipError_t launch_expand_weights(T *w, const T *wlev_dev, int n1, int n2, int C,
     template hipError_t launch_rev_combine<T>(const T *, const T *, T *, T *, T, T, int, int64_t, DevIter, \
                                               hipStream_t);                                             \
     template hipError_t launch_rev_combine_mask<T>(T *, const T *, T *, T *, const T *, T *, T, T, int, int64_t, \
-                                                   DevIter, hipStream_t);                                        \
+                                                   DevIter, int, int, int, int64_t, hipStream_t);                \
     template hipError_t launch_add<T>(const T *, T *, int64_t, hipStream_t);                            \
     template hipError_t launch_expand_weights<T>(T *, const T *, int, int, int, int, hipStream_t);
 PD_INST_REV(float)
